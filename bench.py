@@ -1,0 +1,220 @@
+#!/usr/bin/env python3
+"""Oblique-QR benchmark on one MI355X: mixed-precision vs FP64 CholQR2-A.
+
+Default workload: dense SPD A, m = 32768, n = 256, kappa(A) = 1e8 (log-spaced
+eigenvalues, dense random orthogonal eigenvectors), Z = U diag(s) W^T with
+kappa(Z) = 1e5 (Haar factors).  One step = one CholQR2-A factorisation of Z:
+pass 1 with A Z on split-bfloat16 MFMA (three slices, FP32 accumulation
+inside 256-row tiles, FP64 across them), FP64 Gram/Cholesky/substitution;
+pass 2 all FP64.  The same step in all-FP64 is timed beside it.
+
+Throughput uses the paper's normalised flop count 2 m^2 n + 2 m n^2 for one
+factorisation (Section 8), whatever the algorithm executes.  Inputs are
+resident in HBM before the timed region; the timed region is K back-to-back
+steps bracketed by device synchronisation.  The roofline entry is the
+dominant kernel (the FP64 A-times-Q1 product of pass 2), its average launch
+time taken from HIP events recorded around each launch inside the timed
+region.  The CPU baseline times the CPU oracle (CHOL-EQR, Algorithm 3) on the
+leading m' x m' sub-problem.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload dense32768|dense8192|stencil]
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "oblique-QR GFLOP/s & % roofline, mixed vs FP64 CholQR2-A at orth loss ≤1e-12"
+PEAK = {"fp64": 78.6e12, "bf16": 2.5e15, "hbm": 8.0e12}
+TRAFFIC_NOTE = None   # filled from rocprofv3 counter runs (profiles/); null until measured for this kernel
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def parse():
+    p = argparse.ArgumentParser()
+    p.add_argument("--gpus", type=int, default=1)
+    p.add_argument("--steps", type=int, default=10)
+    p.add_argument("--warmup", type=int, default=3)
+    p.add_argument("--workload", default="dense32768", choices=["dense32768", "dense8192", "stencil"])
+    p.add_argument("--pass1", default=None, help="precision of pass 1 of the mixed schedule")
+    p.add_argument("--cpu-sample", type=int, default=8192, help="m' of the CPU oracle sample (0 = skip)")
+    return p.parse_args()
+
+
+def make_inputs(wl, torch):
+    import numpy as np
+    import workloads as W
+    import paper_1401_5171_amd as oqr
+    dev = torch.device("cuda", 0)
+    if wl in ("dense32768", "dense8192"):
+        m = 32768 if wl == "dense32768" else 8192
+        cfg = 4 if m == 32768 else 2
+        n, ka, kz = (256, 1e8, 1e5) if m == 32768 else (64, 1e6, 1e4)
+        rng = W.rng_for(cfg, 0)
+        t = time.time()
+        A, _, _ = W.dense_spd_device(rng, m, ka, dev)
+        z = W.tall_skinny(rng, m, n, kz)
+        log(f"generated A ({m}x{m}) on the device and Z in {time.time() - t:.1f}s")
+        Z = torch.from_numpy(np.ascontiguousarray(z.T)).to(dev).t()
+        desc = dict(workload=f"dense SPD A m={m} n={n} kappa(A)={ka:g} kappa(Z)={kz:g}", m=m, n=n,
+                    kappa_a=ka, kappa_z=kz, operator="dense", eigenvectors="butterfly-Haar",
+                    seeds=f"SeedSequence([15171, {cfg}, 0])")
+        flops = 2.0 * m * m * n + 2.0 * m * n * n
+        return A, Z, z, m, n, desc, flops, "gemm_f64", 2.0 * m * m * n
+    nx, ny, nz, n = 128, 128, 64, 128
+    st = W.laplacian7(nx, ny, nz)
+    rng = W.rng_for(3, 0)
+    z = W.gaussian_scaled(rng, st.m, n, 1e4)
+    Z = torch.from_numpy(np.ascontiguousarray(z.T)).to(dev).t()
+    A = oqr.Stencil7(nx, ny, nz, st.center, st.off)
+    m = st.m
+    desc = dict(workload=f"7-point Laplacian+1e-3 I on {nx}x{ny}x{nz} (m={m}) n={n} kappa(Z)=1e4 column-scaled",
+                m=m, n=n, operator="stencil7")
+    return A, Z, z, m, n, desc, 2.0 * m * n * n, "gram", 1.0 * m * n * n
+
+
+def time_steps(plan, Z, Q, R, steps, torch, kernel):
+    import paper_1401_5171_amd as oqr
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    with oqr.KernelTimer(kernel) as kt:
+        for _ in range(steps):
+            plan.run(Z, Q, R)
+        torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    if int(plan.info.item()) != 0:
+        raise RuntimeError(f"numerical failure in the timed region: info={int(plan.info.item())}")
+    return (t1 - t0) / steps, kt.avg_ms, kt.count
+
+
+def breakdown(plan, Z, Q, R, torch):
+    import paper_1401_5171_amd as oqr
+    out = {}
+    for k in ("split_z", "gemm_split", "gemm_f64", "stencil", "gram", "chol", "trsm"):
+        with oqr.KernelTimer(k) as kt:
+            plan.run(Z, Q, R)
+            torch.cuda.synchronize()
+        if kt.count:
+            out[k] = round(kt.total_ms, 4)
+    return out
+
+
+def cpu_baseline(A, z, n, ms, torch):
+    """CPU oracle (CHOL-EQR) on the leading ms x ms block of A and the first ms rows of Z."""
+    import numpy as np
+    from threadpoolctl import threadpool_info
+    from oracle import reference
+    if hasattr(A, "nx"):
+        from oracle import stencil as ost
+        import workloads as W
+        nz_s = max(1, ms // (A.nx * A.ny))
+        st = W.Stencil7(A.nx, A.ny, nz_s, A.center, A.off)
+        zs = np.asfortranarray(z[: st.m])
+        t = time.perf_counter()
+        reference.stencil_eqr(st, zs)
+        dt = time.perf_counter() - t
+        f = 2.0 * st.m * n * n
+        sample = f"stencil_eqr (DST route) on a {A.nx}x{A.ny}x{nz_s} grid (m'={st.m}), n={n}"
+    else:
+        a = A[:ms, :ms].cpu().numpy()
+        zs = np.asfortranarray(z[:ms])
+        t = time.perf_counter()
+        reference.chol_eqr(a, zs)
+        dt = time.perf_counter() - t
+        f = 2.0 * ms * ms * n + 2.0 * ms * n * n
+        sample = f"chol_eqr on the leading {ms}x{ms} block of A and first {ms} rows of Z, n={n}"
+    threads = max([i.get("num_threads", 1) for i in threadpool_info()] + [1])
+    return {"value": round(f / dt / 1e9, 3), "unit": "GFLOP/s", "cores": int(threads), "kind": "oracle",
+            "sample": sample, "seconds": round(dt, 3)}
+
+
+def main():
+    args = parse()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(how it would shard is described in DESIGN.md)", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    import paper_1401_5171_amd as oqr
+    if not torch.cuda.is_available():
+        print("bench.py needs a HIP device", file=sys.stderr)
+        sys.exit(2)
+    oqr.lib()   # fail loudly if the library is missing
+    torch.cuda.set_device(0)
+    A, Z, z_host, m, n, desc, flops, dom_kernel, dom_flops = make_inputs(args.workload, torch)
+    dense = not hasattr(A, "nx")
+    pass1 = args.pass1 or ("bf16x3")
+    Q = torch.empty(n, m, dtype=torch.float64, device="cuda").t()
+    R = torch.empty(n, n, dtype=torch.float64, device="cuda").t()
+    mixed = oqr.Plan("cholqr2", A, n, pass1=pass1, pass2="fp64")
+    fp64 = oqr.Plan("cholqr2", A, n, pass1="fp64", pass2="fp64")
+    fp64_1 = oqr.Plan("cholqr", A, n, pass1="fp64")
+
+    for _ in range(args.warmup):
+        mixed.run(Z, Q, R)
+        fp64.run(Z, Q, R)
+    torch.cuda.synchronize()
+    log(f"warmup done ({args.warmup} steps of each schedule)")
+
+    res = {}
+    for name, plan in (("mixed", mixed), ("fp64", fp64)):
+        t, kavg, kcnt = time_steps(plan, Z, Q, R, args.steps, torch, dom_kernel)
+        orth_f, resid = oqr.check(A, Z, Q, R)
+        res[name] = dict(ms_per_step=t * 1e3, kernel_avg_ms=kavg, kernel_launches=kcnt, orth_fro=orth_f,
+                         residual_fro=resid, gflops=flops / t / 1e9, breakdown_ms=breakdown(plan, Z, Q, R, torch))
+        log(f"{name}: {t * 1e3:.3f} ms/step, {flops / t / 1e9:.1f} GFLOP/s, orth_F={orth_f:.2e} res={resid:.2e}")
+    # single FP64 pass (the paper's CHOLQR) for context
+    t1, _, _ = time_steps(fp64_1, Z, Q, R, args.steps, torch, dom_kernel)
+    orth1, _ = oqr.check(A, Z, Q, R)
+
+    mx = res["mixed"]
+    kernel_ms = mx["kernel_avg_ms"] if mx["kernel_launches"] else res["fp64"]["kernel_avg_ms"]
+    achieved = dom_flops / (kernel_ms * 1e-3)
+    peak = PEAK["fp64"]
+    roof = {"bound": "mfma", "kernel": dom_kernel + (" (FP64, pass 2)" if dense else " (stencil Gram)"),
+            "achieved": round(achieved / 1e12, 3), "peak": round(peak / 1e12, 1), "unit": "TFLOP/s",
+            "frac": round(achieved / peak, 4), "traffic": TRAFFIC_NOTE,
+            "per_launch_flops": dom_flops, "avg_launch_ms": round(kernel_ms, 4)}
+    line = {
+        "metric": METRIC,
+        "value": round(mx["gflops"], 2),
+        "unit": "GFLOP/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(mx["ms_per_step"], 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": f"{pass1}+f64",
+        "data": "synthetic",
+        "config": dict(desc, schedule=f"CholQR2-A pass1={pass1} pass2=fp64", flops_per_step=flops,
+                       flop_count="2m^2n+2mn^2 (paper normalisation)" if dense else "2mn^2"),
+        "orth_loss_fro": mx["orth_fro"],
+        "residual_fro": mx["residual_fro"],
+        "fp64_cholqr2": {"value": round(res["fp64"]["gflops"], 2), "ms_per_step": round(res["fp64"]["ms_per_step"], 4),
+                         "orth_loss_fro": res["fp64"]["orth_fro"]},
+        "fp64_cholqr_single_pass": {"value": round(flops / t1 / 1e9, 2), "ms_per_step": round(t1 * 1e3, 4),
+                                    "orth_loss_fro": orth1},
+        "speedup_vs_fp64_cholqr2": round(res["fp64"]["ms_per_step"] / mx["ms_per_step"], 3),
+        "breakdown_ms": {"mixed": mx["breakdown_ms"], "fp64": res["fp64"]["breakdown_ms"]},
+        "roofline": roof,
+    }
+    if args.cpu_sample:
+        log("timing the CPU oracle sample")
+        line["cpu_baseline"] = cpu_baseline(A, z_host, n, min(args.cpu_sample, m), torch)
+    else:
+        line["cpu_baseline"] = None
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

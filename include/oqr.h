@@ -1,0 +1,230 @@
+/*
+ * oqr.h -- oblique QR factorisation on one MI355X (gfx950), plain C ABI.
+ *
+ * Given a symmetric positive definite m x m operator A and a full-rank m x n
+ * matrix Z (m >= n), compute Z = Q R with R (n x n) upper triangular with a
+ * positive diagonal and Q^T A Q = I (Lowery & Langou, "Stability Analysis of
+ * QR factorization in an Oblique Inner Product", Section 1).  The pair is
+ * unique: R is the Cholesky factor of the normal-equation matrix Z^T A Z.
+ *
+ * Conventions shared by every entry point
+ *   - Matrices are column-major with a leading dimension: element (i, j) of
+ *     X is X[i + j * ldx].  A torch caller passes an (n, m) row-major tensor,
+ *     which is the same memory.
+ *   - Pointers named *_dev, and the matrix pointers A->a, Z, Q, R, are device
+ *     pointers owned by the caller.  Descriptor structs (oqr_op, oqr_opts) are
+ *     host memory read during the call only.
+ *   - The library allocates nothing inside a call.  Scratch memory is the
+ *     caller's workspace `ws` of at least oqr_workspace_bytes(...) bytes
+ *     (256-byte aligned); its contents on entry are irrelevant.
+ *   - Work is enqueued on `stream` (a hipStream_t; NULL = the null stream)
+ *     and the call returns without synchronising.
+ *   - The return value reports host-detectable errors only (oqr_status).
+ *     Numerical failure is reported on the device in *info_dev, following
+ *     LAPACK potrf: 0 = success; k > 0 = the k-th pivot of the n x n
+ *     Cholesky factorisation was not positive (or NaN) after all shifted
+ *     retries.  On info_dev != 0 the contents of Q are unspecified.
+ *   - Q may alias Z (same pointer and ld): the triangular solve is done in
+ *     place.  No other aliasing is allowed (A, R, ws, info distinct).
+ *   - R is written in full: strictly lower triangle set to 0.
+ *   - Only the upper triangle of dense A need be symmetric-consistent: the
+ *     kernels read the whole of A and assume A = A^T.
+ */
+#ifndef OQR_H
+#define OQR_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Return codes (host-detectable errors). */
+typedef enum {
+  OQR_OK = 0,
+  OQR_E_ARG = 1,          /* bad size, leading dimension, null pointer or option */
+  OQR_E_NOT_SPD = 2,      /* reserved: numerical failure is reported in info_dev */
+  OQR_E_HIP = 3,          /* a HIP launch or runtime call failed */
+  OQR_E_WORKSPACE = 4,    /* workspace too small or misaligned */
+  OQR_E_UNSUPPORTED = 5   /* valid request this build does not implement (e.g. n too large) */
+} oqr_status;
+
+/* Storage type of A, Z, Q and R. */
+typedef enum { OQR_F64 = 0, OQR_F32 = 1 } oqr_dtype;
+
+/* Kind of operator A. */
+typedef enum {
+  OQR_OP_DENSE = 0,       /* explicit m x m symmetric matrix */
+  OQR_OP_STENCIL7 = 1     /* matrix-free 7-point operator on an nx x ny x nz grid */
+} oqr_op_kind;
+
+/* The operator A.
+ *   dense:   a = device pointer to A (column-major, full symmetric storage),
+ *            lda >= m.  Single-instance entry points take dtype = OQR_F64.
+ *   stencil: m = nx*ny*nz, grid index p = x + nx*(y + ny*z);
+ *            (A z)_p = center*z_p + off*(sum of z_q over the face neighbours
+ *            q of p inside the grid) -- homogeneous Dirichlet boundary.  The
+ *            Dirichlet 3D Laplacian (h = 1) plus s*I is center = 6 + s,
+ *            off = -1.  a and lda are ignored. */
+typedef struct oqr_op {
+  int32_t kind;
+  int32_t dtype;
+  const void* a;
+  int64_t lda;
+  int32_t nx, ny, nz;
+  int32_t reserved;
+  double center;
+  double off;
+} oqr_op;
+
+/* Arithmetic of the operator product A*Z (dense A) or of the Gram product
+ * Z^T W (stencil A) within one CholQR pass.  Gram accumulation across tiles,
+ * the Cholesky factorisation and the triangular solve are FP64 always.
+ *   FP64    : FP64 throughout.
+ *   BF16X2  : operands split into two bfloat16 slices (hi = bf16(x),
+ *             lo = bf16(x - hi)), products hi*hi + hi*lo + lo*hi on MFMA,
+ *             FP32 accumulation inside a tile of K, FP64 across tiles.
+ *   BF16X3  : three slices, the six products with slice indices i + j < 3.
+ *   FP32    : reserved (OQR_E_UNSUPPORTED in this build for single instances). */
+typedef enum { OQR_P_FP64 = 0, OQR_P_FP32 = 1, OQR_P_BF16X2 = 2, OQR_P_BF16X3 = 3 } oqr_prec;
+
+/* Gram-Schmidt variants for oqr_gs (Section 6 and the comments of Section 8). */
+typedef enum {
+  OQR_GS_CGS = 0,         /* classical Gram-Schmidt */
+  OQR_GS_MGS_ROW = 1,     /* modified, R computed a row at a time (A applied once per column) */
+  OQR_GS_MGS_COL = 2,     /* modified, R computed a column at a time (A inside the inner loop) */
+  OQR_GS_CGS2 = 3         /* classical with one reorthogonalisation */
+} oqr_gs_variant;
+
+/* Options.  NULL means the defaults of oqr_default_opts().
+ *   pass1, pass2  oqr_prec of the first and second CholQR pass (CholQR uses pass1 only).
+ *   shift_c       first-attempt shift s = shift_c * u_p * max_i G_ii added to the
+ *                 diagonal of G before the Cholesky factorisation, with u_p = 2^-24
+ *                 for reduced-precision passes; FP64 passes start unshifted.  On a
+ *                 failed pivot the factorisation is redone from the kept G with the
+ *                 constant multiplied by 10 (an unshifted FP64 pass retries with
+ *                 shift_c * 2^-53), at most max_retries times.
+ *   max_retries   number of shifted retries (0..16).
+ *   gs_variant    oqr_gs_variant, used by oqr_gs only. */
+typedef struct oqr_opts {
+  int32_t pass1;
+  int32_t pass2;
+  double shift_c;
+  int32_t max_retries;
+  int32_t gs_variant;
+} oqr_opts;
+
+/* Algorithms, for the workspace query. */
+typedef enum {
+  OQR_ALG_CHOLQR = 0, OQR_ALG_CHOLQR2 = 1, OQR_ALG_CHOL_A = 2, OQR_ALG_EIG_A = 3, OQR_ALG_GS = 4
+} oqr_alg;
+
+/* Largest n the single-instance kernels support. */
+#define OQR_MAX_N 256
+
+/* Fills *opts with the defaults: pass1 = pass2 = FP64, shift_c = 1, max_retries = 3, CGS. */
+void oqr_default_opts(oqr_opts* opts);
+
+/* Workspace bytes needed by algorithm `alg` for this operator and size
+ * (0 on invalid arguments). */
+size_t oqr_workspace_bytes(int32_t alg, const oqr_op* A, int64_t m, int64_t n, const oqr_opts* opts);
+
+/* CHOLQR-A (Algorithm 1, Section 2): W = A Z, G = Z^T W, R = chol(G [+ shift]),
+ * Q = Z R^{-1} by row-wise substitution (FP64).  Precision of A Z / Z^T W is
+ * opts->pass1.  Arguments as described at the top of this file. */
+int oqr_cholqr(const oqr_op* A, const double* Z, int64_t ldz, int64_t m, int64_t n,
+               double* Q, int64_t ldq, double* R, int64_t ldr, const oqr_opts* opts,
+               void* ws, size_t ws_bytes, int32_t* info_dev, void* stream);
+
+/* CholQR2-A: CHOLQR-A twice, (Q1, R1) = CHOLQR(A, Z) in precision pass1,
+ * (Q, R2) = CHOLQR(A, Q1) in precision pass2, R = R2 R1.  The repetition is
+ * the device PRE-CHOLQR (Algorithm 2, Section 3) uses to remove the kappa(Z)
+ * dependence of the loss of orthogonality; the analysis of Theorem 2.1 with
+ * Z = Q1 gives loss c m n u ||A|| ||Q||^2.  info_dev reports the first pass
+ * that failed (its pivot index). */
+int oqr_cholqr2(const oqr_op* A, const double* Z, int64_t ldz, int64_t m, int64_t n,
+                double* Q, int64_t ldq, double* R, int64_t ldr, const oqr_opts* opts,
+                void* ws, size_t ws_bytes, int32_t* info_dev, void* stream);
+
+/* CHOL-EQR (Algorithm 3, Section 4), dense A only: C = chol(A) upper
+ * (A = C^T C), W = C Z, Householder [Y, R] = qr(W) with positive diag(R),
+ * Q = C^{-1} Y.  info_dev = k if the k-th pivot of chol(A) failed
+ * (no shift is applied to A).  FP64 throughout. */
+int oqr_chol_a(const oqr_op* A, const double* Z, int64_t ldz, int64_t m, int64_t n,
+               double* Q, int64_t ldq, double* R, int64_t ldr, const oqr_opts* opts,
+               void* ws, size_t ws_bytes, int32_t* info_dev, void* stream);
+
+/* EQR-SYEV (Algorithm 4, Section 5), dense A only: A = V D V^T (cyclic
+ * Jacobi), X = V^T Z, W = D^{1/2} X, [Y, R] = qr(W), U = D^{-1/2} Y, Q = V U.
+ * info_dev = 1 if an eigenvalue is not positive, 2 if Jacobi did not
+ * converge.  FP64 throughout. */
+int oqr_eig_a(const oqr_op* A, const double* Z, int64_t ldz, int64_t m, int64_t n,
+              double* Q, int64_t ldq, double* R, int64_t ldr, const oqr_opts* opts,
+              void* ws, size_t ws_bytes, int32_t* info_dev, void* stream);
+
+/* Gram-Schmidt in the A inner product (Section 6), variant opts->gs_variant.
+ * info_dev = j if ||v_j||_A^2 was not positive at column j (1-based).  FP64. */
+int oqr_gs(const oqr_op* A, const double* Z, int64_t ldz, int64_t m, int64_t n,
+           double* Q, int64_t ldq, double* R, int64_t ldr, const oqr_opts* opts,
+           void* ws, size_t ws_bytes, int32_t* info_dev, void* stream);
+
+/* Error measures of Section 7, computed on the device in FP64 (a report, not
+ * a reference): out_dev[0] = ||I - Q^T A Q||_F (upper bound of the 2-norm
+ * and within sqrt(n) of it), out_dev[1] = ||Z - Q R||_F / ||Z||_F. */
+int oqr_check(const oqr_op* A, const double* Z, int64_t ldz, int64_t m, int64_t n,
+              const double* Q, int64_t ldq, const double* R, int64_t ldr,
+              void* ws, size_t ws_bytes, double* out_dev, void* stream);
+
+/* One item of a batch (device memory).  a: dense A_i (column-major, lda);
+ * z, q, r: Z_i, Q_i, R_i with their leading dimensions.  Storage type is the
+ * batch's dtype.  q may alias z. */
+typedef struct oqr_batch_item {
+  const void* a;
+  const void* z;
+  void* q;
+  void* r;
+  int64_t lda, ldz, ldq, ldr;
+  int32_t m, n;
+} oqr_batch_item;
+
+/* Workspace bytes for oqr_cholqr2_batched. */
+size_t oqr_batched_workspace_bytes(int64_t batch, int32_t max_m, int32_t max_n, int32_t dtype);
+
+/* Batched CholQR2-A over `batch` independent dense instances in one
+ * persistent launch: workgroups take instances from a device work queue
+ * (largest first), each instance runs both passes inside one workgroup with
+ * FP64 Gram accumulation, Cholesky (shift/retry as in opts) and substitution.
+ * items_dev: device array of `batch` items; m_i >= n_i >= 1, n_i <= 64,
+ * m_i <= max_m.  dtype: OQR_F64 or OQR_F32 (FP32 storage and FP32 operator
+ * products, FP64 Gram/Cholesky/substitution).  info_dev: `batch` int32, one per
+ * instance.  The call allocates nothing and may be captured in a hipGraph.
+ * tile: 0 = use the built-in tile table, else a tile id from
+ * oqr_batched_tile_count() (autotuning). */
+int oqr_cholqr2_batched(int64_t batch, const oqr_batch_item* items_dev, int32_t dtype,
+                        int32_t max_m, int32_t max_n, const oqr_opts* opts, int32_t tile,
+                        void* ws, size_t ws_bytes, int32_t* info_dev, void* stream);
+
+/* Number of batched tile configurations (ids 1..count). */
+int oqr_batched_tile_count(void);
+
+/* Timing aid: from oqr_trace_start(name) until oqr_trace_stop, every launch
+ * of the named kernel ("gemm_f64", "gemm_split", "gram", "chol", "trsm",
+ * "stencil", "split_z") made by this process is bracketed by a pair of HIP
+ * events recorded on its stream (events are created on first use and reused).
+ * oqr_trace_stop waits for the recorded events and returns the summed kernel
+ * time in milliseconds and the number of launches.  Not thread-safe; do not
+ * trace while capturing a graph. */
+int oqr_trace_start(const char* kernel);
+int oqr_trace_stop(double* total_ms, int32_t* count);
+
+/* Human-readable text for a status code. */
+const char* oqr_status_string(int status);
+
+/* ABI version (major*10000 + minor*100 + patch). */
+int oqr_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* OQR_H */

@@ -81,7 +81,10 @@ def shift_for(g: np.ndarray, scheme: str, c: float) -> float:
 
 def cholqr_pass(a, z: np.ndarray, scheme: str, shift_c: float = 1.0, max_retries: int = 3, kt: int = 256):
     """One CHOLQR pass with a reduced-precision product, FP64 Cholesky with the
-    shift-and-retry rule (shift x10 per retry), FP64 substitution for Q.
+    shift-and-retry rule, FP64 substitution for Q.  A reduced-precision pass
+    starts with s = shift_c u_p max diag(G); an FP64 pass starts unshifted and
+    retries with shift_c u max diag(G); each further retry multiplies the
+    constant by 10.
 
     Returns (Q, R, info, shift_used)."""
     g = gram(a, z, scheme, kt)
@@ -92,7 +95,7 @@ def cholqr_pass(a, z: np.ndarray, scheme: str, shift_c: float = 1.0, max_retries
         r, info = chol_info(g + s * np.eye(g.shape[0]))
         if info == 0:
             return trsm_right_upper(z, r), r, 0, s
-        c = (c * 10.0) if c else 1.0
+        c = (c * 10.0) if c else shift_c
     return None, r, info, s
 
 

@@ -1,0 +1,289 @@
+"""Oblique QR factorisation Z = QR, Q^T A Q = I, on one MI355X.
+
+A thin ctypes binding over liboqr.so (C ABI in include/oqr.h).  Every step of
+every algorithm runs in the library's HIP kernels; this module only marshals
+arguments: it checks shapes, allocates outputs and the workspace with torch on
+the current device and stream, and raises OQRError on a non-zero status or
+device `info`.  There is no CPU fallback: importing works without a GPU, but
+every call needs the built library and a HIP device.
+
+Matrices are column-major: an (m, n) tensor with stride (1, ld), ld >= m, as
+produced by `colmajor(x)`.  The dense operator A is an (m, m) contiguous
+float64 tensor holding a symmetric matrix (its row- and column-major readings
+coincide).
+"""
+from __future__ import annotations
+
+import ctypes
+import dataclasses
+import os
+from typing import Optional, Tuple
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "liboqr.so")
+
+OQR_OK, OQR_E_ARG, OQR_E_NOT_SPD, OQR_E_HIP, OQR_E_WORKSPACE, OQR_E_UNSUPPORTED = range(6)
+OQR_F64, OQR_F32 = 0, 1
+OQR_OP_DENSE, OQR_OP_STENCIL7 = 0, 1
+PREC = {"fp64": 0, "fp32": 1, "bf16x2": 2, "bf16x3": 3}
+GS = {"cgs": 0, "mgs_row": 1, "mgs_col": 2, "cgs2": 3}
+ALG = {"cholqr": 0, "cholqr2": 1, "chol_a": 2, "eig_a": 3, "gs": 4}
+MAX_N = 256
+
+EXPORTS = (
+    "oqr_default_opts", "oqr_workspace_bytes", "oqr_cholqr", "oqr_cholqr2", "oqr_chol_a", "oqr_eig_a",
+    "oqr_gs", "oqr_check", "oqr_batched_workspace_bytes", "oqr_cholqr2_batched", "oqr_batched_tile_count",
+    "oqr_status_string", "oqr_version", "oqr_trace_start", "oqr_trace_stop",
+)
+
+
+class OQRError(RuntimeError):
+    def __init__(self, msg, status=None, info=None):
+        super().__init__(msg)
+        self.status = status
+        self.info = info
+
+
+class _Op(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int32), ("dtype", ctypes.c_int32), ("a", ctypes.c_void_p),
+                ("lda", ctypes.c_int64), ("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("nz", ctypes.c_int32),
+                ("reserved", ctypes.c_int32), ("center", ctypes.c_double), ("off", ctypes.c_double)]
+
+
+class _Opts(ctypes.Structure):
+    _fields_ = [("pass1", ctypes.c_int32), ("pass2", ctypes.c_int32), ("shift_c", ctypes.c_double),
+                ("max_retries", ctypes.c_int32), ("gs_variant", ctypes.c_int32)]
+
+
+class BatchItem(ctypes.Structure):
+    _fields_ = [("a", ctypes.c_void_p), ("z", ctypes.c_void_p), ("q", ctypes.c_void_p), ("r", ctypes.c_void_p),
+                ("lda", ctypes.c_int64), ("ldz", ctypes.c_int64), ("ldq", ctypes.c_int64), ("ldr", ctypes.c_int64),
+                ("m", ctypes.c_int32), ("n", ctypes.c_int32)]
+
+
+_lib = None
+
+
+def lib():
+    """The loaded liboqr.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise OQRError(f"{LIB_PATH} is missing: build it with `python -m paper_1401_5171_amd.build`")
+        L = ctypes.CDLL(LIB_PATH)
+        vp, i64, i32, sz = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32, ctypes.c_size_t
+        sig = [ctypes.POINTER(_Op), vp, i64, i64, i64, vp, i64, vp, i64, ctypes.POINTER(_Opts), vp, sz, vp, vp]
+        for name in ("oqr_cholqr", "oqr_cholqr2", "oqr_chol_a", "oqr_eig_a", "oqr_gs"):
+            f = getattr(L, name)
+            f.argtypes = sig
+            f.restype = ctypes.c_int
+        L.oqr_workspace_bytes.argtypes = [i32, ctypes.POINTER(_Op), i64, i64, ctypes.POINTER(_Opts)]
+        L.oqr_workspace_bytes.restype = sz
+        L.oqr_check.argtypes = [ctypes.POINTER(_Op), vp, i64, i64, i64, vp, i64, vp, i64, vp, sz, vp, vp]
+        L.oqr_check.restype = ctypes.c_int
+        L.oqr_batched_workspace_bytes.argtypes = [i64, i32, i32, i32]
+        L.oqr_batched_workspace_bytes.restype = sz
+        L.oqr_cholqr2_batched.argtypes = [i64, vp, i32, i32, i32, ctypes.POINTER(_Opts), i32, vp, sz, vp, vp]
+        L.oqr_cholqr2_batched.restype = ctypes.c_int
+        L.oqr_batched_tile_count.restype = ctypes.c_int
+        L.oqr_status_string.argtypes = [ctypes.c_int]
+        L.oqr_status_string.restype = ctypes.c_char_p
+        L.oqr_default_opts.argtypes = [ctypes.POINTER(_Opts)]
+        L.oqr_version.restype = ctypes.c_int
+        L.oqr_trace_start.argtypes = [ctypes.c_char_p]
+        L.oqr_trace_start.restype = ctypes.c_int
+        L.oqr_trace_stop.argtypes = [ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int32)]
+        L.oqr_trace_stop.restype = ctypes.c_int
+        _lib = L
+    return _lib
+
+
+def status_string(code: int) -> str:
+    return lib().oqr_status_string(int(code)).decode()
+
+
+def _raise(code, what):
+    if code != OQR_OK:
+        raise OQRError(f"{what}: {status_string(code)}", status=code)
+
+
+@dataclasses.dataclass(frozen=True)
+class Stencil7:
+    """Matrix-free 7-point operator (A z)_p = center z_p + off * sum of in-grid face neighbours,
+    p = x + nx (y + ny z)."""
+
+    nx: int
+    ny: int
+    nz: int
+    center: float
+    off: float
+
+    @property
+    def m(self):
+        return self.nx * self.ny * self.nz
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def colmajor(x):
+    """Column-major view (stride (1, m)) of a 2D tensor, copying only if needed."""
+    if x.dim() != 2:
+        raise ValueError("expected a 2D tensor")
+    if (x.stride(0) == 1 or x.shape[0] <= 1) and (x.shape[1] <= 1 or x.stride(1) >= max(1, x.shape[0])):
+        return x
+    return x.t().contiguous().t()
+
+
+def _ld(x):
+    """Leading dimension of a column-major tensor (size-1 dimensions carry arbitrary strides)."""
+    if x.shape[1] <= 1:
+        return max(1, x.shape[0])
+    return max(1, x.stride(1))
+
+
+def make_op(A) -> Tuple[_Op, int]:
+    """oqr_op for a dense symmetric float64 tensor or a Stencil7; returns (op, m)."""
+    op = _Op()
+    if isinstance(A, Stencil7) or hasattr(A, "nx"):
+        op.kind, op.dtype = OQR_OP_STENCIL7, OQR_F64
+        op.nx, op.ny, op.nz = int(A.nx), int(A.ny), int(A.nz)
+        op.center, op.off = float(A.center), float(A.off)
+        return op, op.nx * op.ny * op.nz
+    torch = _torch()
+    if A.dim() != 2 or A.shape[0] != A.shape[1]:
+        raise ValueError("A must be square")
+    if A.dtype != torch.float64 or not A.is_cuda or not A.is_contiguous():
+        raise ValueError("A must be a contiguous float64 CUDA tensor")
+    op.kind, op.dtype = OQR_OP_DENSE, OQR_F64
+    op.a, op.lda = A.data_ptr(), A.shape[0]
+    return op, A.shape[0]
+
+
+def make_opts(pass1="fp64", pass2="fp64", shift_c=1.0, max_retries=3, gs_variant="cgs") -> _Opts:
+    o = _Opts()
+    o.pass1, o.pass2 = PREC[pass1], PREC[pass2]
+    o.shift_c, o.max_retries = float(shift_c), int(max_retries)
+    o.gs_variant = GS[gs_variant]
+    return o
+
+
+class Plan:
+    """Pre-allocated call of one algorithm on a fixed operator and shape (no allocation per run)."""
+
+    def __init__(self, alg: str, A, n: int, **opts):
+        torch = _torch()
+        self.alg = alg
+        self.A = A                      # keep the operand alive
+        self.op, self.m = make_op(A)
+        self.n = int(n)
+        self.opts = make_opts(**opts)
+        self.device = A.device if hasattr(A, "device") else torch.device("cuda", torch.cuda.current_device())
+        L = lib()
+        nbytes = L.oqr_workspace_bytes(ALG[alg], ctypes.byref(self.op), self.m, self.n, ctypes.byref(self.opts))
+        if nbytes == 0 and self.n > 0:
+            raise OQRError(f"workspace query failed for {alg} (m={self.m}, n={self.n})")
+        self.ws = torch.empty(max(int(nbytes), 256), dtype=torch.uint8, device=self.device)
+        self.info = torch.zeros(1, dtype=torch.int32, device=self.device)
+        self.fn = getattr(L, "oqr_" + alg)
+
+    def run(self, Z, Q, R, stream=None):
+        """Enqueue the factorisation of column-major Z into Q (may be Z) and R; returns nothing."""
+        torch = _torch()
+        s = stream if stream is not None else torch.cuda.current_stream(self.device).cuda_stream
+        rc = self.fn(ctypes.byref(self.op), Z.data_ptr(), _ld(Z), self.m, self.n, Q.data_ptr(), _ld(Q),
+                     R.data_ptr(), _ld(R), ctypes.byref(self.opts), self.ws.data_ptr(), self.ws.numel(),
+                     self.info.data_ptr(), s)
+        _raise(rc, "oqr_" + self.alg)
+
+    def __call__(self, Z, check_info=True):
+        torch = _torch()
+        Z = colmajor(Z)
+        if Z.dtype != torch.float64 or not Z.is_cuda:
+            raise ValueError("Z must be a float64 CUDA tensor")
+        if Z.shape != (self.m, self.n):
+            raise ValueError(f"Z must be {self.m} x {self.n}")
+        Q = torch.empty(self.n, self.m, dtype=torch.float64, device=Z.device).t()
+        R = torch.empty(self.n, self.n, dtype=torch.float64, device=Z.device).t()
+        self.run(Z, Q, R)
+        info = int(self.info.item()) if check_info else None
+        if check_info and info != 0:
+            raise OQRError(f"oqr_{self.alg}: numerical failure, info = {info}", info=info)
+        return Q, R
+
+
+class KernelTimer:
+    """Context manager: summed HIP-event time of every launch of one library kernel."""
+
+    def __init__(self, kernel: str):
+        self.kernel = kernel
+        self.total_ms = 0.0
+        self.count = 0
+
+    def __enter__(self):
+        _raise(lib().oqr_trace_start(self.kernel.encode()), "oqr_trace_start")
+        return self
+
+    def __exit__(self, *exc):
+        t = ctypes.c_double()
+        c = ctypes.c_int32()
+        rc = lib().oqr_trace_stop(ctypes.byref(t), ctypes.byref(c))
+        if exc[0] is None:
+            _raise(rc, "oqr_trace_stop")
+        self.total_ms, self.count = t.value, c.value
+        return False
+
+    @property
+    def avg_ms(self):
+        return self.total_ms / self.count if self.count else float("nan")
+
+
+def _run(alg, A, Z, **opts):
+    Z = colmajor(Z)
+    return Plan(alg, A, Z.shape[1], **opts)(Z)
+
+
+def cholqr(A, Z, prec="fp64", shift_c=1.0, max_retries=3):
+    """CHOLQR-A (Algorithm 1): returns (Q, R)."""
+    return _run("cholqr", A, Z, pass1=prec, shift_c=shift_c, max_retries=max_retries)
+
+
+def cholqr2(A, Z, pass1="fp64", pass2="fp64", shift_c=1.0, max_retries=3):
+    """CholQR2-A (CHOLQR-A twice, R = R2 R1): returns (Q, R)."""
+    return _run("cholqr2", A, Z, pass1=pass1, pass2=pass2, shift_c=shift_c, max_retries=max_retries)
+
+
+def chol_a(A, Z):
+    """CHOL-EQR (Algorithm 3): returns (Q, R)."""
+    return _run("chol_a", A, Z)
+
+
+def eig_a(A, Z):
+    """EQR-SYEV (Algorithm 4): returns (Q, R)."""
+    return _run("eig_a", A, Z)
+
+
+def gs(A, Z, variant="cgs"):
+    """Gram-Schmidt in the A inner product (cgs, mgs_row, mgs_col, cgs2): returns (Q, R)."""
+    return _run("gs", A, Z, gs_variant=variant)
+
+
+def check(A, Z, Q, R):
+    """Device report: (||I - Q^T A Q||_F, ||Z - QR||_F / ||Z||_F)."""
+    torch = _torch()
+    op, m = make_op(A)
+    Z, Q, R = colmajor(Z), colmajor(Q), colmajor(R)
+    n = Z.shape[1]
+    L = lib()
+    # workspace: W (m x n) + Gram partials + G + per-block partial sums; generous upper bound
+    nbytes = L.oqr_workspace_bytes(ALG["cholqr"], ctypes.byref(op), m, n, None) + 4 * m * 8 + (1 << 20)
+    ws = torch.empty(nbytes, dtype=torch.uint8, device=Z.device)
+    out = torch.zeros(2, dtype=torch.float64, device=Z.device)
+    s = torch.cuda.current_stream(Z.device).cuda_stream
+    rc = L.oqr_check(ctypes.byref(op), Z.data_ptr(), _ld(Z), m, n, Q.data_ptr(), _ld(Q), R.data_ptr(), _ld(R),
+                     ws.data_ptr(), ws.numel(), out.data_ptr(), s)
+    _raise(rc, "oqr_check")
+    o = out.cpu()
+    return float(o[0]), float(o[1])

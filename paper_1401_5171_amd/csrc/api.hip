@@ -1,0 +1,380 @@
+// The C ABI of the library (declared in include/oqr.h): argument checks,
+// workspace carving and the kernel sequence of each algorithm.  Every step
+// runs on the caller's stream; nothing here allocates or synchronises.
+#include <math.h>
+#include <string.h>
+
+#include <vector>
+
+#include "common.hpp"
+
+namespace oqr {
+
+// ---- optional per-kernel timing (oqr_trace_start / oqr_trace_stop) ---------------------------
+namespace {
+struct TraceState {
+  int kernel = 0;                       // 0 = off
+  std::vector<hipEvent_t> begin, end;   // one pair per traced launch
+  size_t used = 0;
+  bool failed = false;
+};
+TraceState g_trace;
+
+const char* const kKernelNames[] = {"", "gemm_f64", "gemm_split", "gram", "chol", "trsm", "stencil", "split_z"};
+constexpr int kNumKernels = 8;
+}  // namespace
+
+void trace_pre(int kid, hipStream_t s) {
+  if (g_trace.kernel != kid || g_trace.failed) return;
+  if (g_trace.used == g_trace.begin.size()) {
+    hipEvent_t a, b;
+    if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess) {
+      g_trace.failed = true;
+      return;
+    }
+    g_trace.begin.push_back(a);
+    g_trace.end.push_back(b);
+  }
+  if (hipEventRecord(g_trace.begin[g_trace.used], s) != hipSuccess) g_trace.failed = true;
+}
+
+void trace_post(int kid, hipStream_t s) {
+  if (g_trace.kernel != kid || g_trace.failed) return;
+  if (hipEventRecord(g_trace.end[g_trace.used], s) != hipSuccess) g_trace.failed = true;
+  ++g_trace.used;
+}
+
+#define OQR_TRACED(kid, s, expr)            \
+  do {                                      \
+    trace_pre((kid), (s));                  \
+    hipError_t e_ = (expr);                 \
+    trace_post((kid), (s));                 \
+    if (e_ != hipSuccess) return OQR_E_HIP; \
+  } while (0)
+
+// Implemented in k_check.hip / k_baselines.hip / k_gs.hip / k_batch.hip.
+size_t check_workspace_bytes(const oqr_op* A, int64_t m, int64_t n);
+int check_run(const oqr_op* A, const double* Z, int64_t ldz, int64_t m, int64_t n, const double* Q, int64_t ldq,
+              const double* R, int64_t ldr, void* ws, size_t ws_bytes, double* out, hipStream_t s);
+size_t gs_workspace_bytes(const oqr_op* A, int64_t m, int64_t n);
+int gs_run(const oqr_op* A, const double* Z, int64_t ldz, int64_t m, int64_t n, double* Q, int64_t ldq, double* R,
+           int64_t ldr, int variant, void* ws, int32_t* info, hipStream_t s);
+size_t chol_a_workspace_bytes(int64_t m, int64_t n);
+int chol_a_run(const oqr_op* A, const double* Z, int64_t ldz, int64_t m, int64_t n, double* Q, int64_t ldq,
+               double* R, int64_t ldr, void* ws, int32_t* info, hipStream_t s);
+size_t eig_a_workspace_bytes(int64_t m, int64_t n);
+int eig_a_run(const oqr_op* A, const double* Z, int64_t ldz, int64_t m, int64_t n, double* Q, int64_t ldq,
+              double* R, int64_t ldr, void* ws, int32_t* info, hipStream_t s);
+
+namespace {
+
+constexpr double U64 = 1.1102230246251565e-16;   // 2^-53
+constexpr double U32 = 5.9604644775390625e-08;   // 2^-24
+
+#define OQR_TRY(expr)                       \
+  do {                                      \
+    hipError_t e_ = (expr);                 \
+    if (e_ != hipSuccess) return OQR_E_HIP; \
+  } while (0)
+
+oqr_opts defaults() {
+  oqr_opts o;
+  o.pass1 = OQR_P_FP64;
+  o.pass2 = OQR_P_FP64;
+  o.shift_c = 1.0;
+  o.max_retries = 3;
+  o.gs_variant = OQR_GS_CGS;
+  return o;
+}
+
+int64_t op_m(const oqr_op* A) { return (int64_t)A->nx * A->ny * A->nz; }
+
+int slices_of(int prec) { return prec == OQR_P_BF16X3 ? 3 : 2; }
+
+bool prec_ok(int p) { return p == OQR_P_FP64 || p == OQR_P_BF16X2 || p == OQR_P_BF16X3; }
+
+int check_op(const oqr_op* A, int64_t m) {
+  if (!A) return OQR_E_ARG;
+  if (A->kind == OQR_OP_DENSE) {
+    if (!A->a || A->lda < m || A->lda < 1) return OQR_E_ARG;
+    if (A->dtype != OQR_F64) return OQR_E_UNSUPPORTED;
+  } else if (A->kind == OQR_OP_STENCIL7) {
+    if (A->nx < 1 || A->ny < 1 || A->nz < 1 || op_m(A) != m) return OQR_E_ARG;
+  } else {
+    return OQR_E_ARG;
+  }
+  return OQR_OK;
+}
+
+int check_common(const oqr_op* A, const double* Z, int64_t ldz, int64_t m, int64_t n, const double* Q, int64_t ldq,
+                 const double* R, int64_t ldr, const int32_t* info) {
+  if (m < 0 || n < 0 || m < n) return OQR_E_ARG;
+  if (n > OQR_MAX_N) return OQR_E_UNSUPPORTED;
+  if (!info) return OQR_E_ARG;
+  if (n == 0) return OQR_OK;
+  if (!Z || !Q || !R) return OQR_E_ARG;
+  if (ldz < m || ldq < m || ldr < n || ldz < 1) return OQR_E_ARG;
+  int rc = check_op(A, m);
+  if (rc) return rc;
+  // Q may alias Z exactly; any other overlap is rejected.
+  if (Q != Z) {
+    const char* zb = (const char*)Z;
+    const char* ze = zb + ((n - 1) * ldz + m) * sizeof(double);
+    const char* qb = (const char*)Q;
+    const char* qe = qb + ((n - 1) * ldq + m) * sizeof(double);
+    if (qb < ze && zb < qe) return OQR_E_ARG;
+  } else if (ldq != ldz) {
+    return OQR_E_ARG;
+  }
+  return OQR_OK;
+}
+
+// Workspace of one CholQR pass sequence.
+struct Carve {
+  char* base;
+  size_t off;
+  template <class T>
+  T* take(size_t count) {
+    T* p = (T*)(base + off);
+    off = align256(off + count * sizeof(T));
+    return p;
+  }
+};
+
+struct PassWs {
+  double* W;          // m x n
+  double* partial;    // Gram partials
+  double* G;          // n x n
+  double* R1;         // n x n (first pass of CholQR2)
+  double* R2;         // n x n (second pass)
+  unsigned short* zs; // bf16 slices of Z (dense reduced precision)
+  double* shifts;     // [2] shift used per pass
+};
+
+size_t pass_ws(const oqr_op* A, int64_t m, int64_t n, const oqr_opts& o, bool two, PassWs* out, void* base) {
+  Carve c{(char*)base, 0};
+  PassWs w;
+  w.W = c.take<double>((size_t)m * n);
+  w.partial = c.take<double>(gram_partial_bytes(m, n) / sizeof(double));
+  w.G = c.take<double>((size_t)n * n);
+  w.R1 = c.take<double>((size_t)n * n);
+  w.R2 = c.take<double>((size_t)n * n);
+  int maxs = 0;
+  if (A->kind == OQR_OP_DENSE) {
+    if (o.pass1 != OQR_P_FP64) maxs = slices_of(o.pass1);
+    if (two && o.pass2 != OQR_P_FP64 && slices_of(o.pass2) > maxs) maxs = slices_of(o.pass2);
+  }
+  w.zs = c.take<unsigned short>((size_t)maxs * split_ld(m) * n);
+  w.shifts = c.take<double>(2);
+  if (out) *out = w;
+  return c.off;
+}
+
+// One CHOLQR pass (Algorithm 1) on the device: W = A Z; G = Z^T W; R = chol(G [+ s I]); Q = Z R^{-1}.
+int cholqr_pass(const oqr_op* A, const double* Z, int64_t ldz, int64_t m, int64_t n, double* Q, int64_t ldq,
+                double* R, int64_t ldr, int prec, const oqr_opts& o, const PassWs& w, double* shift_slot,
+                int32_t* info, hipStream_t s) {
+  if (A->kind == OQR_OP_DENSE) {
+    const double* a = (const double*)A->a;
+    if (prec == OQR_P_FP64) {
+      OQR_TRACED(K_GEMM_F64, s, launch_gemm_f64(a, A->lda, Z, ldz, w.W, m, m, n, s));
+    } else {
+      OQR_TRACED(K_SPLIT_Z, s, launch_split_z(Z, ldz, w.zs, m, n, slices_of(prec), s));
+      OQR_TRACED(K_GEMM_SPLIT, s, launch_gemm_split(a, A->lda, w.zs, w.W, m, m, n, slices_of(prec), s));
+    }
+    OQR_TRACED(K_GRAM, s, launch_gram_f64(Z, ldz, w.W, m, m, n, w.partial, w.G, s));
+  } else {
+    OQR_TRACED(K_STENCIL, s, launch_stencil_apply(A, Z, ldz, w.W, m, n, s));
+    if (prec == OQR_P_FP64)
+      OQR_TRACED(K_GRAM, s, launch_gram_f64(Z, ldz, w.W, m, m, n, w.partial, w.G, s));
+    else
+      OQR_TRACED(K_GRAM, s, launch_gram_split(Z, ldz, w.W, m, m, n, slices_of(prec), w.partial, w.G, s));
+  }
+  const bool red = prec != OQR_P_FP64;
+  OQR_TRACED(K_CHOL, s, launch_chol_small(w.G, n, R, ldr, red ? U32 : U64, red ? o.shift_c : 0.0,
+                                          red ? 10.0 * o.shift_c : o.shift_c, o.max_retries, info, shift_slot, s));
+  OQR_TRACED(K_TRSM, s, launch_trsm(Z, ldz, R, ldr, Q, ldq, m, n, info, s));
+  return OQR_OK;
+}
+
+int resolve_opts(const oqr_opts* in, oqr_opts* out) {
+  *out = in ? *in : defaults();
+  if (!prec_ok(out->pass1) || !prec_ok(out->pass2)) {
+    if (out->pass1 == OQR_P_FP32 || out->pass2 == OQR_P_FP32) return OQR_E_UNSUPPORTED;
+    return OQR_E_ARG;
+  }
+  if (!(out->shift_c >= 0.0) || !isfinite(out->shift_c)) return OQR_E_ARG;
+  if (out->max_retries < 0 || out->max_retries > 16) return OQR_E_ARG;
+  return OQR_OK;
+}
+
+int ws_check(void* ws, size_t ws_bytes, size_t need) {
+  if (need == 0) return OQR_OK;
+  if (!ws || ws_bytes < need || ((uintptr_t)ws & 255u)) return OQR_E_WORKSPACE;
+  return OQR_OK;
+}
+
+}  // namespace
+}  // namespace oqr
+
+using namespace oqr;
+
+extern "C" {
+
+void oqr_default_opts(oqr_opts* opts) {
+  if (opts) *opts = defaults();
+}
+
+int oqr_version(void) { return 100; }
+
+int oqr_trace_start(const char* kernel) {
+  if (!kernel) return OQR_E_ARG;
+  int kid = 0;
+  for (int k = 1; k < kNumKernels; ++k)
+    if (strcmp(kernel, kKernelNames[k]) == 0) kid = k;
+  if (!kid) return OQR_E_ARG;
+  g_trace.kernel = kid;
+  g_trace.used = 0;
+  g_trace.failed = false;
+  return OQR_OK;
+}
+
+int oqr_trace_stop(double* total_ms, int32_t* count) {
+  if (!total_ms || !count) return OQR_E_ARG;
+  const int kid = g_trace.kernel;
+  g_trace.kernel = 0;
+  *total_ms = 0.0;
+  *count = 0;
+  if (!kid) return OQR_E_ARG;
+  if (g_trace.failed) return OQR_E_HIP;
+  for (size_t i = 0; i < g_trace.used; ++i) {
+    if (hipEventSynchronize(g_trace.end[i]) != hipSuccess) return OQR_E_HIP;
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, g_trace.begin[i], g_trace.end[i]) != hipSuccess) return OQR_E_HIP;
+    *total_ms += ms;
+  }
+  *count = (int32_t)g_trace.used;
+  g_trace.used = 0;
+  return OQR_OK;
+}
+
+const char* oqr_status_string(int status) {
+  switch (status) {
+    case OQR_OK: return "OQR_OK: success";
+    case OQR_E_ARG: return "OQR_E_ARG: invalid argument (size, leading dimension, pointer or option)";
+    case OQR_E_NOT_SPD: return "OQR_E_NOT_SPD: operator is not symmetric positive definite";
+    case OQR_E_HIP: return "OQR_E_HIP: a HIP launch or runtime call failed";
+    case OQR_E_WORKSPACE: return "OQR_E_WORKSPACE: workspace too small or not 256-byte aligned";
+    case OQR_E_UNSUPPORTED: return "OQR_E_UNSUPPORTED: request not implemented by this build";
+    default: return "unknown oqr status";
+  }
+}
+
+size_t oqr_workspace_bytes(int32_t alg, const oqr_op* A, int64_t m, int64_t n, const oqr_opts* opts) {
+  oqr_opts o;
+  if (resolve_opts(opts, &o) != OQR_OK || !A || m < n || n < 0 || n > OQR_MAX_N) return 0;
+  if (n == 0) return 0;
+  if (check_op(A, m) != OQR_OK) return 0;
+  switch (alg) {
+    case OQR_ALG_CHOLQR: return pass_ws(A, m, n, o, false, nullptr, nullptr);
+    case OQR_ALG_CHOLQR2: return pass_ws(A, m, n, o, true, nullptr, nullptr);
+    case OQR_ALG_CHOL_A: return A->kind == OQR_OP_DENSE ? chol_a_workspace_bytes(m, n) : 0;
+    case OQR_ALG_EIG_A: return A->kind == OQR_OP_DENSE ? eig_a_workspace_bytes(m, n) : 0;
+    case OQR_ALG_GS: return gs_workspace_bytes(A, m, n);
+    default: return 0;
+  }
+}
+
+int oqr_cholqr(const oqr_op* A, const double* Z, int64_t ldz, int64_t m, int64_t n, double* Q, int64_t ldq,
+               double* R, int64_t ldr, const oqr_opts* opts, void* ws, size_t ws_bytes, int32_t* info_dev,
+               void* stream) {
+  int rc = check_common(A, Z, ldz, m, n, Q, ldq, R, ldr, info_dev);
+  if (rc) return rc;
+  oqr_opts o;
+  if ((rc = resolve_opts(opts, &o))) return rc;
+  hipStream_t s = (hipStream_t)stream;
+  if (launch_fill_i32(info_dev, 0, 1, s) != hipSuccess) return OQR_E_HIP;
+  if (n == 0) return OQR_OK;
+  PassWs w;
+  const size_t need = pass_ws(A, m, n, o, false, nullptr, nullptr);
+  if ((rc = ws_check(ws, ws_bytes, need))) return rc;
+  pass_ws(A, m, n, o, false, &w, ws);
+  return cholqr_pass(A, Z, ldz, m, n, Q, ldq, R, ldr, o.pass1, o, w, w.shifts, info_dev, s);
+}
+
+int oqr_cholqr2(const oqr_op* A, const double* Z, int64_t ldz, int64_t m, int64_t n, double* Q, int64_t ldq,
+                double* R, int64_t ldr, const oqr_opts* opts, void* ws, size_t ws_bytes, int32_t* info_dev,
+                void* stream) {
+  int rc = check_common(A, Z, ldz, m, n, Q, ldq, R, ldr, info_dev);
+  if (rc) return rc;
+  oqr_opts o;
+  if ((rc = resolve_opts(opts, &o))) return rc;
+  hipStream_t s = (hipStream_t)stream;
+  if (launch_fill_i32(info_dev, 0, 1, s) != hipSuccess) return OQR_E_HIP;
+  if (n == 0) return OQR_OK;
+  PassWs w;
+  const size_t need = pass_ws(A, m, n, o, true, nullptr, nullptr);
+  if ((rc = ws_check(ws, ws_bytes, need))) return rc;
+  pass_ws(A, m, n, o, true, &w, ws);
+  // pass 1: Z -> (Q1 in Q, R1);  pass 2: Q1 -> (Q in place, R2);  R = R2 R1
+  if ((rc = cholqr_pass(A, Z, ldz, m, n, Q, ldq, w.R1, n, o.pass1, o, w, w.shifts, info_dev, s))) return rc;
+  if ((rc = cholqr_pass(A, Q, ldq, m, n, Q, ldq, w.R2, n, o.pass2, o, w, w.shifts + 1, info_dev, s))) return rc;
+  if (launch_trmm_upper(w.R2, n, w.R1, n, R, ldr, n, info_dev, s) != hipSuccess) return OQR_E_HIP;
+  return OQR_OK;
+}
+
+int oqr_gs(const oqr_op* A, const double* Z, int64_t ldz, int64_t m, int64_t n, double* Q, int64_t ldq, double* R,
+           int64_t ldr, const oqr_opts* opts, void* ws, size_t ws_bytes, int32_t* info_dev, void* stream) {
+  int rc = check_common(A, Z, ldz, m, n, Q, ldq, R, ldr, info_dev);
+  if (rc) return rc;
+  oqr_opts o;
+  if ((rc = resolve_opts(opts, &o))) return rc;
+  if (o.gs_variant < OQR_GS_CGS || o.gs_variant > OQR_GS_CGS2) return OQR_E_ARG;
+  hipStream_t s = (hipStream_t)stream;
+  if (launch_fill_i32(info_dev, 0, 1, s) != hipSuccess) return OQR_E_HIP;
+  if (n == 0) return OQR_OK;
+  if ((rc = ws_check(ws, ws_bytes, gs_workspace_bytes(A, m, n)))) return rc;
+  return gs_run(A, Z, ldz, m, n, Q, ldq, R, ldr, o.gs_variant, ws, info_dev, s);
+}
+
+int oqr_chol_a(const oqr_op* A, const double* Z, int64_t ldz, int64_t m, int64_t n, double* Q, int64_t ldq,
+               double* R, int64_t ldr, const oqr_opts* opts, void* ws, size_t ws_bytes, int32_t* info_dev,
+               void* stream) {
+  int rc = check_common(A, Z, ldz, m, n, Q, ldq, R, ldr, info_dev);
+  if (rc) return rc;
+  if (A->kind != OQR_OP_DENSE) return OQR_E_UNSUPPORTED;
+  oqr_opts o;
+  if ((rc = resolve_opts(opts, &o))) return rc;
+  hipStream_t s = (hipStream_t)stream;
+  if (launch_fill_i32(info_dev, 0, 1, s) != hipSuccess) return OQR_E_HIP;
+  if (n == 0) return OQR_OK;
+  if ((rc = ws_check(ws, ws_bytes, chol_a_workspace_bytes(m, n)))) return rc;
+  return chol_a_run(A, Z, ldz, m, n, Q, ldq, R, ldr, ws, info_dev, s);
+}
+
+int oqr_eig_a(const oqr_op* A, const double* Z, int64_t ldz, int64_t m, int64_t n, double* Q, int64_t ldq,
+              double* R, int64_t ldr, const oqr_opts* opts, void* ws, size_t ws_bytes, int32_t* info_dev,
+              void* stream) {
+  int rc = check_common(A, Z, ldz, m, n, Q, ldq, R, ldr, info_dev);
+  if (rc) return rc;
+  if (A->kind != OQR_OP_DENSE) return OQR_E_UNSUPPORTED;
+  oqr_opts o;
+  if ((rc = resolve_opts(opts, &o))) return rc;
+  hipStream_t s = (hipStream_t)stream;
+  if (launch_fill_i32(info_dev, 0, 1, s) != hipSuccess) return OQR_E_HIP;
+  if (n == 0) return OQR_OK;
+  if ((rc = ws_check(ws, ws_bytes, eig_a_workspace_bytes(m, n)))) return rc;
+  return eig_a_run(A, Z, ldz, m, n, Q, ldq, R, ldr, ws, info_dev, s);
+}
+
+int oqr_check(const oqr_op* A, const double* Z, int64_t ldz, int64_t m, int64_t n, const double* Q, int64_t ldq,
+              const double* R, int64_t ldr, void* ws, size_t ws_bytes, double* out_dev, void* stream) {
+  if (!out_dev) return OQR_E_ARG;
+  if (m < n || n < 1 || n > OQR_MAX_N || !Z || !Q || !R || ldz < m || ldq < m || ldr < n) return OQR_E_ARG;
+  int rc = check_op(A, m);
+  if (rc) return rc;
+  if ((rc = ws_check(ws, ws_bytes, check_workspace_bytes(A, m, n)))) return rc;
+  return check_run(A, Z, ldz, m, n, Q, ldq, R, ldr, ws, ws_bytes, out_dev, (hipStream_t)stream);
+}
+
+}  // extern "C"

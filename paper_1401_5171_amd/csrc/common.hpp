@@ -1,0 +1,99 @@
+// Shared device/host helpers of the oblique-QR library (gfx950 only).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "oqr.h"
+
+namespace oqr {
+
+typedef double f64x4 __attribute__((ext_vector_type(4)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef unsigned short u16x8 __attribute__((ext_vector_type(8)));
+
+// Lane layouts of the MFMA instructions used here (wave64; verified on gfx950):
+//  v_mfma_f64_16x16x4_f64   A[i][k]: lane l holds (i = l%16, k = l/16); B[k][j]: (k = l/16, j = l%16);
+//                           D[i][j]: lane l, element r holds (i = 4r + l/16, j = l%16).
+//  v_mfma_f32_16x16x32_bf16 A[i][k]: lane l holds i = l%16, k = 8(l/16)+e; B[k][j]: k = 8(l/16)+e, j = l%16;
+//                           D: lane l, element r holds (i = 4(l/16) + r, j = l%16).
+//  v_mfma_f32_32x32x16_bf16 A[i][k]: i = l%32, k = 8(l/32)+e; B[k][j]: k = 8(l/32)+e, j = l%32;
+//                           D: element r holds (i = 8(r/4) + 4(l/32) + r%4, j = l%32).
+
+__device__ __forceinline__ f64x4 mfma_f64(double a, double b, f64x4 c) {
+  return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+
+// Round an FP32 value to bfloat16, nearest-even, returned as its 16 bits.
+// (Inputs here are finite; a NaN input maps to a quiet NaN.)
+__device__ __forceinline__ unsigned short bf16_bits(float f) {
+  unsigned int u = __float_as_uint(f);
+  if ((u & 0x7fffffffu) > 0x7f800000u) return 0x7fc0;
+  u += 0x7fffu + ((u >> 16) & 1u);
+  return (unsigned short)(u >> 16);
+}
+__device__ __forceinline__ float bf16_to_f32(unsigned short b) { return __uint_as_float(((unsigned int)b) << 16); }
+
+// Split x (FP64) into k bfloat16 slices s_0 = bf16(x), s_j = bf16(x - s_0 - ... - s_{j-1}),
+// rounding through FP32 at each step.
+template <int K>
+__device__ __forceinline__ void split_bf16(double x, unsigned short (&s)[K]) {
+  double r = x;
+#pragma unroll
+  for (int j = 0; j < K; ++j) {
+    s[j] = bf16_bits((float)r);
+    r -= (double)bf16_to_f32(s[j]);
+  }
+}
+
+inline int ceil_div(int64_t a, int64_t b) { return (int)((a + b - 1) / b); }
+// Leading dimension of the bfloat16 slices of Z: m rounded up to a multiple of 32.
+__host__ __device__ inline int64_t split_ld(int64_t m) { return (m + 31) & ~(int64_t)31; }
+inline size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+// Kernel ids for oqr_trace_start (names in api.hip).
+enum KernelId { K_GEMM_F64 = 1, K_GEMM_SPLIT = 2, K_GRAM = 3, K_CHOL = 4, K_TRSM = 5, K_STENCIL = 6, K_SPLIT_Z = 7 };
+void trace_pre(int kid, hipStream_t s);
+void trace_post(int kid, hipStream_t s);
+
+// ---- launchers implemented in the kernel translation units --------------------------------------
+
+// W (m x n, ldw) = A (m x m, lda) * Z (m x n, ldz), FP64 MFMA.
+hipError_t launch_gemm_f64(const double* A, int64_t lda, const double* Z, int64_t ldz, double* W, int64_t ldw,
+                           int64_t m, int64_t n, hipStream_t s);
+// W = A * Z with A split on the fly into `slices` bfloat16 slices and Z pre-split (zs: slices x n
+// columns of split_ld(m) bf16 each); FP32 MFMA accumulation over K tiles of 256, FP64 across tiles.
+hipError_t launch_gemm_split(const double* A, int64_t lda, const unsigned short* zs, double* W, int64_t ldw,
+                             int64_t m, int64_t n, int slices, hipStream_t s);
+// zs[s][j*m + i] = slice s of Z(i, j).
+hipError_t launch_split_z(const double* Z, int64_t ldz, unsigned short* zs, int64_t m, int64_t n, int slices,
+                          hipStream_t s);
+// W = A Z for the 7-point stencil (FP64).
+hipError_t launch_stencil_apply(const oqr_op* op, const double* Z, int64_t ldz, double* W, int64_t ldw,
+                                int64_t n, hipStream_t s);
+
+// Gram: partial[c] = (X^T Y) restricted to row chunk c, upper 64x64 tiles; then G = sum_c partial[c].
+size_t gram_partial_bytes(int64_t m, int64_t n);
+hipError_t launch_gram_f64(const double* X, int64_t ldx, const double* Y, int64_t ldy, int64_t m, int64_t n,
+                           double* partial, double* G, hipStream_t s);
+hipError_t launch_gram_split(const double* X, int64_t ldx, const double* Y, int64_t ldy, int64_t m, int64_t n,
+                             int slices, double* partial, double* G, hipStream_t s);
+
+// Shifted Cholesky of G (n x n, ld n, FP64, upper triangle read) into R (ldr), info on device.
+// Shift s = c * unit * max_i G_ii with c = c_first on the first attempt; on a failed pivot the
+// constant becomes c_retry (if it was 0) or 10c, at most max_retries times.  Skipped if *info != 0.
+hipError_t launch_chol_small(const double* G, int64_t n, double* R, int64_t ldr, double unit, double c_first,
+                             double c_retry, int max_retries, int32_t* info, double* shift_used, hipStream_t s);
+// Q = Z R^{-1} (row-wise substitution), Q may alias Z.  Skipped when *info != 0.
+hipError_t launch_trsm(const double* Z, int64_t ldz, const double* R, int64_t ldr, double* Q, int64_t ldq,
+                       int64_t m, int64_t n, const int32_t* info, hipStream_t s);
+// R = R2 * R1 (upper x upper).
+hipError_t launch_trmm_upper(const double* R2, int64_t ld2, const double* R1, int64_t ld1, double* R, int64_t ldr,
+                             int64_t n, const int32_t* info, hipStream_t s);
+hipError_t launch_copy_matrix(const double* X, int64_t ldx, double* Y, int64_t ldy, int64_t m, int64_t n,
+                              hipStream_t s);
+hipError_t launch_fill_i32(int32_t* p, int32_t v, int64_t count, hipStream_t s);
+
+}  // namespace oqr

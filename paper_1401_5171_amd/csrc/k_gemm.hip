@@ -1,0 +1,282 @@
+// Dense operator product W = A * Z (step 1 of CHOLQR, Algorithm 1), on MFMA.
+//
+// A is m x m (column-major, lda), Z and W are m x n (column-major).  A is the
+// large operand and is streamed from HBM exactly once: a workgroup owns a
+// 64-row block of W over the full width of n (up to 256 columns), so that
+// each A tile is used for every column.  Z tiles are re-read by every row
+// block and are served from L2/MALL.
+#include "common.hpp"
+
+namespace oqr {
+namespace {
+
+constexpr int BM = 64;       // rows of W per workgroup
+constexpr int NT = 256;      // threads per workgroup (4 waves)
+
+// ---------------------------------------------------------------------------------------------
+// FP64: v_mfma_f64_16x16x4_f64.  Wave w owns all 64 rows and columns [w*16*CB, (w+1)*16*CB).
+// ---------------------------------------------------------------------------------------------
+constexpr int BK64 = 16;
+constexpr int APAD = 8, BPAD = 8;
+
+template <int CB>
+__global__ __launch_bounds__(NT, 2) void gemm_f64_kernel(const double* __restrict__ A, int64_t lda,
+                                                          const double* __restrict__ Z, int64_t ldz,
+                                                          double* __restrict__ W, int64_t ldw, int m, int n) {
+  constexpr int BN = 64 * CB;                   // columns per workgroup
+  __shared__ double As[BK64][BM + APAD];
+  __shared__ double Bs[BK64][BN + BPAD];
+  const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+  const int i0 = blockIdx.x * BM, j0 = blockIdx.y * BN;
+  const int wc = wave * 16 * CB;
+
+  f64x4 acc[4][CB];
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = 0; b < CB; ++b) acc[a][b] = f64x4{0, 0, 0, 0};
+
+  // global -> register staging
+  constexpr int AR = BM * BK64 / NT;            // 4
+  constexpr int BR = BK64 * BN / NT;            // 4*CB
+  double ra[AR], rb[BR];
+  const int ai = t % BM, ak = t / BM;           // A: row ai, k = ak + 4r
+  const int bk = t % BK64, bj = t / BK64;       // Z: k = bk, col = bj + 16r
+  auto load = [&](int k0) {
+#pragma unroll
+    for (int r = 0; r < AR; ++r) {
+      int i = i0 + ai, k = k0 + ak + 4 * r;
+      ra[r] = (i < m && k < m) ? A[(int64_t)k * lda + i] : 0.0;
+    }
+#pragma unroll
+    for (int r = 0; r < BR; ++r) {
+      int k = k0 + bk, j = j0 + bj + 16 * r;
+      rb[r] = (k < m && j < n) ? Z[(int64_t)j * ldz + k] : 0.0;
+    }
+  };
+  auto store = [&]() {
+#pragma unroll
+    for (int r = 0; r < AR; ++r) As[ak + 4 * r][ai] = ra[r];
+#pragma unroll
+    for (int r = 0; r < BR; ++r) Bs[bk][bj + 16 * r] = rb[r];
+  };
+
+  load(0);
+  store();
+  __syncthreads();
+  for (int k0 = 0; k0 < m; k0 += BK64) {
+    const bool more = k0 + BK64 < m;
+    if (more) load(k0 + BK64);
+#pragma unroll
+    for (int kk = 0; kk < BK64; kk += 4) {
+      const int kr = kk + (lane >> 4);
+      double af[4], bf[CB];
+#pragma unroll
+      for (int a = 0; a < 4; ++a) af[a] = As[kr][a * 16 + (lane & 15)];
+#pragma unroll
+      for (int b = 0; b < CB; ++b) bf[b] = Bs[kr][wc + b * 16 + (lane & 15)];
+#pragma unroll
+      for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < CB; ++b) acc[a][b] = mfma_f64(af[a], bf[b], acc[a][b]);
+    }
+    __syncthreads();
+    if (more) {
+      store();
+      __syncthreads();
+    }
+  }
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = 0; b < CB; ++b)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        int i = i0 + a * 16 + 4 * r + (lane >> 4);
+        int j = j0 + wc + b * 16 + (lane & 15);
+        if (i < m && j < n) W[(int64_t)j * ldw + i] = acc[a][b][r];
+      }
+}
+
+// ---------------------------------------------------------------------------------------------
+// Split bfloat16: v_mfma_f32_16x16x32_bf16 on S slices, FP32 accumulation over KT = 256 rows of
+// K, then folded into FP64 accumulators.
+// ---------------------------------------------------------------------------------------------
+constexpr int BKS = 32;
+constexpr int KT = 256;
+constexpr int SPAD = 8;   // bf16 elements of padding per LDS row
+
+template <int S, int CB>
+__global__ __launch_bounds__(NT, 1) void gemm_split_kernel(const double* __restrict__ A, int64_t lda,
+                                                            const unsigned short* __restrict__ zs,
+                                                            double* __restrict__ W, int64_t ldw, int m, int n) {
+  constexpr int BN = 64 * CB;
+  __shared__ __attribute__((aligned(16))) unsigned short As[S][BM][BKS + SPAD];   // [slice][row i][k]
+  __shared__ __attribute__((aligned(16))) unsigned short Bs[S][BN][BKS + SPAD];   // [slice][col j][k]
+  const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+  const int i0 = blockIdx.x * BM, j0 = blockIdx.y * BN;
+  const int wc = wave * 16 * CB;
+  const int64_t mz = (int64_t)split_ld(m);   // ld of the slices of Z (rows padded with zeros)
+
+  f32x4 acc[4][CB];
+  double dacc[4][CB][4];
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = 0; b < CB; ++b) {
+      acc[a][b] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+      for (int r = 0; r < 4; ++r) dacc[a][b][r] = 0.0;
+    }
+
+  // A tile 64 x 32 doubles: thread t handles row ai = t % 64, k = ak*8 .. ak*8+7 (ak = t / 64).
+  const int ai = t % BM, ak = t / BM;
+  // Z tile 32 x BN: thread handles column bj = t / 8 (+ 32 r), k = (t % 8) * 4 .. +3.
+  const int bq = t % 8, bj = t / 8;
+  constexpr int BR = BN / 32;
+  double ra[8];
+  uint2 rb[S][BR];          // 4 consecutive k of one column, packed
+  auto load = [&](int k0) {
+    const int i = i0 + ai;
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+      int k = k0 + ak * 8 + e;
+      ra[e] = (i < m && k < m) ? A[(int64_t)k * lda + i] : 0.0;
+    }
+#pragma unroll
+    for (int r = 0; r < BR; ++r) {
+      int j = j0 + bj + 32 * r;
+#pragma unroll
+      for (int s = 0; s < S; ++s)
+        rb[s][r] = (j < n) ? *reinterpret_cast<const uint2*>(zs + (int64_t)s * mz * n + (int64_t)j * mz + k0 + bq * 4)
+                           : make_uint2(0u, 0u);
+    }
+  };
+  auto store = [&]() {
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+      unsigned short sl[S];
+      split_bf16<S>(ra[e], sl);
+#pragma unroll
+      for (int s = 0; s < S; ++s) As[s][ai][ak * 8 + e] = sl[s];
+    }
+#pragma unroll
+    for (int r = 0; r < BR; ++r)
+#pragma unroll
+      for (int s = 0; s < S; ++s) *reinterpret_cast<uint2*>(&Bs[s][bj + 32 * r][bq * 4]) = rb[s][r];
+  };
+
+  load(0);
+  store();
+  __syncthreads();
+  int since_fold = 0;
+  for (int k0 = 0; k0 < m; k0 += BKS) {
+    const bool more = k0 + BKS < m;
+    if (more) load(k0 + BKS);
+    const int kb = 8 * (lane >> 4);
+    bf16x8 af[S][4], bfr[S][CB];
+#pragma unroll
+    for (int s = 0; s < S; ++s) {
+#pragma unroll
+      for (int a = 0; a < 4; ++a) {
+        u16x8 v = *reinterpret_cast<const u16x8*>(&As[s][a * 16 + (lane & 15)][kb]);
+        af[s][a] = __builtin_bit_cast(bf16x8, v);
+      }
+#pragma unroll
+      for (int b = 0; b < CB; ++b) {
+        u16x8 v = *reinterpret_cast<const u16x8*>(&Bs[s][wc + b * 16 + (lane & 15)][kb]);
+        bfr[s][b] = __builtin_bit_cast(bf16x8, v);
+      }
+    }
+#pragma unroll
+    for (int p = S - 1; p >= 0; --p)
+#pragma unroll
+      for (int q = S - 1 - p; q >= 0; --q)
+#pragma unroll
+        for (int a = 0; a < 4; ++a)
+#pragma unroll
+          for (int b = 0; b < CB; ++b)
+            acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[p][a], bfr[q][b], acc[a][b], 0, 0, 0);
+    since_fold += BKS;
+    if (since_fold == KT || !more) {
+#pragma unroll
+      for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < CB; ++b) {
+#pragma unroll
+          for (int r = 0; r < 4; ++r) dacc[a][b][r] += (double)acc[a][b][r];
+          acc[a][b] = f32x4{0.f, 0.f, 0.f, 0.f};
+        }
+      since_fold = 0;
+    }
+    __syncthreads();
+    if (more) {
+      store();
+      __syncthreads();
+    }
+  }
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = 0; b < CB; ++b)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        int i = i0 + a * 16 + 4 * (lane >> 4) + r;
+        int j = j0 + wc + b * 16 + (lane & 15);
+        if (i < m && j < n) W[(int64_t)j * ldw + i] = dacc[a][b][r];
+      }
+}
+
+// zs[s][j][i] (ld = split_ld(m)) = slice s of Z(i, j); rows m..ld-1 are zero.
+__global__ void split_z_kernel(const double* __restrict__ Z, int64_t ldz, unsigned short* __restrict__ zs,
+                               int64_t m, int64_t n, int slices) {
+  const int64_t mp = split_ld(m);
+  int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= mp * n) return;
+  int64_t j = idx / mp, i = idx % mp;
+  double r = (i < m) ? Z[j * ldz + i] : 0.0;
+  for (int s = 0; s < slices; ++s) {
+    unsigned short b = bf16_bits((float)r);
+    zs[(int64_t)s * mp * n + idx] = b;
+    r -= (double)bf16_to_f32(b);
+  }
+}
+
+int col_blocks(int64_t n) { return n <= 64 ? 1 : (n <= 128 ? 2 : 4); }
+
+}  // namespace
+
+hipError_t launch_gemm_f64(const double* A, int64_t lda, const double* Z, int64_t ldz, double* W, int64_t ldw,
+                           int64_t m, int64_t n, hipStream_t s) {
+  const int cb = col_blocks(n);
+  dim3 grid(ceil_div(m, BM), ceil_div(n, 64 * cb));
+  switch (cb) {
+    case 1: gemm_f64_kernel<1><<<grid, NT, 0, s>>>(A, lda, Z, ldz, W, ldw, (int)m, (int)n); break;
+    case 2: gemm_f64_kernel<2><<<grid, NT, 0, s>>>(A, lda, Z, ldz, W, ldw, (int)m, (int)n); break;
+    default: gemm_f64_kernel<4><<<grid, NT, 0, s>>>(A, lda, Z, ldz, W, ldw, (int)m, (int)n); break;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_gemm_split(const double* A, int64_t lda, const unsigned short* zs, double* W, int64_t ldw,
+                             int64_t m, int64_t n, int slices, hipStream_t s) {
+  const int cb = col_blocks(n);
+  dim3 grid(ceil_div(m, BM), ceil_div(n, 64 * cb));
+#define OQR_SPLIT_CASE(S_, CB_) gemm_split_kernel<S_, CB_><<<grid, NT, 0, s>>>(A, lda, zs, W, ldw, (int)m, (int)n)
+  if (slices == 2) {
+    if (cb == 1) OQR_SPLIT_CASE(2, 1); else if (cb == 2) OQR_SPLIT_CASE(2, 2); else OQR_SPLIT_CASE(2, 4);
+  } else {
+    if (cb == 1) OQR_SPLIT_CASE(3, 1); else if (cb == 2) OQR_SPLIT_CASE(3, 2); else OQR_SPLIT_CASE(3, 4);
+  }
+#undef OQR_SPLIT_CASE
+  return hipGetLastError();
+}
+
+hipError_t launch_split_z(const double* Z, int64_t ldz, unsigned short* zs, int64_t m, int64_t n, int slices,
+                          hipStream_t s) {
+  int64_t total = split_ld(m) * n;
+  split_z_kernel<<<(unsigned)((total + 255) / 256), 256, 0, s>>>(Z, ldz, zs, m, n, slices);
+  return hipGetLastError();
+}
+
+}  // namespace oqr

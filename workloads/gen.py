@@ -29,7 +29,7 @@ BASE_SEED = 15171
 
 __all__ = [
     "BASE_SEED", "rng_for", "logspace_to", "haar", "Butterfly", "butterfly",
-    "spd_from_eigs", "dense_spd", "tall_skinny", "gaussian_scaled",
+    "spd_from_eigs", "spd_from_eigs_torch", "dense_spd", "dense_spd_device", "tall_skinny", "gaussian_scaled",
     "paper_case", "Stencil7", "laplacian7", "BatchInstance", "batch_plan",
     "batch_instance", "CONFIGS",
 ]
@@ -78,6 +78,27 @@ class Butterfly:
     def dense(self) -> np.ndarray:
         return self.apply(np.eye(self.m))
 
+    def apply_torch(self, x):
+        """V @ x for a torch tensor x of shape (m, k) on any device (same V as `apply`)."""
+        import torch
+        dev = x.device
+        y = x.index_select(0, torch.as_tensor(self.perms[0], device=dev))
+        for r, blks in enumerate(self.blocks):
+            full = [b for b in blks if b[1] - b[0] == blks[0][1] - blks[0][0]]
+            bs = full[0][1] - full[0][0]
+            nf = len(full)
+            stack = torch.as_tensor(np.stack([b[2] for b in full]), device=dev, dtype=y.dtype)
+            head = y[: nf * bs].reshape(nf, bs, -1)
+            y_new = torch.empty_like(y)
+            y_new[: nf * bs] = torch.bmm(stack, head).reshape(nf * bs, -1)
+            del head
+            for (s_, e_, b) in blks[nf:]:
+                y_new[s_:e_] = torch.as_tensor(b, device=dev, dtype=y.dtype) @ y[s_:e_]
+            del y
+            y = y_new.index_select(0, torch.as_tensor(self.perms[r + 1], device=dev))
+            del y_new
+        return y
+
 
 def butterfly(rng: np.random.Generator, m: int, block: int = 256, rounds: int = 3) -> Butterfly:
     perms = [rng.permutation(m) for _ in range(rounds + 1)]
@@ -119,6 +140,27 @@ def spd_from_eigs(v, d: np.ndarray) -> np.ndarray:
     return a
 
 
+def spd_from_eigs_torch(v: Butterfly, d: np.ndarray, device):
+    """A = V diag(d) V^T for a Butterfly V, built with torch on `device` and stored exactly
+    symmetric (same recipe as `spd_from_eigs`; rounding of the products may differ)."""
+    import torch
+    m = v.m
+    y = torch.diag(torch.as_tensor(d, dtype=torch.float64, device=device))
+    y = v.apply_torch(y)                       # V D
+    y = v.apply_torch(y.t().contiguous())      # V D V^T
+    a = y
+    tile = 4096
+    for i in range(0, m, tile):                # symmetrise in place, tile by tile
+        ie = min(m, i + tile)
+        a[i:ie, i:ie] = 0.5 * (a[i:ie, i:ie] + a[i:ie, i:ie].t())
+        for j in range(ie, m, tile):
+            je = min(m, j + tile)
+            s_ = 0.5 * (a[i:ie, j:je] + a[j:je, i:ie].t())
+            a[i:ie, j:je] = s_
+            a[j:je, i:ie] = s_.t()
+    return a
+
+
 def dense_spd(rng: np.random.Generator, m: int, kappa: float, kind: str = "haar", block: int = 256):
     """Dense SPD A with eigenvalues logspace_to(m, kappa) and eigenvectors V.
 
@@ -131,6 +173,13 @@ def dense_spd(rng: np.random.Generator, m: int, kappa: float, kind: str = "haar"
     else:
         raise ValueError(kind)
     return spd_from_eigs(v, d), v, d
+
+
+def dense_spd_device(rng: np.random.Generator, m: int, kappa: float, device, block: int = 256):
+    """Butterfly-eigenvector SPD A built on a torch device (for sizes where the host is too slow)."""
+    d = logspace_to(m, kappa)
+    v = butterfly(rng, m, block=block)
+    return spd_from_eigs_torch(v, d, device), v, d
 
 
 def tall_skinny(rng: np.random.Generator, m: int, n: int, kappa_z: float, u: Optional[np.ndarray] = None) -> np.ndarray:
