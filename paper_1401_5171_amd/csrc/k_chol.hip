@@ -2,15 +2,18 @@
 // the Gram matrix (step 3 of Algorithm 1, R = chol(C)) with the shift-and-retry
 // rule, the triangular product R = R2 R1 that combines two passes, and fills.
 //
-// Cholesky: one workgroup of 1024 threads, blocked right-looking with 32x32
-// blocks, working in place in R (global memory, L2-resident):
-//   (a) the diagonal block is factored in LDS (one entry per thread),
-//   (b) the block row to its right is solved column by column,
-//       R_KJ = R_KK^{-T} G_KJ (substitution, one thread per column),
-//   (c) the trailing upper blocks get G_IJ -= R_KI^T R_KJ on FP64 MFMA.
-// A pivot that is not positive (or NaN) restarts the factorisation from the
-// kept G with a larger diagonal shift; after the last retry the 1-based pivot
-// index goes to info (LAPACK potrf convention).
+// Cholesky: one workgroup of 512 threads (8 waves), blocked left-looking with
+// 32x32 blocks, writing R in place.  For block row K:
+//   (a) wave w forms block (K, K+w) of G - sum_{P<K} R_PK^T R_PJ on FP64 MFMA,
+//       reading the finished rows of R (L2-resident) and keeping the result in
+//       LDS,
+//   (b) the diagonal block is factored in LDS (double-buffered, 2 entries per
+//       thread, one barrier per pivot),
+//   (c) the rest of the block row is solved column by column,
+//       R_KJ = R_KK^{-T} (G_KJ - ...), and written to R.
+// A pivot that is not positive (or NaN) restarts the factorisation from G with
+// a larger diagonal shift; after the last retry the 1-based pivot index goes
+// to info (LAPACK potrf convention).
 #include "common.hpp"
 
 #include <math.h>
@@ -19,19 +22,22 @@ namespace oqr {
 namespace {
 
 constexpr int CB = 32;
-constexpr int NTC = 1024;
+constexpr int NTC = 512;
+constexpr int NW = NTC / 64;
+constexpr int DPT = CB * CB / NTC;   // diagonal-block entries per thread
 
 __global__ __launch_bounds__(NTC) void chol_kernel(const double* __restrict__ G, int n, double* __restrict__ R,
                                                     int64_t ldr, double unit, double c_first, double c_retry,
                                                     int max_retries, int32_t* __restrict__ info,
                                                     double* __restrict__ shift_used) {
-  __shared__ double Dk[CB][CB + 1];
-  __shared__ double P[CB][OQR_MAX_N + 2];     // P[p][j] = R(k0 + p, j), j absolute column
-  __shared__ double red[NTC / 64];
+  __shared__ double Dk[2][CB][CB + 1];
+  __shared__ double P[CB][OQR_MAX_N + 2];     // block row K: P[p][j] = entry (k0 + p, j), j absolute column
+  __shared__ double red[NW];
   __shared__ double s_dmax;
   __shared__ int s_fail;
   const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
   if (info[0] != 0) return;                   // an earlier pass failed
+  const int nb = (n + CB - 1) / CB;
 
   // max_i G_ii (estimator of ||G||_2 for the shift)
   double v = (t < n) ? G[(int64_t)t * n + t] : 0.0;
@@ -40,79 +46,24 @@ __global__ __launch_bounds__(NTC) void chol_kernel(const double* __restrict__ G,
   __syncthreads();
   if (t == 0) {
     double mx = 0.0;
-    for (int w = 0; w < NTC / 64; ++w) mx = fmax(mx, red[w]);
+    for (int w = 0; w < NW; ++w) mx = fmax(mx, red[w]);
     s_dmax = mx;
   }
   __syncthreads();
   const double dmax = s_dmax;
-  const int npad = (n + CB - 1) / CB * CB;
+  const int li = lane >> 4, lj = lane & 15;   // MFMA layouts
 
   double c = c_first;
   for (int attempt = 0;; ++attempt) {
     const double s = c * unit * dmax;
-    for (int idx = t; idx < n * n; idx += NTC) {
-      const int j = idx / n, i = idx % n;
-      R[(int64_t)j * ldr + i] = (i <= j) ? G[(int64_t)j * n + i] + (i == j ? s : 0.0) : 0.0;
-    }
     if (t == 0) s_fail = 0;
     __syncthreads();
-
-    for (int k0 = 0; k0 < n; k0 += CB) {
-      const int kb = min(CB, n - k0);
-      // (a) factor the diagonal block in LDS
-      const int di = t >> 5, dj = t & 31;
-      Dk[di][dj] = (di < kb && dj < kb) ? R[(int64_t)(k0 + dj) * ldr + k0 + di] : (di == dj ? 1.0 : 0.0);
-      __syncthreads();
-      for (int k = 0; k < kb; ++k) {
-        const double piv = Dk[k][k];
-        if (!(piv > 0.0)) {                    // every thread reads the same value: uniform exit
-          if (t == 0) s_fail = k0 + k + 1;
-          break;
-        }
-        const double rkk = sqrt(piv);
-        double nv = 0.0;
-        bool wr = false;
-        if (di == k && dj >= k) {
-          nv = (dj == k) ? rkk : Dk[k][dj] / rkk;
-          wr = true;
-        } else if (di > k && dj >= di) {
-          nv = Dk[di][dj] - (Dk[k][di] / rkk) * (Dk[k][dj] / rkk);
-          wr = true;
-        }
-        __syncthreads();
-        if (wr) Dk[di][dj] = nv;
-        __syncthreads();
-      }
-      __syncthreads();
-      if (s_fail) break;
-      // (b) write the factored block, solve the block row R_KJ = R_KK^{-T} G_KJ
-      if (di < kb && dj < kb && di <= dj) R[(int64_t)(k0 + dj) * ldr + k0 + di] = Dk[di][dj];
-      const int k1 = k0 + kb;
-      const int jcol = k1 + t;
-      if (jcol < npad) {
-        double x[CB];
-#pragma unroll
-        for (int p = 0; p < CB; ++p) {
-          double acc = (p < kb && jcol < n) ? R[(int64_t)jcol * ldr + k0 + p] : 0.0;
-#pragma unroll
-          for (int q = 0; q < p; ++q) acc -= Dk[q][p] * x[q];
-          x[p] = (p < kb && jcol < n) ? acc / Dk[p][p] : 0.0;
-        }
-#pragma unroll
-        for (int p = 0; p < CB; ++p) {
-          P[p][jcol] = x[p];
-          if (p < kb && jcol < n) R[(int64_t)jcol * ldr + k0 + p] = x[p];
-        }
-      }
-      __syncthreads();
-      // (c) trailing update of the upper 32x32 blocks (I, J), k1 <= I <= J
-      const int nbt = (n - k1 + CB - 1) / CB;
-      const int pairs = nbt * (nbt + 1) / 2;
-      for (int pr = wave; pr < pairs; pr += NTC / 64) {
-        int a = 0, rem = pr;
-        while (rem >= nbt - a) { rem -= nbt - a; ++a; }
-        const int b = a + rem;
-        const int I0 = k1 + a * CB, J0 = k1 + b * CB;
+    for (int K = 0; K < nb; ++K) {
+      const int k0 = K * CB;
+      // (a) block (K, J) for J = K + wave, minus the contributions of the finished rows
+      const int J = K + wave;
+      if (J < nb) {
+        const int J0 = J * CB;
         f64x4 acc[2][2];
 #pragma unroll
         for (int x = 0; x < 2; ++x)
@@ -120,21 +71,37 @@ __global__ __launch_bounds__(NTC) void chol_kernel(const double* __restrict__ G,
           for (int y = 0; y < 2; ++y)
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
-              const int i = I0 + 16 * x + 4 * r + (lane >> 4), j = J0 + 16 * y + (lane & 15);
-              acc[x][y][r] = (i < n && j < n) ? R[(int64_t)j * ldr + i] : 0.0;
+              const int i = k0 + 16 * x + 4 * r + li, j = J0 + 16 * y + lj;
+              double g = (i == j) ? 1.0 : 0.0;      // identity beyond n
+              if (i < n && j < n) g = (i <= j) ? G[(int64_t)j * n + i] + (i == j ? s : 0.0) : 0.0;
+              acc[x][y][r] = g;
+            }
+        const double* Ra[2];
+        const double* Rb[2];
+        bool oka[2], okb[2];
+#pragma unroll
+        for (int x = 0; x < 2; ++x) {
+          const int ca = k0 + 16 * x + lj, cb = J0 + 16 * x + lj;
+          oka[x] = ca < n;
+          okb[x] = cb < n;
+          Ra[x] = R + (int64_t)min(ca, n - 1) * ldr + li;
+          Rb[x] = R + (int64_t)min(cb, n - 1) * ldr + li;
+        }
+        for (int p0 = 0; p0 < k0; p0 += 16) {          // k0 is a multiple of 32
+          double a[4][2], b[4][2];
+#pragma unroll
+          for (int u = 0; u < 4; ++u)
+#pragma unroll
+            for (int x = 0; x < 2; ++x) {
+              a[u][x] = oka[x] ? -Ra[x][p0 + 4 * u] : 0.0;
+              b[u][x] = okb[x] ? Rb[x][p0 + 4 * u] : 0.0;
             }
 #pragma unroll
-        for (int kk = 0; kk < CB; kk += 4) {
-          const int kr = kk + (lane >> 4);
-          double av[2], bv[2];
+          for (int u = 0; u < 4; ++u)
 #pragma unroll
-          for (int x = 0; x < 2; ++x) av[x] = -P[kr][I0 + 16 * x + (lane & 15)];
+            for (int x = 0; x < 2; ++x)
 #pragma unroll
-          for (int y = 0; y < 2; ++y) bv[y] = P[kr][J0 + 16 * y + (lane & 15)];
-#pragma unroll
-          for (int x = 0; x < 2; ++x)
-#pragma unroll
-            for (int y = 0; y < 2; ++y) acc[x][y] = mfma_f64(av[x], bv[y], acc[x][y]);
+              for (int y = 0; y < 2; ++y) acc[x][y] = mfma_f64(a[u][x], b[u][y], acc[x][y]);
         }
 #pragma unroll
         for (int x = 0; x < 2; ++x)
@@ -142,9 +109,53 @@ __global__ __launch_bounds__(NTC) void chol_kernel(const double* __restrict__ G,
           for (int y = 0; y < 2; ++y)
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
-              const int i = I0 + 16 * x + 4 * r + (lane >> 4), j = J0 + 16 * y + (lane & 15);
-              if (i < n && j < n && i <= j) R[(int64_t)j * ldr + i] = acc[x][y][r];
+              const int i = 16 * x + 4 * r + li, j = 16 * y + lj;
+              if (J == K) Dk[0][i][j] = acc[x][y][r];
+              else P[i][J0 + j] = acc[x][y][r];
             }
+      }
+      __syncthreads();
+      // (b) factor the diagonal block (double-buffered, one barrier per step)
+      for (int k = 0; k < CB; ++k) {
+        const int cur = k & 1, nxt = cur ^ 1;
+        const double piv = Dk[cur][k][k];
+        if (!(piv > 0.0)) {                    // every thread reads the same value: uniform exit
+          if (t == 0) s_fail = k0 + k + 1;
+          break;
+        }
+        const double rkk = sqrt(piv);
+#pragma unroll
+        for (int e = 0; e < DPT; ++e) {
+          const int di = (t + NTC * e) >> 5, dj = (t + NTC * e) & 31;
+          double nv = Dk[cur][di][dj];
+          if (di == k && dj >= k) nv = (dj == k) ? rkk : nv / rkk;
+          else if (di > k && dj >= di) nv = nv - (Dk[cur][k][di] / rkk) * (Dk[cur][k][dj] / rkk);
+          Dk[nxt][di][dj] = nv;
+        }
+        __syncthreads();
+      }
+      __syncthreads();
+      if (s_fail) break;
+      // (c) write the diagonal block; solve the rest of the block row, one thread per column
+#pragma unroll
+      for (int e = 0; e < DPT; ++e) {
+        const int di = (t + NTC * e) >> 5, dj = (t + NTC * e) & 31;
+        if (k0 + di < n && k0 + dj < n) R[(int64_t)(k0 + dj) * ldr + k0 + di] = (di <= dj) ? Dk[0][di][dj] : 0.0;
+      }
+      const int jcol = k0 + CB + t;
+      if (jcol < n) {
+        for (int p = 0; p < CB; ++p) {
+          double a = P[p][jcol];
+          for (int q = 0; q < p; ++q) a -= Dk[0][q][p] * P[q][jcol];
+          a = a / Dk[0][p][p];
+          P[p][jcol] = a;
+          if (k0 + p < n) R[(int64_t)jcol * ldr + k0 + p] = a;
+        }
+      }
+      // strictly lower part of block column K (rows below the diagonal block) is zero
+      for (int idx = t; idx < CB * n; idx += NTC) {
+        const int j = k0 + idx % CB, i = k0 + CB + idx / CB;
+        if (j < n && i < n) R[(int64_t)j * ldr + i] = 0.0;
       }
       __syncthreads();
     }

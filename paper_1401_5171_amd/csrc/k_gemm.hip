@@ -99,24 +99,38 @@ __global__ __launch_bounds__(NT, 2) void gemm_f64_kernel(const double* __restric
 }
 
 // ---------------------------------------------------------------------------------------------
-// Split bfloat16: v_mfma_f32_16x16x32_bf16 on S slices, FP32 accumulation over KT = 256 rows of
-// K, then folded into FP64 accumulators.
+// Split bfloat16: v_mfma_f32_16x16x32_bf16 on the S-slice products with slice indices p + q < S.
+// A is split on the fly (FP64 -> FP32 -> S bfloat16 slices) into a double-buffered LDS tile; the
+// slices of Z are pre-split in HBM and read as MFMA B fragments straight into registers, one
+// K step ahead.  FP32 accumulation over KT rows of K, then folded into FP64 accumulators.
+// One wave per SIMD (4 waves, up to 512 registers each), one barrier per K step.
 // ---------------------------------------------------------------------------------------------
 constexpr int BKS = 32;
-constexpr int KT = 256;
-constexpr int SPAD = 8;   // bf16 elements of padding per LDS row
+constexpr int KT = 1024;
+constexpr int SROW = BKS + 8;   // LDS row stride of an A slice (bf16 elements)
+
+// x ~ s0 + s1 + ... with s_j = bf16 (round to nearest even) of the FP32 remainder; the remainders
+// f - s0 - ... are exact in FP32 because each slice is the leading part of the remainder.
+template <int S>
+__device__ __forceinline__ void split_f32_bf16(float f, unsigned short (&sl)[S]) {
+#pragma unroll
+  for (int j = 0; j < S; ++j) {
+    sl[j] = bf16_bits(f);
+    f -= bf16_to_f32(sl[j]);
+  }
+}
 
 template <int S, int CB>
 __global__ __launch_bounds__(NT, 1) void gemm_split_kernel(const double* __restrict__ A, int64_t lda,
                                                             const unsigned short* __restrict__ zs,
                                                             double* __restrict__ W, int64_t ldw, int m, int n) {
   constexpr int BN = 64 * CB;
-  __shared__ __attribute__((aligned(16))) unsigned short As[S][BM][BKS + SPAD];   // [slice][row i][k]
-  __shared__ __attribute__((aligned(16))) unsigned short Bs[S][BN][BKS + SPAD];   // [slice][col j][k]
+  __shared__ __attribute__((aligned(16))) unsigned short As[2][S][BM][SROW];
   const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
   const int i0 = blockIdx.x * BM, j0 = blockIdx.y * BN;
-  const int wc = wave * 16 * CB;
-  const int64_t mz = (int64_t)split_ld(m);   // ld of the slices of Z (rows padded with zeros)
+  const int wc = j0 + wave * 16 * CB;
+  const int64_t mp = split_ld(m);             // ld of the slices of Z (rows padded with zeros)
+  const int64_t slice_stride = mp * n;
 
   f32x4 acc[4][CB];
   double dacc[4][CB][4];
@@ -129,74 +143,79 @@ __global__ __launch_bounds__(NT, 1) void gemm_split_kernel(const double* __restr
       for (int r = 0; r < 4; ++r) dacc[a][b][r] = 0.0;
     }
 
-  // A tile 64 x 32 doubles: thread t handles row ai = t % 64, k = ak*8 .. ak*8+7 (ak = t / 64).
+  // A tile 64 x 32: thread t loads row ai = t % 64, k = 8 ak .. 8 ak + 7 (ak = t / 64).
   const int ai = t % BM, ak = t / BM;
-  // Z tile 32 x BN: thread handles column bj = t / 8 (+ 32 r), k = (t % 8) * 4 .. +3.
-  const int bq = t % 8, bj = t / 8;
-  constexpr int BR = BN / 32;
+  const double* Arow = A + i0 + ai;
+  const bool arow_ok = i0 + ai < m;
   double ra[8];
-  uint2 rb[S][BR];          // 4 consecutive k of one column, packed
-  auto load = [&](int k0) {
-    const int i = i0 + ai;
+  auto load_a = [&](int k0) {
 #pragma unroll
     for (int e = 0; e < 8; ++e) {
-      int k = k0 + ak * 8 + e;
-      ra[e] = (i < m && k < m) ? A[(int64_t)k * lda + i] : 0.0;
-    }
-#pragma unroll
-    for (int r = 0; r < BR; ++r) {
-      int j = j0 + bj + 32 * r;
-#pragma unroll
-      for (int s = 0; s < S; ++s)
-        rb[s][r] = (j < n) ? *reinterpret_cast<const uint2*>(zs + (int64_t)s * mz * n + (int64_t)j * mz + k0 + bq * 4)
-                           : make_uint2(0u, 0u);
+      const int k = k0 + ak * 8 + e;
+      ra[e] = (arow_ok && k < m) ? Arow[(int64_t)k * lda] : 0.0;
     }
   };
-  auto store = [&]() {
+  auto store_a = [&](int buf) {
+    unsigned short sl[8][S];
 #pragma unroll
-    for (int e = 0; e < 8; ++e) {
-      unsigned short sl[S];
-      split_bf16<S>(ra[e], sl);
-#pragma unroll
-      for (int s = 0; s < S; ++s) As[s][ai][ak * 8 + e] = sl[s];
-    }
-#pragma unroll
-    for (int r = 0; r < BR; ++r)
-#pragma unroll
-      for (int s = 0; s < S; ++s) *reinterpret_cast<uint2*>(&Bs[s][bj + 32 * r][bq * 4]) = rb[s][r];
-  };
-
-  load(0);
-  store();
-  __syncthreads();
-  int since_fold = 0;
-  for (int k0 = 0; k0 < m; k0 += BKS) {
-    const bool more = k0 + BKS < m;
-    if (more) load(k0 + BKS);
-    const int kb = 8 * (lane >> 4);
-    bf16x8 af[S][4], bfr[S][CB];
+    for (int e = 0; e < 8; ++e) split_f32_bf16<S>((float)ra[e], sl[e]);
 #pragma unroll
     for (int s = 0; s < S; ++s) {
-#pragma unroll
-      for (int a = 0; a < 4; ++a) {
-        u16x8 v = *reinterpret_cast<const u16x8*>(&As[s][a * 16 + (lane & 15)][kb]);
-        af[s][a] = __builtin_bit_cast(bf16x8, v);
-      }
-#pragma unroll
-      for (int b = 0; b < CB; ++b) {
-        u16x8 v = *reinterpret_cast<const u16x8*>(&Bs[s][wc + b * 16 + (lane & 15)][kb]);
-        bfr[s][b] = __builtin_bit_cast(bf16x8, v);
-      }
+      uint4 v;
+      v.x = (unsigned)sl[0][s] | ((unsigned)sl[1][s] << 16);
+      v.y = (unsigned)sl[2][s] | ((unsigned)sl[3][s] << 16);
+      v.z = (unsigned)sl[4][s] | ((unsigned)sl[5][s] << 16);
+      v.w = (unsigned)sl[6][s] | ((unsigned)sl[7][s] << 16);
+      *reinterpret_cast<uint4*>(&As[buf][s][ai][ak * 8]) = v;
     }
+  };
+  // B fragments: lane holds k = 8 (lane / 16) .. + 7 of column wc + 16 b + lane % 16.
+  const unsigned short* zb[CB];
+  bool zok[CB];
 #pragma unroll
-    for (int p = S - 1; p >= 0; --p)
+  for (int b = 0; b < CB; ++b) {
+    const int j = wc + 16 * b + (lane & 15);
+    zok[b] = j < n;
+    zb[b] = zs + (int64_t)(zok[b] ? j : 0) * mp + 8 * (lane >> 4);
+  }
+  uint4 bcur[S][CB], bnxt[S][CB];
+  auto load_b = [&](int k0, uint4 (&dst)[S][CB]) {
 #pragma unroll
-      for (int q = S - 1 - p; q >= 0; --q)
+    for (int s = 0; s < S; ++s)
+#pragma unroll
+      for (int b = 0; b < CB; ++b)
+        dst[s][b] = zok[b] ? *reinterpret_cast<const uint4*>(zb[b] + s * slice_stride + k0) : make_uint4(0, 0, 0, 0);
+  };
+
+  load_a(0);
+  load_b(0, bcur);
+  store_a(0);
+  __syncthreads();
+  const int nsteps = (m + BKS - 1) / BKS;
+  int since_fold = 0;
+  for (int st = 0; st < nsteps; ++st) {
+    const bool more = st + 1 < nsteps;
+    const int cur = st & 1;
+    if (more) {
+      load_a((st + 1) * BKS);
+      load_b((st + 1) * BKS, bnxt);
+    }
+    const int kb = 8 * (lane >> 4);
+#pragma unroll
+    for (int p = 0; p < S; ++p) {
+      bf16x8 af[4];
+#pragma unroll
+      for (int a = 0; a < 4; ++a)
+        af[a] = __builtin_bit_cast(bf16x8, *reinterpret_cast<const u16x8*>(&As[cur][p][a * 16 + (lane & 15)][kb]));
+#pragma unroll
+      for (int q = 0; q < S - p; ++q)
 #pragma unroll
         for (int a = 0; a < 4; ++a)
 #pragma unroll
           for (int b = 0; b < CB; ++b)
-            acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[p][a], bfr[q][b], acc[a][b], 0, 0, 0);
+            acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[a], __builtin_bit_cast(bf16x8, bcur[q][b]),
+                                                                acc[a][b], 0, 0, 0);
+    }
     since_fold += BKS;
     if (since_fold == KT || !more) {
 #pragma unroll
@@ -209,11 +228,14 @@ __global__ __launch_bounds__(NT, 1) void gemm_split_kernel(const double* __restr
         }
       since_fold = 0;
     }
-    __syncthreads();
     if (more) {
-      store();
-      __syncthreads();
+      store_a(cur ^ 1);
+#pragma unroll
+      for (int s = 0; s < S; ++s)
+#pragma unroll
+        for (int b = 0; b < CB; ++b) bcur[s][b] = bnxt[s][b];
     }
+    __syncthreads();
   }
 #pragma unroll
   for (int a = 0; a < 4; ++a)
@@ -221,8 +243,8 @@ __global__ __launch_bounds__(NT, 1) void gemm_split_kernel(const double* __restr
     for (int b = 0; b < CB; ++b)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        int i = i0 + a * 16 + 4 * (lane >> 4) + r;
-        int j = j0 + wc + b * 16 + (lane & 15);
+        const int i = i0 + a * 16 + 4 * (lane >> 4) + r;
+        const int j = wc + b * 16 + (lane & 15);
         if (i < m && j < n) W[(int64_t)j * ldw + i] = dacc[a][b][r];
       }
 }

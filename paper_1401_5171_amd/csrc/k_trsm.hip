@@ -1,51 +1,126 @@
 // Triangular solve Q = Z R^{-1} (step 4 of CHOLQR, Algorithm 1), FP64.
 //
-// Each row of Q solves q_i R = z_i by substitution, which is the row-wise
-// backward-stable solve the residual bound of Theorem 2.1 rests on:
-// q_ij = (z_ij - sum_{k<j} q_ik r_kj) / r_jj, with k ascending.  One thread per
-// row (coalesced across the rows of a column-major Z); columns are processed
-// in blocks of 32 held in registers; R is read with uniform addresses.
-// Q may alias Z: a block of Z is read before the same columns of Q are written.
+// Each row of Q solves q_i R = z_i, the row-wise solve whose backward error
+// |dR^i| <= c n u |R| gives the residual bound of Theorem 2.1.  Column blocks
+// of 32 are processed left to right:
+//   (1) Z_J -= Q_{<J} R_{<J,J}    FP64 MFMA (a blocked form of the same sums)
+//   (2) Q_J  = Z_J R_JJ^{-1}       substitution, k ascending, 4 lanes per row
+// A workgroup owns 64 rows x all n columns, staged once in LDS (Z is read
+// from HBM once and Q written once).  Q may alias Z: the whole row block of Z
+// is in LDS before any of its Q columns is written.
 #include "common.hpp"
 
 namespace oqr {
 namespace {
 
+constexpr int BM = 64;
 constexpr int JB = 32;
-constexpr int NT = 64;
+constexpr int NT = 256;
+constexpr int LDQ = BM + 1;   // LDS column stride (doubles)
 
+template <int NMAX>
 __global__ __launch_bounds__(NT) void trsm_kernel(const double* Z, int64_t ldz, const double* __restrict__ R,
                                                   int64_t ldr, double* Q, int64_t ldq, int m, int n,
                                                   const int32_t* __restrict__ info) {
+  __shared__ double Qs[NMAX * LDQ];          // Qs[j * LDQ + i]: row i of the block, column j
+  __shared__ double RJ[JB][JB + 1];          // diagonal block of R
   if (info[0] != 0) return;
-  const int i = blockIdx.x * NT + threadIdx.x;
-  const bool ok = i < m;
-  for (int j0 = 0; j0 < n; j0 += JB) {
-    const int jb = min(JB, n - j0);
-    double x[JB];
-#pragma unroll
-    for (int c = 0; c < JB; ++c) x[c] = (ok && c < jb) ? Z[(int64_t)(j0 + c) * ldz + i] : 0.0;
-    for (int k = 0; k < j0; ++k) {
-      const double qk = ok ? Q[(int64_t)k * ldq + i] : 0.0;
-      const double* rk = R + (int64_t)j0 * ldr + k;
-#pragma unroll
-      for (int c = 0; c < JB; ++c)
-        if (c < jb) x[c] -= qk * rk[(int64_t)c * ldr];
+  const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+  const int i0 = blockIdx.x * BM;
+  const int nblk = (n + JB - 1) / JB;
+
+  // load the Z row block (column-major: 64 contiguous rows per column)
+  {
+    const int i = t % BM, jq = t / BM;
+    const bool ok = i0 + i < m;
+    for (int j = jq; j < nblk * JB; j += NT / BM)
+      Qs[j * LDQ + i] = (ok && j < n) ? Z[(int64_t)j * ldz + i0 + i] : 0.0;
+  }
+  const int row = t >> 2, sub = t & 3;      // substitution: 4 lanes per row
+  for (int J = 0; J < nblk; ++J) {
+    const int j0 = J * JB;
+    // stage R_JJ (upper 32x32; identity beyond n)
+    for (int idx = t; idx < JB * JB; idx += NT) {
+      const int p = idx % JB, c = idx / JB;
+      const int gp = j0 + p, gc = j0 + c;
+      double v;
+      if (gp < n && gc < n) v = (p <= c) ? R[(int64_t)gc * ldr + gp] : 0.0;
+      else v = (p == c) ? 1.0 : 0.0;
+      RJ[p][c] = v;
     }
+    __syncthreads();
+    // (1) block update on MFMA: wave w owns rows 16w..16w+15, two 16-column halves
+    if (J > 0) {
+      f64x4 acc[2];
 #pragma unroll
-    for (int c = 0; c < JB; ++c) {
-      if (c < jb) {
-        const double* rc = R + (int64_t)(j0 + c) * ldr + j0;
+      for (int h = 0; h < 2; ++h)
 #pragma unroll
-        for (int p = 0; p < c; ++p) x[c] -= x[p] * rc[p];
-        x[c] = x[c] / rc[c];
+        for (int r = 0; r < 4; ++r) acc[h][r] = Qs[(j0 + 16 * h + (lane & 15)) * LDQ + wave * 16 + 4 * r + (lane >> 4)];
+      const int jc0 = j0 + (lane & 15), jc1 = j0 + 16 + (lane & 15);
+      const double* R0 = R + (int64_t)min(jc0, n - 1) * ldr + (lane >> 4);
+      const double* R1 = R + (int64_t)min(jc1, n - 1) * ldr + (lane >> 4);
+      const bool ok0 = jc0 < n, ok1 = jc1 < n;
+      // R fragments are read from L2 in chunks of 32 k (8 MFMA steps), one chunk ahead
+      double b0[8], b1[8];
+#pragma unroll
+      for (int s = 0; s < 8; ++s) {
+        b0[s] = ok0 ? R0[4 * s] : 0.0;
+        b1[s] = ok1 ? R1[4 * s] : 0.0;
+      }
+      for (int kc = 0; kc < j0; kc += 32) {
+        double nb0[8], nb1[8];
+        const bool more = kc + 32 < j0;
+#pragma unroll
+        for (int s = 0; s < 8; ++s) {
+          nb0[s] = (more && ok0) ? R0[kc + 32 + 4 * s] : 0.0;
+          nb1[s] = (more && ok1) ? R1[kc + 32 + 4 * s] : 0.0;
+        }
+#pragma unroll
+        for (int s = 0; s < 8; ++s) {
+          const int kr = kc + 4 * s + (lane >> 4);
+          const double a = -Qs[kr * LDQ + wave * 16 + (lane & 15)];
+          acc[0] = mfma_f64(a, b0[s], acc[0]);
+          acc[1] = mfma_f64(a, b1[s], acc[1]);
+        }
+#pragma unroll
+        for (int s = 0; s < 8; ++s) {
+          b0[s] = nb0[s];
+          b1[s] = nb1[s];
+        }
+      }
+      __syncthreads();
+#pragma unroll
+      for (int h = 0; h < 2; ++h)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) Qs[(j0 + 16 * h + (lane & 15)) * LDQ + wave * 16 + 4 * r + (lane >> 4)] = acc[h][r];
+      __syncthreads();
+    }
+    // (2) substitution on the 32 columns of the block: lane `sub` of a row owns columns sub + 4e
+    {
+      double x[8];
+#pragma unroll
+      for (int e = 0; e < 8; ++e) x[e] = Qs[(j0 + sub + 4 * e) * LDQ + row];
+#pragma unroll
+      for (int c = 0; c < JB; ++c) {
+        const int owner = c & 3, ec = c >> 2;
+        double q = 0.0;
+        if (sub == owner) {
+          x[ec] = x[ec] / RJ[c][c];
+          q = x[ec];
+        }
+        q = __shfl(q, (lane & ~3) | owner);
+#pragma unroll
+        for (int e = 0; e < 8; ++e)
+          if (sub + 4 * e > c) x[e] -= q * RJ[c][sub + 4 * e];
+      }
+#pragma unroll
+      for (int e = 0; e < 8; ++e) {
+        const int j = j0 + sub + 4 * e;
+        Qs[j * LDQ + row] = x[e];
+        if (i0 + row < m && j < n) Q[(int64_t)j * ldq + i0 + row] = x[e];
       }
     }
-    if (ok) {
-#pragma unroll
-      for (int c = 0; c < JB; ++c)
-        if (c < jb) Q[(int64_t)(j0 + c) * ldq + i] = x[c];
-    }
+    __syncthreads();
   }
 }
 
@@ -75,7 +150,13 @@ __global__ void stencil_apply_kernel(const double* __restrict__ Z, int64_t ldz, 
 
 hipError_t launch_trsm(const double* Z, int64_t ldz, const double* R, int64_t ldr, double* Q, int64_t ldq,
                        int64_t m, int64_t n, const int32_t* info, hipStream_t s) {
-  trsm_kernel<<<ceil_div(m, NT), NT, 0, s>>>(Z, ldz, R, ldr, Q, ldq, (int)m, (int)n, info);
+  const int grid = ceil_div(m, BM);
+  if (n <= 64)
+    trsm_kernel<64><<<grid, NT, 0, s>>>(Z, ldz, R, ldr, Q, ldq, (int)m, (int)n, info);
+  else if (n <= 128)
+    trsm_kernel<128><<<grid, NT, 0, s>>>(Z, ldz, R, ldr, Q, ldq, (int)m, (int)n, info);
+  else
+    trsm_kernel<256><<<grid, NT, 0, s>>>(Z, ldz, R, ldr, Q, ldq, (int)m, (int)n, info);
   return hipGetLastError();
 }
 
