@@ -48,6 +48,33 @@ __device__ __forceinline__ void split_bf16(double x, unsigned short (&s)[K]) {
   }
 }
 
+// Branch-free guarded load: the element is always read from a valid address (index 0 when the
+// guard fails) and replaced by zero afterwards, so no divergent branch or wait is generated.
+template <class T>
+__device__ __forceinline__ T sel_load(const T* base, int64_t idx, bool valid) {
+  const T v = base[valid ? idx : 0];
+  return valid ? v : T(0);
+}
+
+// Raw buffer loads: a buffer resource (base, size in bytes) and 32-bit byte offsets.  An offset
+// at or beyond the size returns zero, which gives bounds-checked tile loads without branches or
+// selects; kOOB marks a lane whose element lies outside the matrix.
+typedef __amdgpu_buffer_rsrc_t bufrsrc;
+constexpr uint32_t kOOB = 0x80000000u;
+__device__ __forceinline__ bufrsrc make_buf(const void* base, int64_t bytes) {
+  const int64_t lim = 0x7fffffff;
+  const int nb = (int)(bytes <= 0 ? 0 : (bytes > lim ? lim : bytes));
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), (short)0, nb, 0x00020000);
+}
+__device__ __forceinline__ double buf_f64(bufrsrc r, uint32_t off) {
+  return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, (int)off, 0, 0));
+}
+__device__ __forceinline__ uint4 buf_b128(bufrsrc r, uint32_t off) {
+  typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+  const u32x4 v = __builtin_bit_cast(u32x4, __builtin_amdgcn_raw_buffer_load_b128(r, (int)off, 0, 0));
+  return make_uint4(v.x, v.y, v.z, v.w);
+}
+
 inline int ceil_div(int64_t a, int64_t b) { return (int)((a + b - 1) / b); }
 // Leading dimension of the bfloat16 slices of Z: m rounded up to a multiple of 32.
 __host__ __device__ inline int64_t split_ld(int64_t m) { return (m + 31) & ~(int64_t)31; }

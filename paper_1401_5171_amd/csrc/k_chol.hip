@@ -87,21 +87,36 @@ __global__ __launch_bounds__(NTC) void chol_kernel(const double* __restrict__ G,
           Ra[x] = R + (int64_t)min(ca, n - 1) * ldr + li;
           Rb[x] = R + (int64_t)min(cb, n - 1) * ldr + li;
         }
-        for (int p0 = 0; p0 < k0; p0 += 16) {          // k0 is a multiple of 32
-          double a[4][2], b[4][2];
+        // rows of R in chunks of 32 (8 MFMA k steps), the next chunk loaded during the current one
+        double a[8][2], b[8][2];
+        auto load_chunk = [&](int p0, double (&aa)[8][2], double (&bb)[8][2]) {
 #pragma unroll
-          for (int u = 0; u < 4; ++u)
+          for (int u = 0; u < 8; ++u)
 #pragma unroll
             for (int x = 0; x < 2; ++x) {
-              a[u][x] = oka[x] ? -Ra[x][p0 + 4 * u] : 0.0;
-              b[u][x] = okb[x] ? Rb[x][p0 + 4 * u] : 0.0;
+              aa[u][x] = -sel_load(Ra[x], p0 + 4 * u, oka[x]);
+              bb[u][x] = sel_load(Rb[x], p0 + 4 * u, okb[x]);
             }
+        };
+        if (k0 > 0) load_chunk(0, a, b);
+        for (int p0 = 0; p0 < k0; p0 += CB) {          // k0 is a multiple of 32
+          double na[8][2], nbv[8][2];
+          if (p0 + CB < k0) load_chunk(p0 + CB, na, nbv);
 #pragma unroll
-          for (int u = 0; u < 4; ++u)
+          for (int u = 0; u < 8; ++u)
 #pragma unroll
             for (int x = 0; x < 2; ++x)
 #pragma unroll
               for (int y = 0; y < 2; ++y) acc[x][y] = mfma_f64(a[u][x], b[u][y], acc[x][y]);
+          if (p0 + CB < k0) {
+#pragma unroll
+            for (int u = 0; u < 8; ++u)
+#pragma unroll
+              for (int x = 0; x < 2; ++x) {
+                a[u][x] = na[u][x];
+                b[u][x] = nbv[u][x];
+              }
+          }
         }
 #pragma unroll
         for (int x = 0; x < 2; ++x)
@@ -142,14 +157,34 @@ __global__ __launch_bounds__(NTC) void chol_kernel(const double* __restrict__ G,
         const int di = (t + NTC * e) >> 5, dj = (t + NTC * e) & 31;
         if (k0 + di < n && k0 + dj < n) R[(int64_t)(k0 + dj) * ldr + k0 + di] = (di <= dj) ? Dk[0][di][dj] : 0.0;
       }
-      const int jcol = k0 + CB + t;
-      if (jcol < n) {
-        for (int p = 0; p < CB; ++p) {
-          double a = P[p][jcol];
-          for (int q = 0; q < p; ++q) a -= Dk[0][q][p] * P[q][jcol];
-          a = a / Dk[0][p][p];
-          P[p][jcol] = a;
-          if (k0 + p < n) R[(int64_t)jcol * ldr + k0 + p] = a;
+      // four lanes per column: lane `sub` owns rows sub + 4e; pivots are broadcast within the quad
+      {
+        const int sub = t & 3;
+        for (int cb = k0 + CB; cb < n; cb += NTC / 4) {
+          const int jcol = cb + (t >> 2);
+          const bool ok = jcol < n;
+          double x[8];
+#pragma unroll
+          for (int e = 0; e < 8; ++e) x[e] = P[sub + 4 * e][ok ? jcol : 0];
+#pragma unroll
+          for (int p = 0; p < CB; ++p) {
+            const int owner = p & 3, ep = p >> 2;
+            // branch-free: every lane divides, the owner's quotient is broadcast
+            const double qo = x[ep] / Dk[0][p][p];
+            const double q = __shfl(qo, (lane & ~3) | owner);
+            if (sub == owner) x[ep] = q;
+#pragma unroll
+            for (int e = 0; e < 8; ++e) {
+              const double upd = x[e] - Dk[0][p][sub + 4 * e] * q;
+              x[e] = (sub + 4 * e > p) ? upd : x[e];
+            }
+            __builtin_amdgcn_sched_barrier(0);   // keep the LDS reads of one pivot row together
+          }
+          if (ok) {
+#pragma unroll
+            for (int e = 0; e < 8; ++e)
+              if (k0 + sub + 4 * e < n) R[(int64_t)jcol * ldr + k0 + sub + 4 * e] = x[e];
+          }
         }
       }
       // strictly lower part of block column K (rows below the diagonal block) is zero

@@ -42,17 +42,22 @@ __global__ __launch_bounds__(NT, 2) void gemm_f64_kernel(const double* __restric
   double ra[AR], rb[BR];
   const int ai = t % BM, ak = t / BM;           // A: row ai, k = ak + 4r
   const int bk = t % BK64, bj = t / BK64;       // Z: k = bk, col = bj + 16r
+  // byte offsets inside the per-step buffers (rows beyond m / columns beyond n -> kOOB)
+  uint32_t aoff[AR], boff[BR];
+#pragma unroll
+  for (int r = 0; r < AR; ++r) aoff[r] = (i0 + ai < m) ? (uint32_t)(((int64_t)(ak + 4 * r) * lda + ai) * 8) : kOOB;
+#pragma unroll
+  for (int r = 0; r < BR; ++r)
+    boff[r] = (j0 + bj + 16 * r < n) ? (uint32_t)(((int64_t)(bj + 16 * r) * ldz + bk) * 8) : kOOB;
   auto load = [&](int k0) {
+    // A rows i0.., columns k0..: the size bound cuts k >= m; Z rows k0.., columns j0..
+    const bufrsrc abuf = make_buf(A + (int64_t)k0 * lda + i0, (int64_t)(m - k0) * lda * 8);
+    const bufrsrc zbuf = make_buf(Z + (int64_t)j0 * ldz + k0, (int64_t)(n - j0) * ldz * 8);
+    const bool kin = k0 + bk < m;
 #pragma unroll
-    for (int r = 0; r < AR; ++r) {
-      int i = i0 + ai, k = k0 + ak + 4 * r;
-      ra[r] = (i < m && k < m) ? A[(int64_t)k * lda + i] : 0.0;
-    }
+    for (int r = 0; r < AR; ++r) ra[r] = buf_f64(abuf, aoff[r]);
 #pragma unroll
-    for (int r = 0; r < BR; ++r) {
-      int k = k0 + bk, j = j0 + bj + 16 * r;
-      rb[r] = (k < m && j < n) ? Z[(int64_t)j * ldz + k] : 0.0;
-    }
+    for (int r = 0; r < BR; ++r) rb[r] = buf_f64(zbuf, kin ? boff[r] : kOOB);
   };
   auto store = [&]() {
 #pragma unroll
@@ -65,8 +70,7 @@ __global__ __launch_bounds__(NT, 2) void gemm_f64_kernel(const double* __restric
   store();
   __syncthreads();
   for (int k0 = 0; k0 < m; k0 += BK64) {
-    const bool more = k0 + BK64 < m;
-    if (more) load(k0 + BK64);
+    load(k0 + BK64);                   // past the end: guarded loads return zeros
 #pragma unroll
     for (int kk = 0; kk < BK64; kk += 4) {
       const int kr = kk + (lane >> 4);
@@ -81,10 +85,8 @@ __global__ __launch_bounds__(NT, 2) void gemm_f64_kernel(const double* __restric
         for (int b = 0; b < CB; ++b) acc[a][b] = mfma_f64(af[a], bf[b], acc[a][b]);
     }
     __syncthreads();
-    if (more) {
-      store();
-      __syncthreads();
-    }
+    store();
+    __syncthreads();
   }
 #pragma unroll
   for (int a = 0; a < 4; ++a)
@@ -102,8 +104,8 @@ __global__ __launch_bounds__(NT, 2) void gemm_f64_kernel(const double* __restric
 // Split bfloat16: v_mfma_f32_16x16x32_bf16 on the S-slice products with slice indices p + q < S.
 // A is split on the fly (FP64 -> FP32 -> S bfloat16 slices) into a double-buffered LDS tile; the
 // slices of Z are pre-split in HBM and read as MFMA B fragments straight into registers, one
-// K step ahead.  FP32 accumulation over KT rows of K, then folded into FP64 accumulators.
-// One wave per SIMD (4 waves, up to 512 registers each), one barrier per K step.
+// K step ahead.  FP32 accumulation over KT rows of K, then folded into FP64 accumulators kept
+// in LDS (each lane owns its slots).  One wave per SIMD, one barrier per K step.
 // ---------------------------------------------------------------------------------------------
 constexpr int BKS = 32;
 constexpr int KT = 1024;
@@ -126,6 +128,7 @@ __global__ __launch_bounds__(NT, 1) void gemm_split_kernel(const double* __restr
                                                             double* __restrict__ W, int64_t ldw, int m, int n) {
   constexpr int BN = 64 * CB;
   __shared__ __attribute__((aligned(16))) unsigned short As[2][S][BM][SROW];
+  __shared__ double Dacc[NT / 64][4 * CB * 4][64];     // FP64 accumulators: [wave][slot][lane]
   const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
   const int i0 = blockIdx.x * BM, j0 = blockIdx.y * BN;
   const int wc = j0 + wave * 16 * CB;
@@ -133,29 +136,28 @@ __global__ __launch_bounds__(NT, 1) void gemm_split_kernel(const double* __restr
   const int64_t slice_stride = mp * n;
 
   f32x4 acc[4][CB];
-  double dacc[4][CB][4];
 #pragma unroll
   for (int a = 0; a < 4; ++a)
 #pragma unroll
     for (int b = 0; b < CB; ++b) {
       acc[a][b] = f32x4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-      for (int r = 0; r < 4; ++r) dacc[a][b][r] = 0.0;
+      for (int r = 0; r < 4; ++r) Dacc[wave][(a * CB + b) * 4 + r][lane] = 0.0;
     }
 
   // A tile 64 x 32: thread t loads row ai = t % 64, k = 8 ak .. 8 ak + 7 (ak = t / 64).
+  // Three register stages keep A two K steps ahead of the MFMAs (HBM latency).
   const int ai = t % BM, ak = t / BM;
-  const double* Arow = A + i0 + ai;
-  const bool arow_ok = i0 + ai < m;
-  double ra[8];
-  auto load_a = [&](int k0) {
+  uint32_t aoff[8];
 #pragma unroll
-    for (int e = 0; e < 8; ++e) {
-      const int k = k0 + ak * 8 + e;
-      ra[e] = (arow_ok && k < m) ? Arow[(int64_t)k * lda] : 0.0;
-    }
+  for (int e = 0; e < 8; ++e) aoff[e] = (i0 + ai < m) ? (uint32_t)(((int64_t)(ak * 8 + e) * lda + ai) * 8) : kOOB;
+  double ra0[8], ra1[8], ra2[8];
+  auto load_a = [&](double (&ra)[8], int k0) {
+    const bufrsrc abuf = make_buf(A + (int64_t)min(k0, m) * lda + i0, (int64_t)(m - k0) * lda * 8);
+#pragma unroll
+    for (int e = 0; e < 8; ++e) ra[e] = buf_f64(abuf, aoff[e]);
   };
-  auto store_a = [&](int buf) {
+  auto store_a = [&](const double (&ra)[8], int buf) {
     unsigned short sl[8][S];
 #pragma unroll
     for (int e = 0; e < 8; ++e) split_f32_bf16<S>((float)ra[e], sl[e]);
@@ -170,36 +172,33 @@ __global__ __launch_bounds__(NT, 1) void gemm_split_kernel(const double* __restr
     }
   };
   // B fragments: lane holds k = 8 (lane / 16) .. + 7 of column wc + 16 b + lane % 16.
-  const unsigned short* zb[CB];
-  bool zok[CB];
+  uint32_t zoff[CB];
 #pragma unroll
   for (int b = 0; b < CB; ++b) {
     const int j = wc + 16 * b + (lane & 15);
-    zok[b] = j < n;
-    zb[b] = zs + (int64_t)(zok[b] ? j : 0) * mp + 8 * (lane >> 4);
+    zoff[b] = (j < n) ? (uint32_t)(((int64_t)j * mp + 8 * (lane >> 4)) * 2) : kOOB;
   }
   uint4 bcur[S][CB], bnxt[S][CB];
   auto load_b = [&](int k0, uint4 (&dst)[S][CB]) {
+    // rows k0 .. k0 + 31 of every slice; past the padded end the buffer is empty (zeros)
+    const bufrsrc zbuf = make_buf(zs + min((int64_t)k0, mp), k0 < mp ? (int64_t)(S * slice_stride - k0) * 2 : 0);
 #pragma unroll
     for (int s = 0; s < S; ++s)
 #pragma unroll
       for (int b = 0; b < CB; ++b)
-        dst[s][b] = zok[b] ? *reinterpret_cast<const uint4*>(zb[b] + s * slice_stride + k0) : make_uint4(0, 0, 0, 0);
+        dst[s][b] = buf_b128(zbuf, zoff[b] == kOOB ? kOOB : zoff[b] + (uint32_t)(s * slice_stride * 2));
   };
 
-  load_a(0);
-  load_b(0, bcur);
-  store_a(0);
-  __syncthreads();
-  const int nsteps = (m + BKS - 1) / BKS;
+  // K steps, padded to a multiple of 3 (the register-stage rotation); steps past the end of K
+  // read clamped addresses and contribute zeros, so no load sits under a branch.
+  const int nsteps = ((m + BKS - 1) / BKS + 2) / 3 * 3;
   int since_fold = 0;
-  for (int st = 0; st < nsteps; ++st) {
-    const bool more = st + 1 < nsteps;
+  // one K step: MFMAs on LDS buffer st & 1; A(st+1) (in ra_store) goes to the other buffer;
+  // A(st+3) is requested into ra_fill.
+  auto step = [&](int st, const double (&ra_store)[8], double (&ra_fill)[8]) {
     const int cur = st & 1;
-    if (more) {
-      load_a((st + 1) * BKS);
-      load_b((st + 1) * BKS, bnxt);
-    }
+    load_a(ra_fill, (st + 3) * BKS);
+    load_b((st + 1) * BKS, bnxt);
     const int kb = 8 * (lane >> 4);
 #pragma unroll
     for (int p = 0; p < S; ++p) {
@@ -217,26 +216,42 @@ __global__ __launch_bounds__(NT, 1) void gemm_split_kernel(const double* __restr
                                                                 acc[a][b], 0, 0, 0);
     }
     since_fold += BKS;
-    if (since_fold == KT || !more) {
+    if (since_fold == KT) {
 #pragma unroll
       for (int a = 0; a < 4; ++a)
 #pragma unroll
         for (int b = 0; b < CB; ++b) {
 #pragma unroll
-          for (int r = 0; r < 4; ++r) dacc[a][b][r] += (double)acc[a][b][r];
+          for (int r = 0; r < 4; ++r) Dacc[wave][(a * CB + b) * 4 + r][lane] += (double)acc[a][b][r];
           acc[a][b] = f32x4{0.f, 0.f, 0.f, 0.f};
         }
       since_fold = 0;
     }
-    if (more) {
-      store_a(cur ^ 1);
+    store_a(ra_store, cur ^ 1);
 #pragma unroll
-      for (int s = 0; s < S; ++s)
+    for (int s2 = 0; s2 < S; ++s2)
 #pragma unroll
-        for (int b = 0; b < CB; ++b) bcur[s][b] = bnxt[s][b];
-    }
+      for (int b = 0; b < CB; ++b) bcur[s2][b] = bnxt[s2][b];
     __syncthreads();
+  };
+
+  load_a(ra0, 0);
+  load_a(ra1, BKS);
+  load_a(ra2, 2 * BKS);
+  load_b(0, bcur);
+  store_a(ra0, 0);
+  __syncthreads();
+  for (int st = 0; st < nsteps; st += 3) {
+    step(st, ra1, ra0);
+    step(st + 1, ra2, ra1);
+    step(st + 2, ra0, ra2);
   }
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = 0; b < CB; ++b)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) Dacc[wave][(a * CB + b) * 4 + r][lane] += (double)acc[a][b][r];
 #pragma unroll
   for (int a = 0; a < 4; ++a)
 #pragma unroll
@@ -245,7 +260,7 @@ __global__ __launch_bounds__(NT, 1) void gemm_split_kernel(const double* __restr
       for (int r = 0; r < 4; ++r) {
         const int i = i0 + a * 16 + 4 * (lane >> 4) + r;
         const int j = wc + b * 16 + (lane & 15);
-        if (i < m && j < n) W[(int64_t)j * ldw + i] = dacc[a][b][r];
+        if (i < m && j < n) W[(int64_t)j * ldw + i] = Dacc[wave][(a * CB + b) * 4 + r][lane];
       }
 }
 

@@ -65,8 +65,8 @@ __global__ __launch_bounds__(NT) void gram_f64_kernel(const double* __restrict__
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
       const int cx = I0 + lc + 16 * r, cy = J0 + lc + 16 * r;
-      rx[r] = (k < r1 && cx < n) ? X[(int64_t)cx * ldx + k] : 0.0;
-      ry[r] = (k < r1 && cy < n) ? Y[(int64_t)cy * ldy + k] : 0.0;
+      rx[r] = sel_load(X, (int64_t)cx * ldx + k, k < r1 && cx < n);
+      ry[r] = sel_load(Y, (int64_t)cy * ldy + k, k < r1 && cy < n);
     }
   };
   auto store = [&]() {
@@ -139,8 +139,8 @@ __global__ __launch_bounds__(NT) void gram_split_kernel(const double* __restrict
 #pragma unroll
     for (int e = 0; e < 8; ++e) {
       const int k = k0 + lq * 8 + e;
-      rx[e] = (k < r1 && cx < n) ? X[(int64_t)cx * ldx + k] : 0.0;
-      ry[e] = (k < r1 && cy < n) ? Y[(int64_t)cy * ldy + k] : 0.0;
+      rx[e] = sel_load(X, (int64_t)cx * ldx + k, k < r1 && cx < n);
+      ry[e] = sel_load(Y, (int64_t)cy * ldy + k, k < r1 && cy < n);
     }
   };
   auto store = [&]() {

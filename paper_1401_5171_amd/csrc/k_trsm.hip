@@ -29,12 +29,22 @@ __global__ __launch_bounds__(NT) void trsm_kernel(const double* Z, int64_t ldz, 
   const int i0 = blockIdx.x * BM;
   const int nblk = (n + JB - 1) / JB;
 
-  // load the Z row block (column-major: 64 contiguous rows per column)
+  // load the Z row block (column-major: 64 contiguous rows per column), 16 loads in flight per thread
   {
     const int i = t % BM, jq = t / BM;
     const bool ok = i0 + i < m;
-    for (int j = jq; j < nblk * JB; j += NT / BM)
-      Qs[j * LDQ + i] = (ok && j < n) ? Z[(int64_t)j * ldz + i0 + i] : 0.0;
+    constexpr int STRIDE = NT / BM;
+#pragma unroll
+    for (int jb = 0; jb < NMAX; jb += 16 * STRIDE) {
+      double v[16];
+#pragma unroll
+      for (int u = 0; u < 16; ++u) {
+        const int j = jb + jq + STRIDE * u;
+        v[u] = sel_load(Z, (int64_t)j * ldz + i0 + i, ok && j < n);
+      }
+#pragma unroll
+      for (int u = 0; u < 16; ++u) Qs[(jb + jq + STRIDE * u) * LDQ + i] = v[u];
+    }
   }
   const int row = t >> 2, sub = t & 3;      // substitution: 4 lanes per row
   for (int J = 0; J < nblk; ++J) {
@@ -64,16 +74,16 @@ __global__ __launch_bounds__(NT) void trsm_kernel(const double* Z, int64_t ldz, 
       double b0[8], b1[8];
 #pragma unroll
       for (int s = 0; s < 8; ++s) {
-        b0[s] = ok0 ? R0[4 * s] : 0.0;
-        b1[s] = ok1 ? R1[4 * s] : 0.0;
+        b0[s] = sel_load(R0, 4 * s, ok0);
+        b1[s] = sel_load(R1, 4 * s, ok1);
       }
       for (int kc = 0; kc < j0; kc += 32) {
         double nb0[8], nb1[8];
         const bool more = kc + 32 < j0;
 #pragma unroll
         for (int s = 0; s < 8; ++s) {
-          nb0[s] = (more && ok0) ? R0[kc + 32 + 4 * s] : 0.0;
-          nb1[s] = (more && ok1) ? R1[kc + 32 + 4 * s] : 0.0;
+          nb0[s] = sel_load(R0, kc + 32 + 4 * s, more && ok0);
+          nb1[s] = sel_load(R1, kc + 32 + 4 * s, more && ok1);
         }
 #pragma unroll
         for (int s = 0; s < 8; ++s) {
@@ -103,15 +113,15 @@ __global__ __launch_bounds__(NT) void trsm_kernel(const double* Z, int64_t ldz, 
 #pragma unroll
       for (int c = 0; c < JB; ++c) {
         const int owner = c & 3, ec = c >> 2;
-        double q = 0.0;
-        if (sub == owner) {
-          x[ec] = x[ec] / RJ[c][c];
-          q = x[ec];
-        }
-        q = __shfl(q, (lane & ~3) | owner);
+        // branch-free: every lane divides, the owner's quotient is broadcast
+        const double qo = x[ec] / RJ[c][c];
+        const double q = __shfl(qo, (lane & ~3) | owner);
+        if (sub == owner) x[ec] = q;
 #pragma unroll
-        for (int e = 0; e < 8; ++e)
-          if (sub + 4 * e > c) x[e] -= q * RJ[c][sub + 4 * e];
+        for (int e = 0; e < 8; ++e) {
+          const double upd = x[e] - q * RJ[c][sub + 4 * e];
+          x[e] = (sub + 4 * e > c) ? upd : x[e];
+        }
       }
 #pragma unroll
       for (int e = 0; e < 8; ++e) {
