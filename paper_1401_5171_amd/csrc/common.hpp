@@ -13,6 +13,8 @@ typedef float f32x4 __attribute__((ext_vector_type(4)));
 typedef float f32x16 __attribute__((ext_vector_type(16)));
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef unsigned short u16x8 __attribute__((ext_vector_type(8)));
+typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+typedef float f32x2 __attribute__((ext_vector_type(2)));
 
 // Lane layouts of the MFMA instructions used here (wave64; verified on gfx950):
 //  v_mfma_f64_16x16x4_f64   A[i][k]: lane l holds (i = l%16, k = l/16); B[k][j]: (k = l/16, j = l%16);

@@ -17,7 +17,9 @@ constexpr int NT = 256;      // threads per workgroup (4 waves)
 // FP64: v_mfma_f64_16x16x4_f64.  Wave w owns all 64 rows and columns [w*16*CB, (w+1)*16*CB).
 // ---------------------------------------------------------------------------------------------
 constexpr int BK64 = 16;
-constexpr int APAD = 8, BPAD = 8;
+// Odd row strides (in doubles): a 16-lane group reading or writing 16 rows of one column, or 16
+// columns of one row, touches 16 distinct bank pairs.
+constexpr int APAD = 1, BPAD = 1;
 
 template <int CB>
 __global__ __launch_bounds__(NT, 2) void gemm_f64_kernel(const double* __restrict__ A, int64_t lda,
@@ -104,23 +106,11 @@ __global__ __launch_bounds__(NT, 2) void gemm_f64_kernel(const double* __restric
 // Split bfloat16: v_mfma_f32_16x16x32_bf16 on the S-slice products with slice indices p + q < S.
 // A is split on the fly (FP64 -> FP32 -> S bfloat16 slices) into a double-buffered LDS tile; the
 // slices of Z are pre-split in HBM and read as MFMA B fragments straight into registers, one
-// K step ahead.  FP32 accumulation over KT rows of K, then folded into FP64 accumulators kept
-// in LDS (each lane owns its slots).  One wave per SIMD, one barrier per K step.
+// K step ahead.  FP32 accumulation over at most 960 rows of K, then folded into FP64
+// accumulators kept in LDS (each lane owns its slots).  One wave per SIMD, one barrier per step.
 // ---------------------------------------------------------------------------------------------
 constexpr int BKS = 32;
-constexpr int KT = 1024;
 constexpr int SROW = BKS + 8;   // LDS row stride of an A slice (bf16 elements)
-
-// x ~ s0 + s1 + ... with s_j = bf16 (round to nearest even) of the FP32 remainder; the remainders
-// f - s0 - ... are exact in FP32 because each slice is the leading part of the remainder.
-template <int S>
-__device__ __forceinline__ void split_f32_bf16(float f, unsigned short (&sl)[S]) {
-#pragma unroll
-  for (int j = 0; j < S; ++j) {
-    sl[j] = bf16_bits(f);
-    f -= bf16_to_f32(sl[j]);
-  }
-}
 
 template <int S, int CB>
 __global__ __launch_bounds__(NT, 1) void gemm_split_kernel(const double* __restrict__ A, int64_t lda,
@@ -157,18 +147,24 @@ __global__ __launch_bounds__(NT, 1) void gemm_split_kernel(const double* __restr
 #pragma unroll
     for (int e = 0; e < 8; ++e) ra[e] = buf_f64(abuf, aoff[e]);
   };
+  // FP64 -> FP32 -> S bfloat16 slices, two elements per v_cvt_pk_bf16_f32 (round to nearest even);
+  // each remainder r - bf16(r) is exact in FP32.
   auto store_a = [&](const double (&ra)[8], int buf) {
-    unsigned short sl[8][S];
+    f32x2 r[4];
 #pragma unroll
-    for (int e = 0; e < 8; ++e) split_f32_bf16<S>((float)ra[e], sl[e]);
+    for (int q = 0; q < 4; ++q) r[q] = f32x2{(float)ra[2 * q], (float)ra[2 * q + 1]};
 #pragma unroll
     for (int s = 0; s < S; ++s) {
-      uint4 v;
-      v.x = (unsigned)sl[0][s] | ((unsigned)sl[1][s] << 16);
-      v.y = (unsigned)sl[2][s] | ((unsigned)sl[3][s] << 16);
-      v.z = (unsigned)sl[4][s] | ((unsigned)sl[5][s] << 16);
-      v.w = (unsigned)sl[6][s] | ((unsigned)sl[7][s] << 16);
-      *reinterpret_cast<uint4*>(&As[buf][s][ai][ak * 8]) = v;
+      unsigned w[4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        w[q] = __builtin_bit_cast(unsigned, __builtin_convertvector(r[q], bf16x2));
+        if (s + 1 < S) {
+          r[q].x -= __uint_as_float(w[q] << 16);
+          r[q].y -= __uint_as_float(w[q] & 0xffff0000u);
+        }
+      }
+      *reinterpret_cast<uint4*>(&As[buf][s][ai][ak * 8]) = make_uint4(w[0], w[1], w[2], w[3]);
     }
   };
   // B fragments: lane holds k = 8 (lane / 16) .. + 7 of column wc + 16 b + lane % 16.
@@ -178,7 +174,7 @@ __global__ __launch_bounds__(NT, 1) void gemm_split_kernel(const double* __restr
     const int j = wc + 16 * b + (lane & 15);
     zoff[b] = (j < n) ? (uint32_t)(((int64_t)j * mp + 8 * (lane >> 4)) * 2) : kOOB;
   }
-  uint4 bcur[S][CB], bnxt[S][CB];
+  uint4 bf0[S][CB], bf1[S][CB], bf2[S][CB];
   auto load_b = [&](int k0, uint4 (&dst)[S][CB]) {
     // rows k0 .. k0 + 31 of every slice; past the padded end the buffer is empty (zeros)
     const bufrsrc zbuf = make_buf(zs + min((int64_t)k0, mp), k0 < mp ? (int64_t)(S * slice_stride - k0) * 2 : 0);
@@ -189,62 +185,71 @@ __global__ __launch_bounds__(NT, 1) void gemm_split_kernel(const double* __restr
         dst[s][b] = buf_b128(zbuf, zoff[b] == kOOB ? kOOB : zoff[b] + (uint32_t)(s * slice_stride * 2));
   };
 
-  // K steps, padded to a multiple of 3 (the register-stage rotation); steps past the end of K
-  // read clamped addresses and contribute zeros, so no load sits under a branch.
-  const int nsteps = ((m + BKS - 1) / BKS + 2) / 3 * 3;
-  int since_fold = 0;
-  // one K step: MFMAs on LDS buffer st & 1; A(st+1) (in ra_store) goes to the other buffer;
-  // A(st+3) is requested into ra_fill.
-  auto step = [&](int st, const double (&ra_store)[8], double (&ra_fill)[8]) {
+  // K steps, padded to a multiple of 6 (3 A register stages x 2 B fragment buffers); steps past the
+  // end of K read empty buffers and contribute zeros, so no load sits under a branch.
+  const int nsteps = ((m + BKS - 1) / BKS + 5) / 6 * 6;
+  // One K step, a single basic block: request B(st+2) and A(st+3); read the A fragments of buffer
+  // st & 1; convert A(st+1) into the other buffer while the MFMAs run; one barrier.  B is requested
+  // before A: memory counters retire in order, so the wait for B(st+1) at the next step must not
+  // also wait for the HBM loads of A issued after it.
+  auto step = [&](int st, const double (&ra_store)[8], double (&ra_fill)[8], const uint4 (&bu)[S][CB],
+                  uint4 (&bfill)[S][CB]) {
     const int cur = st & 1;
+    load_b((st + 2) * BKS, bfill);
     load_a(ra_fill, (st + 3) * BKS);
-    load_b((st + 1) * BKS, bnxt);
     const int kb = 8 * (lane >> 4);
+    bf16x8 af[S][4];
 #pragma unroll
-    for (int p = 0; p < S; ++p) {
-      bf16x8 af[4];
+    for (int p = 0; p < S; ++p)
 #pragma unroll
       for (int a = 0; a < 4; ++a)
-        af[a] = __builtin_bit_cast(bf16x8, *reinterpret_cast<const u16x8*>(&As[cur][p][a * 16 + (lane & 15)][kb]));
+        af[p][a] = __builtin_bit_cast(bf16x8, *reinterpret_cast<const u16x8*>(&As[cur][p][a * 16 + (lane & 15)][kb]));
+    store_a(ra_store, cur ^ 1);
+#pragma unroll
+    for (int p = 0; p < S; ++p)
 #pragma unroll
       for (int q = 0; q < S - p; ++q)
 #pragma unroll
         for (int a = 0; a < 4; ++a)
 #pragma unroll
           for (int b = 0; b < CB; ++b)
-            acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[a], __builtin_bit_cast(bf16x8, bcur[q][b]),
+            acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[p][a], __builtin_bit_cast(bf16x8, bu[q][b]),
                                                                 acc[a][b], 0, 0, 0);
+    // interleave: one MFMA, then a few VALU / LDS-write instructions of the conversion
+#pragma unroll
+    for (int i = 0; i < 4 * CB * S * (S + 1) / 2; ++i) {
+      __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
+      __builtin_amdgcn_sched_group_barrier(0x002, 3, 0);
+      __builtin_amdgcn_sched_group_barrier(0x200, 1, 0);
     }
-    since_fold += BKS;
-    if (since_fold == KT) {
-#pragma unroll
-      for (int a = 0; a < 4; ++a)
-#pragma unroll
-        for (int b = 0; b < CB; ++b) {
-#pragma unroll
-          for (int r = 0; r < 4; ++r) Dacc[wave][(a * CB + b) * 4 + r][lane] += (double)acc[a][b][r];
-          acc[a][b] = f32x4{0.f, 0.f, 0.f, 0.f};
-        }
-      since_fold = 0;
-    }
-    store_a(ra_store, cur ^ 1);
-#pragma unroll
-    for (int s2 = 0; s2 < S; ++s2)
-#pragma unroll
-      for (int b = 0; b < CB; ++b) bcur[s2][b] = bnxt[s2][b];
     __syncthreads();
   };
+  auto fold = [&]() {
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+      for (int b = 0; b < CB; ++b) {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) Dacc[wave][(a * CB + b) * 4 + r][lane] += (double)acc[a][b][r];
+        acc[a][b] = f32x4{0.f, 0.f, 0.f, 0.f};
+      }
+  };
 
+  load_b(0, bf0);
+  load_b(BKS, bf1);
   load_a(ra0, 0);
   load_a(ra1, BKS);
   load_a(ra2, 2 * BKS);
-  load_b(0, bcur);
   store_a(ra0, 0);
   __syncthreads();
-  for (int st = 0; st < nsteps; st += 3) {
-    step(st, ra1, ra0);
-    step(st + 1, ra2, ra1);
-    step(st + 2, ra0, ra2);
+  for (int st = 0; st < nsteps; st += 6) {
+    step(st + 0, ra1, ra0, bf0, bf2);
+    step(st + 1, ra2, ra1, bf1, bf0);
+    step(st + 2, ra0, ra2, bf2, bf1);
+    step(st + 3, ra1, ra0, bf0, bf2);
+    step(st + 4, ra2, ra1, bf1, bf0);
+    step(st + 5, ra0, ra2, bf2, bf1);
+    if ((st / 6) % 5 == 4) fold();      // FP32 accumulation over at most 30 steps (960 rows of K)
   }
 #pragma unroll
   for (int a = 0; a < 4; ++a)
