@@ -240,6 +240,61 @@ class KernelTimer:
         return self.total_ms / self.count if self.count else float("nan")
 
 
+class BatchPlan:
+    """Batched CholQR2-A (one persistent launch) over dense instances A_i (m_i x m_i, symmetric,
+    contiguous) and Z_i (m_i x n_i, column-major), storage float64 or float32, n_i <= 64.
+
+    Outputs Q_i (column-major, same dtype) and R_i (n_i x n_i) are allocated here; `run()` enqueues
+    the launch on the current stream and allocates nothing, so it can be captured in a graph."""
+
+    def __init__(self, As, Zs, tile: int = 0, shift_c: float = 1.0, max_retries: int = 3, q_in_place=False):
+        torch = _torch()
+        if len(As) != len(Zs) or not As:
+            raise ValueError("need as many A_i as Z_i, at least one")
+        dt = As[0].dtype
+        if dt not in (torch.float64, torch.float32):
+            raise ValueError("batch storage must be float64 or float32")
+        self.dtype = OQR_F64 if dt == torch.float64 else OQR_F32
+        self.device = As[0].device
+        self.As, self.Zs = list(As), [colmajor(z) for z in Zs]
+        items = (BatchItem * len(As))()
+        self.Qs, self.Rs = [], []
+        max_m = max_n = 1
+        for k, (a, z) in enumerate(zip(self.As, self.Zs)):
+            m, n = z.shape
+            if a.shape != (m, m) or a.dtype != dt or z.dtype != dt or not a.is_contiguous():
+                raise ValueError(f"instance {k}: shapes or dtypes do not match")
+            q = z if q_in_place else torch.empty(n, m, dtype=dt, device=self.device).t()
+            r = torch.empty(n, n, dtype=dt, device=self.device).t()
+            self.Qs.append(q)
+            self.Rs.append(r)
+            it = items[k]
+            it.a, it.z, it.q, it.r = a.data_ptr(), z.data_ptr(), q.data_ptr(), r.data_ptr()
+            it.lda, it.ldz, it.ldq, it.ldr = m, _ld(z), _ld(q), _ld(r)
+            it.m, it.n = m, n
+            max_m, max_n = max(max_m, m), max(max_n, n)
+        raw = bytes(items)
+        self.items = torch.frombuffer(bytearray(raw), dtype=torch.uint8).to(self.device)
+        self.batch, self.max_m, self.max_n, self.tile = len(As), max_m, max_n, int(tile)
+        self.opts = make_opts(shift_c=shift_c, max_retries=max_retries)
+        L = lib()
+        nbytes = L.oqr_batched_workspace_bytes(self.batch, max_m, max_n, self.dtype)
+        self.ws = torch.empty(max(int(nbytes), 256), dtype=torch.uint8, device=self.device)
+        self.info = torch.zeros(self.batch, dtype=torch.int32, device=self.device)
+
+    def run(self, stream=None, tile=None):
+        torch = _torch()
+        s = stream if stream is not None else torch.cuda.current_stream(self.device).cuda_stream
+        rc = lib().oqr_cholqr2_batched(self.batch, self.items.data_ptr(), self.dtype, self.max_m, self.max_n,
+                                       ctypes.byref(self.opts), self.tile if tile is None else int(tile),
+                                       self.ws.data_ptr(), self.ws.numel(), self.info.data_ptr(), s)
+        _raise(rc, "oqr_cholqr2_batched")
+
+
+def batch_tile_count() -> int:
+    return int(lib().oqr_batched_tile_count())
+
+
 def _run(alg, A, Z, **opts):
     Z = colmajor(Z)
     return Plan(alg, A, Z.shape[1], **opts)(Z)

@@ -21,11 +21,3 @@ int eig_a_run(const oqr_op*, const double*, int64_t, int64_t, int64_t, double*, 
 
 }  // namespace oqr
 
-extern "C" {
-size_t oqr_batched_workspace_bytes(int64_t, int32_t, int32_t, int32_t) { return 0; }
-int oqr_cholqr2_batched(int64_t, const oqr_batch_item*, int32_t, int32_t, int32_t, const oqr_opts*, int32_t, void*,
-                        size_t, int32_t*, void*) {
-  return OQR_E_UNSUPPORTED;
-}
-int oqr_batched_tile_count(void) { return 0; }
-}

@@ -1,0 +1,163 @@
+"""GPU parity of the batched CholQR2-A (one persistent launch) against the CPU oracle.
+
+Instances follow the batch workload's recipe (log-uniform m, n in {8, 16, 32, 64}, kappa(A)
+log-uniform, Gaussian Z, butterfly eigenvectors) at sizes the oracle finishes in seconds, plus
+ragged n.  FP64 storage: residual and orthogonality <= 1e-12 where u ||A|| ||Q||^2 allows it
+(the stable class), R forward error <= 10 n u kappa(R) against CHOL-EQR.  FP32 storage: the oracle
+runs on the FP32-rounded inputs widened to FP64; orthogonality <= max(1e-6, 10 u32 ||A|| ||Q||^2).
+"""
+import numpy as np
+import pytest
+
+import workloads as W
+from gpu_util import U, banner, to_host
+from oracle import metrics, reference, variants
+
+pytestmark = pytest.mark.gpu
+oqr = pytest.importorskip("paper_1401_5171_amd")
+torch = pytest.importorskip("torch")
+
+U32 = 2.0 ** -24
+
+
+def make_batch(count, m_lo=32, m_hi=600, n_set=(8, 16, 32, 64), k=(1e2, 1e6), extra_n=(), seed=7):
+    plan = W.batch_plan(count, m_lo, m_hi, n_set, k[0], k[1], cfg=50 + seed)
+    insts = []
+    for i, p in enumerate(plan):
+        n = p.n if i >= len(extra_n) else extra_n[i]
+        p = W.BatchInstance(p.index, max(p.m, n), n, p.kappa)
+        a, z = W.batch_instance(p, cfg=50 + seed)
+        insts.append((a, z))
+    return insts
+
+
+def upload(insts, dtype):
+    As = [torch.from_numpy(np.ascontiguousarray(a.astype(dtype))).cuda() for a, _ in insts]
+    Zs = [torch.from_numpy(np.ascontiguousarray(z.astype(dtype).T)).cuda().t() for _, z in insts]
+    return As, Zs
+
+
+def check_fp64(insts, plan):
+    info = to_host(plan.info)
+    assert np.all(info == 0), info
+    for k, (a, z) in enumerate(insts):
+        q, r = to_host(plan.Qs[k]), to_host(plan.Rs[k])
+        q0, r0 = reference.chol_eqr(a, z)
+        aq2 = metrics.diagnostics(a, z, q0, r0)["a_q2"]
+        n = z.shape[1]
+        assert metrics.residual_f(z, q, r) <= 1e-12, k
+        assert metrics.orth_loss(a, q) <= max(1e-12, 100 * U * aq2 * n), k
+        assert metrics.r_forward_error(r, r0) <= 10 * n * U * np.linalg.cond(r0) + 1e-15, k
+        assert np.all(np.tril(r, -1) == 0) and np.all(np.diag(r) > 0), k
+
+
+def test_batch_fp64_matches_oracle():
+    insts = make_batch(48, extra_n=(1, 3, 17, 33, 63, 64))
+    As, Zs = upload(insts, np.float64)
+    plan = oqr.BatchPlan(As, Zs)
+    banner("batch fp64 48 instances")
+    plan.run()
+    torch.cuda.synchronize()
+    check_fp64(insts, plan)
+
+
+@pytest.mark.parametrize("tile", [1, 2, 3, 4])
+def test_batch_every_tile_gives_the_same_bits(tile):
+    insts = make_batch(24, seed=8)
+    As, Zs = upload(insts, np.float64)
+    ref = oqr.BatchPlan(As, Zs, tile=0)
+    ref.run()
+    plan = oqr.BatchPlan(As, Zs, tile=tile)
+    banner(f"batch tile {tile}")
+    plan.run()
+    torch.cuda.synchronize()
+    for k in range(len(insts)):
+        assert torch.equal(plan.Qs[k], ref.Qs[k]) and torch.equal(plan.Rs[k], ref.Rs[k])
+
+
+def test_batch_fp32_storage():
+    insts = make_batch(24, seed=9, k=(1e2, 1e4))
+    As, Zs = upload(insts, np.float32)
+    plan = oqr.BatchPlan(As, Zs)
+    banner("batch fp32")
+    plan.run()
+    torch.cuda.synchronize()
+    assert np.all(to_host(plan.info) == 0)
+    for k, (a, z) in enumerate(insts):
+        a32 = a.astype(np.float32).astype(np.float64)     # the oracle sees the rounded inputs
+        z32 = z.astype(np.float32).astype(np.float64)
+        q, r = to_host(plan.Qs[k]).astype(np.float64), to_host(plan.Rs[k]).astype(np.float64)
+        q0, r0 = reference.chol_eqr(a32, z32)
+        aq2 = metrics.diagnostics(a32, z32, q0, r0)["a_q2"]
+        assert metrics.orth_loss(a32, q) <= max(1e-6, 10 * U32 * aq2), k
+        assert metrics.residual_f(z32, q, r) <= 1e-6, k
+        assert metrics.r_forward_error(r, r0) <= 1e-5 * max(1.0, np.linalg.cond(r0) * U32 * 1e3), k
+
+
+def test_batch_matches_per_instance_launches():
+    insts = make_batch(12, seed=10)
+    As, Zs = upload(insts, np.float64)
+    plan = oqr.BatchPlan(As, Zs)
+    plan.run()
+    banner("batch vs per-instance")
+    for k in range(len(insts)):
+        q1, r1 = oqr.cholqr2(As[k], Zs[k])
+        n = insts[k][1].shape[1]
+        kap = np.linalg.cond(to_host(r1))
+        assert metrics.r_forward_error(to_host(plan.Rs[k]), to_host(r1)) <= 10 * n * U * kap
+        assert np.abs(to_host(plan.Qs[k]) - to_host(q1)).max() <= 10 * n * U * kap * np.abs(to_host(q1)).max()
+
+
+def test_failing_instance_does_not_stop_the_batch():
+    insts = make_batch(10, seed=11)
+    m, n = 200, 5
+    d = np.ones(m)
+    d[1] = -1.0
+    bad_a = np.diag(d)
+    bad_z = np.zeros((m, n), order="F")
+    for j in range(n):
+        bad_z[j, j] = 1.0
+    insts[3] = (bad_a, bad_z)
+    As, Zs = upload(insts, np.float64)
+    plan = oqr.BatchPlan(As, Zs)
+    banner("batch with a failing instance")
+    plan.run()
+    torch.cuda.synchronize()
+    info = to_host(plan.info)
+    assert info[3] == variants.chol_info(bad_z.T @ bad_a @ bad_z)[1] == 2
+    good = [k for k in range(len(insts)) if k != 3]
+    assert np.all(info[good] == 0)
+    for k in good:
+        a, z = insts[k]
+        assert metrics.residual_f(z, to_host(plan.Qs[k]), to_host(plan.Rs[k])) <= 1e-12
+
+
+def test_graph_capture_replays_match_eager():
+    """The batched launch captured in a graph: several replays, with eager work and syncs between
+    them, each equal bit for bit to the eager result."""
+    insts = make_batch(16, seed=12)
+    As, Zs = upload(insts, np.float64)
+    plan = oqr.BatchPlan(As, Zs)
+    plan.run()                       # eager reference (also primes the device queries)
+    torch.cuda.synchronize()
+    eager_q = [q.clone() for q in plan.Qs]
+    eager_r = [r.clone() for r in plan.Rs]
+    g = torch.cuda.CUDAGraph()
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        plan.run()
+    torch.cuda.current_stream().wait_stream(s)
+    torch.cuda.synchronize()
+    with torch.cuda.graph(g, stream=s):
+        plan.run()
+    banner("graph replays")
+    for rep in range(4):
+        for q in plan.Qs:
+            q.zero_()
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        assert int(plan.info.sum().item()) == 0
+        for k in range(len(insts)):
+            assert torch.equal(plan.Qs[k], eager_q[k]) and torch.equal(plan.Rs[k], eager_r[k]), (rep, k)
