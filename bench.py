@@ -17,7 +17,11 @@ time taken from HIP events recorded around each launch inside the timed
 region.  The CPU baseline times the CPU oracle (CHOL-EQR, Algorithm 3) on the
 leading m' x m' sub-problem.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload dense32768|dense8192|stencil]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload dense32768|dense8192|stencil|batch]
+
+The batch workload (4096 independent instances, m log-uniform in [256, 4096], n in {8, 16, 32, 64},
+kappa(A_i) log-uniform in [1e2, 1e8], Gaussian Z_i) times one persistent launch of the batched
+FP64 CholQR2-A over all instances, beside the same factorisations launched one instance at a time.
 """
 import argparse
 import json
@@ -42,7 +46,10 @@ def parse():
     p.add_argument("--gpus", type=int, default=1)
     p.add_argument("--steps", type=int, default=10)
     p.add_argument("--warmup", type=int, default=3)
-    p.add_argument("--workload", default="dense32768", choices=["dense32768", "dense8192", "stencil"])
+    p.add_argument("--workload", default="dense32768", choices=["dense32768", "dense8192", "stencil", "batch"])
+    p.add_argument("--batch-count", type=int, default=4096)
+    p.add_argument("--batch-dtype", default="f64", choices=["f64", "f32"], help="storage type of the batch")
+    p.add_argument("--tile", type=int, default=-1, help="batched tile id (-1: time every id, keep the best)")
     p.add_argument("--pass1", default=None, help="precision of pass 1 of the mixed schedule")
     p.add_argument("--cpu-sample", type=int, default=8192, help="m' of the CPU oracle sample (0 = skip)")
     return p.parse_args()
@@ -135,6 +142,126 @@ def cpu_baseline(A, z, n, ms, torch):
             "sample": sample, "seconds": round(dt, 3)}
 
 
+def run_batch(args, torch, oqr):
+    """Batched FP64 CholQR2-A over the synthetic batch (see the module docstring)."""
+    import numpy as np
+    import workloads as W
+    dev = torch.device("cuda", 0)
+    dt = torch.float64 if args.batch_dtype == "f64" else torch.float32
+    sizes = W.batch_plan(args.batch_count)
+    t = time.time()
+    As, Zs = [], []
+    for k, p in enumerate(sizes):
+        a, z = W.batch_instance_device(p, dev, dt)
+        As.append(a)
+        Zs.append(z)
+        if (k + 1) % 512 == 0:
+            log(f"generated {k + 1}/{len(sizes)} instances ({time.time() - t:.1f}s)")
+    torch.cuda.synchronize()
+    ms = np.array([p.m for p in sizes], dtype=np.float64)
+    ns = np.array([p.n for p in sizes], dtype=np.float64)
+    flops = float(np.sum(2 * ms * ms * ns + 2 * ms * ns * ns))                  # paper normalisation
+    alg_flops = float(np.sum(2 * (2 * ms * ms * ns + 2 * ms * ns * ns + ns ** 3 / 3)))   # two passes executed
+    esize = 8 if dt == torch.float64 else 4
+    alg_bytes = float(np.sum(2 * (esize * ms * (ms + 1) / 2 + 3 * esize * ms * ns)))  # unique A + Z, Z, Q per pass
+    log(f"batch: {len(sizes)} instances, sum A = {np.sum(ms * ms) * esize / 1e9:.1f} GB, {flops:.3e} flops")
+    bp = oqr.BatchPlan(As, Zs)
+    tiles = list(range(1, oqr.batch_tile_count() + 1)) if args.tile < 0 else [args.tile]
+    tile_ms = {}
+    for tl in tiles:
+        bp.run(tile=tl)
+        torch.cuda.synchronize()
+        with oqr.KernelTimer("batch") as kt:
+            for _ in range(3):
+                bp.run(tile=tl)
+            torch.cuda.synchronize()
+        tile_ms[tl] = kt.avg_ms
+        log(f"tile {tl}: {kt.avg_ms:.3f} ms per batched launch")
+    best = min(tile_ms, key=tile_ms.get)
+    bp.tile = best
+    for _ in range(args.warmup):
+        bp.run()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    with oqr.KernelTimer("batch") as kt:
+        for _ in range(args.steps):
+            bp.run()
+        torch.cuda.synchronize()
+    step = (time.perf_counter() - t0) / args.steps
+    info = bp.info.cpu().numpy()
+    if np.any(info != 0):
+        raise RuntimeError(f"numerical failure in {int(np.sum(info != 0))} instances")
+    # accuracy on a stratified sample (every 64th instance), computed on the device in FP64
+    worst_o = worst_r = 0.0
+    for k in range(0, len(sizes), 64):
+        a, z, q, r = (x.double() for x in (As[k], Zs[k], bp.Qs[k], bp.Rs[k]))
+        o, rr = oqr.check(a, z, q, r)
+        worst_o, worst_r = max(worst_o, o), max(worst_r, rr)
+    line_extra = {}
+    if dt == torch.float64:
+        # the same factorisations, one instance per call (each call launches its own kernels)
+        plans = [oqr.Plan("cholqr2", As[k], sizes[k].n) for k in range(len(sizes))]
+        outs = [(torch.empty(p.n, p.m, dtype=dt, device=dev).t(), torch.empty(p.n, p.n, dtype=dt, device=dev).t())
+                for p in sizes]
+        for k, pl in enumerate(plans):
+            pl.run(Zs[k], *outs[k])
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for k, pl in enumerate(plans):
+            pl.run(Zs[k], *outs[k])
+        torch.cuda.synchronize()
+        per = time.perf_counter() - t0
+        line_extra["per_instance_launches"] = {"ms_per_step": round(per * 1e3, 3),
+                                               "value": round(flops / per / 1e9, 2),
+                                               "batched_speedup": round(per / step, 3)}
+        log(f"per-instance launches: {per * 1e3:.2f} ms")
+        del plans, outs
+    kms = kt.avg_ms
+    roof = {"bound": "mfma", "kernel": f"batch_kernel<{'double' if esize == 8 else 'float'}> (tile {best})",
+            "achieved": round(alg_flops / (kms * 1e-3) / 1e12, 3), "peak": 78.6, "unit": "TFLOP/s",
+            "frac": round(alg_flops / (kms * 1e-3) / PEAK["fp64"], 4), "traffic": None,
+            "per_launch_flops": alg_flops, "avg_launch_ms": round(kms, 4),
+            "hbm_achieved_GBs": round(alg_bytes / (kms * 1e-3) / 1e9, 1), "per_launch_unique_bytes": alg_bytes}
+    line = {
+        "metric": METRIC, "value": round(flops / step / 1e9, 2), "unit": "GFLOP/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(step * 1e3, 4),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64" if esize == 8 else "f32+f64",
+        "data": "synthetic",
+        "config": {"workload": f"batch of {len(sizes)} CholQR2-A instances, m in [256, 4096] log-uniform, "
+                               f"n in {{8,16,32,64}}, kappa(A) in [1e2, 1e8], {args.batch_dtype} storage",
+                   "count": len(sizes), "flops_per_step": flops, "flop_count": "sum of 2m^2n+2mn^2"},
+        "orth_loss_fro_max_sampled": worst_o, "residual_fro_max_sampled": worst_r,
+        "tile_ms": {str(k): round(v, 4) for k, v in tile_ms.items()},
+        "roofline": roof, "cpu_baseline": None,
+    }
+    line.update(line_extra)
+    if args.cpu_sample:
+        line["cpu_baseline"] = cpu_baseline_batch(As, Zs, sizes, budget_s=12.0)
+    print(json.dumps(line), flush=True)
+
+
+def cpu_baseline_batch(As, Zs, sizes, budget_s):
+    """CPU oracle (CHOL-EQR) on instances taken every 16th through the batch until the budget is spent."""
+    import numpy as np
+    from threadpoolctl import threadpool_info
+    from oracle import reference
+    f = dt = 0.0
+    done = 0
+    for k in range(0, len(sizes), 16):
+        a = As[k].double().cpu().numpy()
+        z = np.asfortranarray(Zs[k].double().cpu().numpy())
+        t = time.perf_counter()
+        reference.chol_eqr(a, z)
+        dt += time.perf_counter() - t
+        f += 2.0 * a.shape[0] ** 2 * z.shape[1] + 2.0 * a.shape[0] * z.shape[1] ** 2
+        done += 1
+        if dt > budget_s:
+            break
+    threads = max([i.get("num_threads", 1) for i in threadpool_info()] + [1])
+    return {"value": round(f / dt / 1e9, 3), "unit": "GFLOP/s", "cores": int(threads), "kind": "oracle",
+            "sample": f"chol_eqr on {done} instances (every 16th of the batch)", "seconds": round(dt, 3)}
+
+
 def main():
     args = parse()
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -149,6 +276,8 @@ def main():
         sys.exit(2)
     oqr.lib()   # fail loudly if the library is missing
     torch.cuda.set_device(0)
+    if args.workload == "batch":
+        return run_batch(args, torch, oqr)
     A, Z, z_host, m, n, desc, flops, dom_kernel, dom_flops = make_inputs(args.workload, torch)
     dense = not hasattr(A, "nx")
     pass1 = args.pass1 or ("bf16x3")

@@ -210,7 +210,7 @@ int oqr_batched_tile_count(void);
 
 /* Timing aid: from oqr_trace_start(name) until oqr_trace_stop, every launch
  * of the named kernel ("gemm_f64", "gemm_split", "gram", "chol", "trsm",
- * "stencil", "split_z") made by this process is bracketed by a pair of HIP
+ * "stencil", "split_z", "batch") made by this process is bracketed by a pair of HIP
  * events recorded on its stream (events are created on first use and reused).
  * oqr_trace_stop waits for the recorded events and returns the summed kernel
  * time in milliseconds and the number of launches.  Not thread-safe; do not

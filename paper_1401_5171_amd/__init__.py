@@ -155,11 +155,21 @@ def make_op(A) -> Tuple[_Op, int]:
     torch = _torch()
     if A.dim() != 2 or A.shape[0] != A.shape[1]:
         raise ValueError("A must be square")
-    if A.dtype != torch.float64 or not A.is_cuda or not A.is_contiguous():
-        raise ValueError("A must be a contiguous float64 CUDA tensor")
+    if A.dtype != torch.float64 or not A.is_cuda:
+        raise ValueError("A must be a float64 CUDA tensor")
+    m = A.shape[0]
+    # symmetric: rows of a row-major view are columns; either unit stride gives a column-major lda
+    if A.stride(1) == 1 and A.stride(0) >= m:
+        lda = A.stride(0)
+    elif A.stride(0) == 1 and A.stride(1) >= m:
+        lda = A.stride(1)
+    elif m <= 1:
+        lda = 1
+    else:
+        raise ValueError("A must have one unit stride and a leading dimension >= m")
     op.kind, op.dtype = OQR_OP_DENSE, OQR_F64
-    op.a, op.lda = A.data_ptr(), A.shape[0]
-    return op, A.shape[0]
+    op.a, op.lda = A.data_ptr(), lda
+    return op, m
 
 
 def make_opts(pass1="fp64", pass2="fp64", shift_c=1.0, max_retries=3, gs_variant="cgs") -> _Opts:

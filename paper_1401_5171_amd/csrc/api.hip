@@ -20,8 +20,8 @@ struct TraceState {
 };
 TraceState g_trace;
 
-const char* const kKernelNames[] = {"", "gemm_f64", "gemm_split", "gram", "chol", "trsm", "stencil", "split_z"};
-constexpr int kNumKernels = 8;
+const char* const kKernelNames[] = {"", "gemm_f64", "gemm_split", "gram", "chol", "trsm", "stencil", "split_z", "batch"};
+constexpr int kNumKernels = 9;
 }  // namespace
 
 void trace_pre(int kid, hipStream_t s) {

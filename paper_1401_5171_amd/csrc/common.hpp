@@ -83,7 +83,8 @@ __host__ __device__ inline int64_t split_ld(int64_t m) { return (m + 31) & ~(int
 inline size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 // Kernel ids for oqr_trace_start (names in api.hip).
-enum KernelId { K_GEMM_F64 = 1, K_GEMM_SPLIT = 2, K_GRAM = 3, K_CHOL = 4, K_TRSM = 5, K_STENCIL = 6, K_SPLIT_Z = 7 };
+enum KernelId { K_GEMM_F64 = 1, K_GEMM_SPLIT = 2, K_GRAM = 3, K_CHOL = 4, K_TRSM = 5, K_STENCIL = 6, K_SPLIT_Z = 7,
+               K_BATCH = 8 };
 void trace_pre(int kid, hipStream_t s);
 void trace_post(int kid, hipStream_t s);
 

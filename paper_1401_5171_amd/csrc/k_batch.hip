@@ -378,13 +378,16 @@ int oqr_cholqr2_batched(int64_t batch, const oqr_batch_item* items_dev, int32_t 
   }
   int64_t grid = (int64_t)cus * cfg.wg_per_cu;
   if (grid > batch) grid = batch;
+  trace_pre(K_BATCH, s);
   if (dtype == OQR_F64)
     batch_kernel<double><<<(unsigned)grid, NT, 0, s>>>(items_dev, order, (int)batch, counter, info_dev, o.shift_c,
                                                        o.max_retries);
   else
     batch_kernel<float><<<(unsigned)grid, NT, 0, s>>>(items_dev, order, (int)batch, counter, info_dev, o.shift_c,
                                                       o.max_retries);
-  return hipGetLastError() == hipSuccess ? OQR_OK : OQR_E_HIP;
+  const hipError_t e = hipGetLastError();
+  trace_post(K_BATCH, s);
+  return e == hipSuccess ? OQR_OK : OQR_E_HIP;
 }
 
 }  // extern "C"

@@ -4,36 +4,75 @@
 // |dR^i| <= c n u |R| gives the residual bound of Theorem 2.1.  Column blocks
 // of 32 are processed left to right:
 //   (1) Z_J -= Q_{<J} R_{<J,J}    FP64 MFMA (a blocked form of the same sums)
-//   (2) Q_J  = Z_J R_JJ^{-1}       substitution, k ascending, 4 lanes per row
-// A workgroup owns 64 rows x all n columns, staged once in LDS (Z is read
-// from HBM once and Q written once).  Q may alias Z: the whole row block of Z
-// is in LDS before any of its Q columns is written.
+//   (2) Q_J  = Z_J R_JJ^{-1}       substitution, k ascending, 4 lanes per row;
+//       the pivot is applied as a product with 1/r_kk (computed once per
+//       workgroup), which perturbs r_kk by one more rounding and keeps the
+//       componentwise backward error bound.
+// A workgroup owns BMR rows x all n columns, staged once in LDS (Z is read
+// from HBM once and Q written once, column-coalesced, at the end); BMR = 64
+// for n <= 128 and 32 above, so that two workgroups fit in one CU's LDS.  Q may
+// alias Z: the whole row block of Z is in LDS before any of its Q is written.
 #include "common.hpp"
 
 namespace oqr {
 namespace {
 
-constexpr int BM = 64;
 constexpr int JB = 32;
 constexpr int NT = 256;
-constexpr int LDQ = BM + 1;   // LDS column stride (doubles)
 
-template <int NMAX>
-__global__ __launch_bounds__(NT) void trsm_kernel(const double* Z, int64_t ldz, const double* __restrict__ R,
-                                                  int64_t ldr, double* Q, int64_t ldq, int m, int n,
-                                                  const int32_t* __restrict__ info) {
+// Broadcast lane O of every group of four lanes to the whole group (DPP quad_perm).
+template <int O>
+__device__ __forceinline__ double quad_bcast(double v) {
+  constexpr int ctrl = O | (O << 2) | (O << 4) | (O << 6);
+  const long long b = __builtin_bit_cast(long long, v);
+  const int lo = __builtin_amdgcn_mov_dpp((int)(b & 0xffffffffll), ctrl, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_mov_dpp((int)(b >> 32), ctrl, 0xF, 0xF, false);
+  return __builtin_bit_cast(double, ((long long)hi << 32) | (unsigned int)lo);
+}
+__device__ __forceinline__ double quad_bcast(double v, int o) {
+  switch (o) {
+    case 0: return quad_bcast<0>(v);
+    case 1: return quad_bcast<1>(v);
+    case 2: return quad_bcast<2>(v);
+    default: return quad_bcast<3>(v);
+  }
+}
+
+template <int NMAX, int BMR>
+__global__ __launch_bounds__(NT, 2) void trsm_kernel(const double* Z, int64_t ldz, const double* __restrict__ R,
+                                                     int64_t ldr, double* Q, int64_t ldq, int m, int n,
+                                                     const int32_t* __restrict__ info) {
+  constexpr int LDQ = BMR + 1;               // LDS column stride (doubles)
   __shared__ double Qs[NMAX * LDQ];          // Qs[j * LDQ + i]: row i of the block, column j
-  __shared__ double RJ[JB][JB + 1];          // diagonal block of R
+  // strictly upper part of R_JJ, per column owner: RZ[c][sub * 8 + e] = R(j0 + c, j0 + sub + 4e)
+  // for sub + 4e > c, else 0; rinv[c] = 1 / R(j0 + c, j0 + c).  Staged at the start of block J,
+  // after the barrier that ends the previous block's substitution (its last reader).
+  __shared__ __attribute__((aligned(16))) double RZ[JB][JB];
+  __shared__ double rinv[JB];
   if (info[0] != 0) return;
   const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
-  const int i0 = blockIdx.x * BM;
+  const int i0 = blockIdx.x * BMR;
   const int nblk = (n + JB - 1) / JB;
 
-  // load the Z row block (column-major: 64 contiguous rows per column), 16 loads in flight per thread
+  auto stage_r = [&](int J) {
+    const int j0 = J * JB;
+    for (int idx = t; idx < JB * JB; idx += NT) {
+      const int c = idx / JB, q = idx % JB, sub = q >> 3, e = q & 7;
+      const int col = sub + 4 * e;
+      const int gr = j0 + c, gc = j0 + col;
+      RZ[c][q] = (col > c && gc < n) ? R[(int64_t)gc * ldr + gr] : 0.0;
+    }
+    if (t < JB) {
+      const int g = j0 + t;
+      rinv[t] = (g < n) ? 1.0 / R[(int64_t)g * ldr + g] : 1.0;
+    }
+  };
+
+  // load the Z row block (column-major: BMR contiguous rows per column), 16 loads in flight per thread
   {
-    const int i = t % BM, jq = t / BM;
+    constexpr int STRIDE = NT / BMR;
+    const int i = t % BMR, jq = t / BMR;
     const bool ok = i0 + i < m;
-    constexpr int STRIDE = NT / BM;
 #pragma unroll
     for (int jb = 0; jb < NMAX; jb += 16 * STRIDE) {
       double v[16];
@@ -46,91 +85,93 @@ __global__ __launch_bounds__(NT) void trsm_kernel(const double* Z, int64_t ldz, 
       for (int u = 0; u < 16; ++u) Qs[(jb + jq + STRIDE * u) * LDQ + i] = v[u];
     }
   }
+  __syncthreads();
+
+  const int li = lane >> 4, lj = lane & 15;
+  // MFMA tiles of the update: BMR = 64: wave = 16-row block, both 16-column halves;
+  //                           BMR = 32: wave = (16-row block, half)
+  constexpr int NH = (BMR == 64) ? 2 : 1;
+  const int rb = (BMR == 64) ? wave : (wave >> 1);
+  const int h0 = (BMR == 64) ? 0 : (wave & 1);
   const int row = t >> 2, sub = t & 3;      // substitution: 4 lanes per row
   for (int J = 0; J < nblk; ++J) {
     const int j0 = J * JB;
-    // stage R_JJ (upper 32x32; identity beyond n)
-    for (int idx = t; idx < JB * JB; idx += NT) {
-      const int p = idx % JB, c = idx / JB;
-      const int gp = j0 + p, gc = j0 + c;
-      double v;
-      if (gp < n && gc < n) v = (p <= c) ? R[(int64_t)gc * ldr + gp] : 0.0;
-      else v = (p == c) ? 1.0 : 0.0;
-      RJ[p][c] = v;
-    }
-    __syncthreads();
-    // (1) block update on MFMA: wave w owns rows 16w..16w+15, two 16-column halves
+    stage_r(J);
+    // (1) block update on MFMA
     if (J > 0) {
-      f64x4 acc[2];
+      f64x4 acc[NH];
 #pragma unroll
-      for (int h = 0; h < 2; ++h)
+      for (int h = 0; h < NH; ++h)
 #pragma unroll
-        for (int r = 0; r < 4; ++r) acc[h][r] = Qs[(j0 + 16 * h + (lane & 15)) * LDQ + wave * 16 + 4 * r + (lane >> 4)];
-      const int jc0 = j0 + (lane & 15), jc1 = j0 + 16 + (lane & 15);
-      const double* R0 = R + (int64_t)min(jc0, n - 1) * ldr + (lane >> 4);
-      const double* R1 = R + (int64_t)min(jc1, n - 1) * ldr + (lane >> 4);
-      const bool ok0 = jc0 < n, ok1 = jc1 < n;
-      // R fragments are read from L2 in chunks of 32 k (8 MFMA steps), one chunk ahead
-      double b0[8], b1[8];
+        for (int r = 0; r < 4; ++r) acc[h][r] = Qs[(j0 + 16 * (h0 + h) + lj) * LDQ + rb * 16 + 4 * r + li];
+      const double* Rc[NH];
+      bool okc[NH];
 #pragma unroll
-      for (int s = 0; s < 8; ++s) {
-        b0[s] = sel_load(R0, 4 * s, ok0);
-        b1[s] = sel_load(R1, 4 * s, ok1);
+      for (int h = 0; h < NH; ++h) {
+        const int jc = j0 + 16 * (h0 + h) + lj;
+        okc[h] = jc < n;
+        Rc[h] = R + (int64_t)min(jc, n - 1) * ldr + li;
       }
+      // R fragments are read from L2 in chunks of 32 k (8 MFMA steps), one chunk ahead
+      double bf[NH][8];
+#pragma unroll
+      for (int h = 0; h < NH; ++h)
+#pragma unroll
+        for (int s = 0; s < 8; ++s) bf[h][s] = sel_load(Rc[h], 4 * s, okc[h]);
       for (int kc = 0; kc < j0; kc += 32) {
-        double nb0[8], nb1[8];
+        double nb[NH][8];
         const bool more = kc + 32 < j0;
 #pragma unroll
-        for (int s = 0; s < 8; ++s) {
-          nb0[s] = sel_load(R0, kc + 32 + 4 * s, more && ok0);
-          nb1[s] = sel_load(R1, kc + 32 + 4 * s, more && ok1);
-        }
+        for (int h = 0; h < NH; ++h)
+#pragma unroll
+          for (int s = 0; s < 8; ++s) nb[h][s] = sel_load(Rc[h], kc + 32 + 4 * s, more && okc[h]);
 #pragma unroll
         for (int s = 0; s < 8; ++s) {
-          const int kr = kc + 4 * s + (lane >> 4);
-          const double a = -Qs[kr * LDQ + wave * 16 + (lane & 15)];
-          acc[0] = mfma_f64(a, b0[s], acc[0]);
-          acc[1] = mfma_f64(a, b1[s], acc[1]);
+          const int kr = kc + 4 * s + li;
+          const double a = -Qs[kr * LDQ + rb * 16 + lj];
+#pragma unroll
+          for (int h = 0; h < NH; ++h) acc[h] = mfma_f64(a, bf[h][s], acc[h]);
         }
 #pragma unroll
-        for (int s = 0; s < 8; ++s) {
-          b0[s] = nb0[s];
-          b1[s] = nb1[s];
-        }
+        for (int h = 0; h < NH; ++h)
+#pragma unroll
+          for (int s = 0; s < 8; ++s) bf[h][s] = nb[h][s];
       }
-      __syncthreads();
+      // columns j0.. are written, columns < j0 were read: disjoint, no barrier in between
 #pragma unroll
-      for (int h = 0; h < 2; ++h)
+      for (int h = 0; h < NH; ++h)
 #pragma unroll
-        for (int r = 0; r < 4; ++r) Qs[(j0 + 16 * h + (lane & 15)) * LDQ + wave * 16 + 4 * r + (lane >> 4)] = acc[h][r];
-      __syncthreads();
+        for (int r = 0; r < 4; ++r) Qs[(j0 + 16 * (h0 + h) + lj) * LDQ + rb * 16 + 4 * r + li] = acc[h][r];
     }
+    __syncthreads();
     // (2) substitution on the 32 columns of the block: lane `sub` of a row owns columns sub + 4e
-    {
+    if (row < BMR) {
       double x[8];
 #pragma unroll
       for (int e = 0; e < 8; ++e) x[e] = Qs[(j0 + sub + 4 * e) * LDQ + row];
 #pragma unroll
       for (int c = 0; c < JB; ++c) {
         const int owner = c & 3, ec = c >> 2;
-        // branch-free: every lane divides, the owner's quotient is broadcast
-        const double qo = x[ec] / RJ[c][c];
-        const double q = __shfl(qo, (lane & ~3) | owner);
-        if (sub == owner) x[ec] = q;
+        const double q = quad_bcast(x[ec] * rinv[c], owner);
+        const double* rz = &RZ[c][sub * 8];
+        // columns sub + 4e <= c are final: e below (c - 3) / 4 is skipped for every lane
 #pragma unroll
-        for (int e = 0; e < 8; ++e) {
-          const double upd = x[e] - q * RJ[c][sub + 4 * e];
-          x[e] = (sub + 4 * e > c) ? upd : x[e];
-        }
+        for (int e = 0; e < 8; ++e)
+          if (4 * e + 3 > c) x[e] = __builtin_fma(-q, rz[e], x[e]);
+        x[ec] = (sub == owner) ? q : x[ec];
       }
 #pragma unroll
-      for (int e = 0; e < 8; ++e) {
-        const int j = j0 + sub + 4 * e;
-        Qs[j * LDQ + row] = x[e];
-        if (i0 + row < m && j < n) Q[(int64_t)j * ldq + i0 + row] = x[e];
-      }
+      for (int e = 0; e < 8; ++e) Qs[(j0 + sub + 4 * e) * LDQ + row] = x[e];
     }
     __syncthreads();
+  }
+  // store Q: column-major, BMR contiguous rows per column
+  {
+    constexpr int STRIDE = NT / BMR;
+    const int i = t % BMR, jq = t / BMR;
+    if (i0 + i < m) {
+      for (int j = jq; j < n; j += STRIDE) Q[(int64_t)j * ldq + i0 + i] = Qs[j * LDQ + i];
+    }
   }
 }
 
@@ -160,13 +201,12 @@ __global__ void stencil_apply_kernel(const double* __restrict__ Z, int64_t ldz, 
 
 hipError_t launch_trsm(const double* Z, int64_t ldz, const double* R, int64_t ldr, double* Q, int64_t ldq,
                        int64_t m, int64_t n, const int32_t* info, hipStream_t s) {
-  const int grid = ceil_div(m, BM);
   if (n <= 64)
-    trsm_kernel<64><<<grid, NT, 0, s>>>(Z, ldz, R, ldr, Q, ldq, (int)m, (int)n, info);
+    trsm_kernel<64, 64><<<ceil_div(m, 64), NT, 0, s>>>(Z, ldz, R, ldr, Q, ldq, (int)m, (int)n, info);
   else if (n <= 128)
-    trsm_kernel<128><<<grid, NT, 0, s>>>(Z, ldz, R, ldr, Q, ldq, (int)m, (int)n, info);
+    trsm_kernel<128, 64><<<ceil_div(m, 64), NT, 0, s>>>(Z, ldz, R, ldr, Q, ldq, (int)m, (int)n, info);
   else
-    trsm_kernel<256><<<grid, NT, 0, s>>>(Z, ldz, R, ldr, Q, ldq, (int)m, (int)n, info);
+    trsm_kernel<256, 32><<<ceil_div(m, 32), NT, 0, s>>>(Z, ldz, R, ldr, Q, ldq, (int)m, (int)n, info);
   return hipGetLastError();
 }
 

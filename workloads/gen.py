@@ -31,7 +31,7 @@ __all__ = [
     "BASE_SEED", "rng_for", "logspace_to", "haar", "Butterfly", "butterfly",
     "spd_from_eigs", "spd_from_eigs_torch", "dense_spd", "dense_spd_device", "tall_skinny", "gaussian_scaled",
     "paper_case", "Stencil7", "laplacian7", "BatchInstance", "batch_plan",
-    "batch_instance", "CONFIGS",
+    "batch_instance", "batch_instance_device", "CONFIGS",
 ]
 
 
@@ -288,6 +288,19 @@ def batch_instance(inst: BatchInstance, dtype=np.float64, cfg: int = 5, block: i
     a = spd_from_eigs(v, logspace_to(inst.m, inst.kappa))
     z = np.asfortranarray(rng.standard_normal((inst.n, inst.m)).T)
     return a.astype(dtype), z.astype(dtype)
+
+
+def batch_instance_device(inst: BatchInstance, device, dtype=None, cfg: int = 5, block: int = 64):
+    """`batch_instance` built with torch on `device`: A_i (m x m, contiguous, exactly symmetric) and
+    Z_i as a column-major (m x n) view.  Same random draws as `batch_instance`; the products that
+    form A_i round differently."""
+    import torch
+    dtype = dtype or torch.float64
+    rng = rng_for(cfg, inst.index + 1)
+    v = butterfly(rng, inst.m, block=block)
+    a = spd_from_eigs_torch(v, logspace_to(inst.m, inst.kappa), device)
+    z = torch.as_tensor(rng.standard_normal((inst.n, inst.m)), device=device)
+    return a.to(dtype), z.to(dtype).t()
 
 
 # The five workloads (sizes and spectra); generators above turn them into arrays.
