@@ -20,8 +20,8 @@ namespace {
 
 constexpr int NT = 256;
 constexpr int NB = 64;        // max n
-constexpr int BR = 64;        // rows of A per block
-constexpr int BK = 16;        // K step of the A X product
+constexpr int BR = 128;       // rows of A per row block
+constexpr int BK = 32;        // K step of the A X product
 constexpr int LD = NB + 1;
 
 constexpr double U64 = 1.1102230246251565e-16;
@@ -32,87 +32,194 @@ __device__ __forceinline__ double ldv(const T* p, int64_t i, bool ok) {
   return ok ? (double)v : 0.0;
 }
 
+// Values the whole workgroup shares, moved to scalar registers (a non-inlined callee receives them in
+// vector registers; buffer resources must be scalar).
+__device__ __forceinline__ int uni(int v) { return __builtin_amdgcn_readfirstlane(v); }
+__device__ __forceinline__ int64_t uni(int64_t v) {
+  const int lo = __builtin_amdgcn_readfirstlane((int)(v & 0xffffffff));
+  const int hi = __builtin_amdgcn_readfirstlane((int)(v >> 32));
+  return ((int64_t)hi << 32) | (uint32_t)lo;
+}
+template <class P>
+__device__ __forceinline__ P* uni(P* p) { return (P*)(uintptr_t)uni((int64_t)(uintptr_t)p); }
+
+// Bounds-checked buffer load of one element (offset in elements; kOOB or beyond the range gives 0).
+// The raw bits are returned so that nothing consumes the value before it is needed.
+template <class T> struct Raw;
+template <> struct Raw<double> {
+  typedef double type;
+  static __device__ __forceinline__ double load(bufrsrc r, uint32_t e) {
+    return buf_f64(r, e == kOOB ? kOOB : e * 8u);
+  }
+};
+template <> struct Raw<float> {
+  typedef float type;
+  static __device__ __forceinline__ float load(bufrsrc r, uint32_t e) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, (int)(e == kOOB ? kOOB : e * 4u), 0, 0));
+  }
+};
+
 struct Tiles {
-  double As[BK][BR + 1];      // A tile: As[k][i]
+  double As[BK][BR + 1];      // A tile: As[k][i] (odd stride: conflict-free MFMA operand reads)
   double Xs[BK][LD];          // X tile: Xs[k][j]
+};
+struct Fact {
+  double Gs[NB][LD];          // Gram, then the factor R (upper)
+  double Ws[NB][LD];          // R1 at the end of pass 2
 };
 struct Smem {
   union {
-    Tiles tl;                 // during the K loop of W_b = A_b X
-    double Ws[BR][LD];        // W_b (rows of the block x columns); R1 at the end
+    Tiles tl;                 // streaming phase of G = X^T A X
+    double red[3][4][4][64];  // partial G of waves in row groups > 0
+    Fact f;                   // Cholesky, substitution, R = R2 R1
   };
-  double Gs[NB][LD];          // Gram, then the factor R (upper)
   double diag[NB];
   int idx;
   int fail;
   double dmax;
 };
 
-// One CHOLQR pass on instance (A, X) in place: X <- X R^{-1}, R into smem Gs (upper, zero lower).
-// Returns 0 or the failing pivot (1-based).
-template <class T>
-__device__ int cholqr_pass_wg(const T* A, int64_t lda, const T* Xin, int64_t ldxin, T* X, int64_t ldx, int m,
-                              int n, double unit, double c_first, double c_retry, int max_retries, Smem& S) {
+// G = X^T A X for one instance, streaming A once by row blocks of BR rows:
+//   W_b = A_b X (MFMA, W_b in registers), then G += X_b^T W_b with W_b's accumulators used directly as
+//   the B operand (the FP64 MFMA's D layout is its B layout, one K step per accumulator element).
+// Wave w owns the 16 columns cb = w % CLS of W and G and the row group rg = w / CLS of each row block
+// (RG = 4 / CLS groups of 16 * RBW rows).  On return, waves of row group 0 hold G(:, 16 cb ..) in g.
+template <class T, int CLS>
+__device__ __noinline__ void gram_phase(const T* A_, int64_t lda_, const T* X_, int64_t ldx_, int m_, int n_, Smem& S,
+                                        f64x4 (&g)[4]) {
+  const T* A = uni(A_);
+  const T* X = uni(X_);
+  const int64_t lda = uni(lda_), ldx = uni(ldx_);
+  const int m = uni(m_), n = uni(n_);
+  constexpr int RG = 4 / CLS, RBW = BR / 16 / RG;
   const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
   const int li = lane >> 4, lj = lane & 15;
-  const int nbk = (n + 15) / 16;              // 16-column blocks of n
-  // ---- G = X^T A X ----------------------------------------------------------------------------
-  f64x4 g[4];                                 // wave owns G rows 16 wave .. + 15, column blocks 0..3
+  const int cb = wave % CLS, rg = wave / CLS;
+  const int nbk = (n + 15) / 16;
+  const bool active = cb < nbk;               // wave-uniform
 #pragma unroll
   for (int b = 0; b < 4; ++b) g[b] = f64x4{0, 0, 0, 0};
+  // tile loads: A 16 values per thread (row t % BR, k = t / BR + 2q), X 8 values (k = t % BK, col t / BK + 8q),
+  // unconditional buffer loads (elements outside the matrix read as 0), consumed only at the next LDS store
+  const int ai = t % BR, ak = t / BR;
+  const int xk = t % BK, xj = t / BK;
+  typedef typename Raw<T>::type RT;
+  const bufrsrc abuf = make_buf(A, ((int64_t)(m - 1) * lda + m) * (int64_t)sizeof(T));
+  const bufrsrc xbuf = make_buf(X, ((int64_t)(n - 1) * ldx + m) * (int64_t)sizeof(T));
+  RT ra[BR * BK / NT], rx[BK * NB / NT];
   for (int r0 = 0; r0 < m; r0 += BR) {
-    f64x4 w[4];                               // wave owns W_b rows 16 wave .. + 15
-#pragma unroll
-    for (int b = 0; b < 4; ++b) w[b] = f64x4{0, 0, 0, 0};
-    for (int k0 = 0; k0 < m; k0 += BK) {
-      // A tile: rows r0..r0+63, columns k0..k0+15 (column-major: contiguous rows)
+    auto load = [&](int k0) {
+      const bool rok = r0 + ai < m;
 #pragma unroll
       for (int q = 0; q < BR * BK / NT; ++q) {
-        const int e = t + NT * q, i = e % BR, k = e / BR;
-        S.tl.As[k][i] = ldv(A, (int64_t)(k0 + k) * lda + r0 + i, r0 + i < m && k0 + k < m);
+        const int k = k0 + ak + 2 * q;
+        ra[q] = Raw<T>::load(abuf, (rok && k < m) ? (uint32_t)((int64_t)k * lda + r0 + ai) : kOOB);
       }
-      // X tile: rows k0..k0+15, columns 0..63
 #pragma unroll
       for (int q = 0; q < BK * NB / NT; ++q) {
-        const int e = t + NT * q, k = e % BK, j = e / BK;
-        S.tl.Xs[k][j] = ldv(Xin, (int64_t)j * ldxin + k0 + k, j < n && k0 + k < m);
+        const int j = xj + 8 * q, k = k0 + xk;
+        rx[q] = Raw<T>::load(xbuf, (j < n && k < m) ? (uint32_t)((int64_t)j * ldx + k) : kOOB);
       }
+    };
+    f64x4 w[RBW];
+#pragma unroll
+    for (int b = 0; b < RBW; ++b) w[b] = f64x4{0, 0, 0, 0};
+    load(0);
+    for (int k0 = 0; k0 < m; k0 += BK) {
+#pragma unroll
+      for (int q = 0; q < BR * BK / NT; ++q) S.tl.As[ak + 2 * q][ai] = (double)ra[q];
+#pragma unroll
+      for (int q = 0; q < BK * NB / NT; ++q) S.tl.Xs[xk][xj + 8 * q] = (double)rx[q];
       __syncthreads();
+      load(k0 + BK);                          // in flight during the MFMAs below (past the end: zeros)
+      if (active) {
 #pragma unroll
-      for (int kk = 0; kk < BK; kk += 4) {
-        const double a = S.tl.As[kk + li][wave * 16 + lj];
+        for (int kk = 0; kk < BK; kk += 4) {
+          const double b = S.tl.Xs[kk + li][16 * cb + lj];
 #pragma unroll
-        for (int b = 0; b < 4; ++b)
-          if (b < nbk) w[b] = mfma_f64(a, S.tl.Xs[kk + li][b * 16 + lj], w[b]);
+          for (int rb = 0; rb < RBW; ++rb)
+            w[rb] = mfma_f64(S.tl.As[kk + li][16 * RBW * rg + 16 * rb + lj], b, w[rb]);
+          __builtin_amdgcn_sched_barrier(0);   // operand reads of one K sub-step only: no hoisting
+        }
       }
       __syncthreads();
     }
+    // G(:, cb) += X_b^T W_b over this wave's rows
+    if (active) {
 #pragma unroll
-    for (int b = 0; b < 4; ++b)
+      for (int rb = 0; rb < RBW; ++rb) {
+        const int rbase = r0 + 16 * RBW * rg + 16 * rb;
+        double xa[4][4];
 #pragma unroll
-      for (int r = 0; r < 4; ++r) S.Ws[wave * 16 + 4 * r + li][b * 16 + lj] = w[b][r];
+        for (int s4 = 0; s4 < 4; ++s4)
+#pragma unroll
+          for (int gi = 0; gi < 4; ++gi) {
+            const int row = rbase + 4 * s4 + li, col = 16 * gi + lj;
+            xa[s4][gi] = ldv(X, (int64_t)col * ldx + row, row < m && col < n);
+          }
+#pragma unroll
+        for (int s4 = 0; s4 < 4; ++s4)
+#pragma unroll
+          for (int gi = 0; gi < 4; ++gi)
+            if (gi < nbk) g[gi] = mfma_f64(xa[s4][gi], w[rb][s4], g[gi]);
+      }
+    }
+  }
+  // sum the row groups into the waves of group 0
+  if (RG > 1) {
+    if (rg > 0 && active) {
+#pragma unroll
+      for (int gi = 0; gi < 4; ++gi)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) S.red[wave - CLS][gi][r][lane] = g[gi][r];
+    }
     __syncthreads();
-    // G += X_b^T W_b: A operand X_b^T (rows of G = columns of X), B operand W_b
-#pragma unroll 4
-    for (int kk = 0; kk < BR; kk += 4) {
-      const int row = r0 + kk + li;
-      const int col = wave * 16 + lj;
-      const double a = ldv(Xin, (int64_t)col * ldxin + row, row < m && col < n);
+    if (rg == 0 && active) {
 #pragma unroll
-      for (int b = 0; b < 4; ++b)
-        if (b < nbk) g[b] = mfma_f64(a, S.Ws[kk + li][b * 16 + lj], g[b]);
+      for (int q = 1; q < RG; ++q)
+#pragma unroll
+        for (int gi = 0; gi < 4; ++gi)
+#pragma unroll
+          for (int r = 0; r < 4; ++r) g[gi][r] += S.red[q * CLS + wave - CLS][gi][r][lane];
     }
     __syncthreads();
   }
+}
+
+// One CHOLQR pass on instance (A, X) in place: X <- X R^{-1}, R into smem Gs (upper, zero lower).
+// Returns 0 or the failing pivot (1-based).
+template <class T>
+__device__ __noinline__ int cholqr_pass_wg(const T* A, int64_t lda, const T* Xin, int64_t ldxin, T* X, int64_t ldx, int m,
+                              int n, double unit, double c_first, double c_retry, int max_retries, Smem& S) {
+  const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+  const int li = lane >> 4, lj = lane & 15;
+  // ---- G = X^T A X ----------------------------------------------------------------------------
+  f64x4 g[4];                                 // waves of row group 0: G(16 gi + .., 16 cb + ..)
+  const int nbk = (n + 15) / 16;
+  int cls;
+  if (nbk <= 1) {
+    gram_phase<T, 1>(A, lda, Xin, ldxin, m, n, S, g);
+    cls = 1;
+  } else if (nbk == 2) {
+    gram_phase<T, 2>(A, lda, Xin, ldxin, m, n, S, g);
+    cls = 2;
+  } else {
+    gram_phase<T, 4>(A, lda, Xin, ldxin, m, n, S, g);
+    cls = 4;
+  }
+  const bool owner = wave < cls && wave < nbk;   // waves holding a column block of G
+  const int cb = wave;
   // ---- R = chol(G + s I), retries from the accumulators ------------------------------------------
   // max diag(G): diagonal entries sit in block b == wave, element r with 4r + li == lj
   if (t < NB) S.diag[t] = 0.0;
   __syncthreads();
+  if (owner) {
 #pragma unroll
-  for (int b = 0; b < 4; ++b)
+    for (int gi = 0; gi < 4; ++gi)
 #pragma unroll
-    for (int r = 0; r < 4; ++r)
-      if (b == wave && 4 * r + li == lj) S.diag[wave * 16 + lj] = g[b][r];
+      for (int r = 0; r < 4; ++r)
+        if (gi == cb && 4 * r + li == lj) S.diag[cb * 16 + lj] = g[gi][r];
+  }
   __syncthreads();
   if (t == 0) {
     double mx = 0.0;
@@ -125,20 +232,24 @@ __device__ int cholqr_pass_wg(const T* A, int64_t lda, const T* Xin, int64_t ldx
   for (int attempt = 0;; ++attempt) {
     const double s = c * unit * S.dmax;
     // G (upper triangle, symmetric use) into Gs; identity beyond n
+    for (int e = t; e < NB * NB; e += NT) {
+      const int i = e / NB, j = e % NB;
+      if (i >= n || j >= n) S.f.Gs[i][j] = (i == j) ? 1.0 : 0.0;
+    }
+    if (owner) {
 #pragma unroll
-    for (int b = 0; b < 4; ++b)
+      for (int gi = 0; gi < 4; ++gi)
 #pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int i = wave * 16 + 4 * r + li, j = b * 16 + lj;
-        double v = g[b][r] + (i == j ? s : 0.0);
-        if (i >= n || j >= n) v = (i == j) ? 1.0 : 0.0;
-        S.Gs[i][j] = v;
-      }
+        for (int r = 0; r < 4; ++r) {
+          const int i = gi * 16 + 4 * r + li, j = cb * 16 + lj;
+          if (i < n && j < n) S.f.Gs[i][j] = g[gi][r] + (i == j ? s : 0.0);
+        }
+    }
     if (t == 0) S.fail = 0;
     __syncthreads();
     // right-looking, upper: one entry per thread-slot, two barriers per pivot
     for (int k = 0; k < n; ++k) {
-      const double piv = S.Gs[k][k];
+      const double piv = S.f.Gs[k][k];
       if (!(piv > 0.0)) {
         if (t == 0) S.fail = k + 1;
         break;
@@ -148,16 +259,16 @@ __device__ int cholqr_pass_wg(const T* A, int64_t lda, const T* Xin, int64_t ldx
 #pragma unroll
       for (int q = 0; q < NB * NB / NT; ++q) {
         const int e = t + NT * q, i = e / NB, j = e % NB;
-        double v = S.Gs[i][j];
+        double v = S.f.Gs[i][j];
         if (i == k && j >= k) v = (j == k) ? rkk : v / rkk;
-        else if (i > k && j >= i) v = v - (S.Gs[k][i] / rkk) * (S.Gs[k][j] / rkk);
+        else if (i > k && j >= i) v = v - (S.f.Gs[k][i] / rkk) * (S.f.Gs[k][j] / rkk);
         nv[q] = v;
       }
       __syncthreads();
 #pragma unroll
       for (int q = 0; q < NB * NB / NT; ++q) {
         const int e = t + NT * q, i = e / NB, j = e % NB;
-        S.Gs[i][j] = nv[q];
+        S.f.Gs[i][j] = nv[q];
       }
       __syncthreads();
     }
@@ -171,7 +282,7 @@ __device__ int cholqr_pass_wg(const T* A, int64_t lda, const T* Xin, int64_t ldx
   // zero the strictly lower triangle
   for (int e = t; e < NB * NB; e += NT) {
     const int i = e / NB, j = e % NB;
-    if (i > j) S.Gs[i][j] = 0.0;
+    if (i > j) S.f.Gs[i][j] = 0.0;
   }
   __syncthreads();
   // ---- X <- X R^{-1}: four lanes per row (lane `sub` owns columns sub + 4e), the pivot column's
@@ -188,12 +299,12 @@ __device__ int cholqr_pass_wg(const T* A, int64_t lda, const T* Xin, int64_t ldx
       for (int c = 0; c < NB; ++c) {
         if (c < n) {
           const int owner = c & 3, ec = c >> 2;
-          const double qo = x[ec] / S.Gs[c][c];
+          const double qo = x[ec] / S.f.Gs[c][c];
           const double qv = __shfl(qo, (lane & ~3) | owner);
           if (sub == owner) x[ec] = qv;
 #pragma unroll
           for (int e = 0; e < NB / 4; ++e) {
-            const double upd = x[e] - qv * S.Gs[c][sub + 4 * e];
+            const double upd = x[e] - qv * S.f.Gs[c][sub + 4 * e];
             x[e] = (sub + 4 * e > c) ? upd : x[e];
           }
           __builtin_amdgcn_sched_barrier(0);
@@ -209,7 +320,7 @@ __device__ int cholqr_pass_wg(const T* A, int64_t lda, const T* Xin, int64_t ldx
 }
 
 template <class T>
-__global__ __launch_bounds__(NT) void batch_kernel(const oqr_batch_item* __restrict__ items,
+__global__ __launch_bounds__(NT, 2) void batch_kernel(const oqr_batch_item* __restrict__ items,
                                                     const int32_t* __restrict__ order, int batch,
                                                     int32_t* __restrict__ counter, int32_t* __restrict__ info,
                                                     double c_retry, int max_retries) {
@@ -235,11 +346,10 @@ __global__ __launch_bounds__(NT) void batch_kernel(const oqr_batch_item* __restr
       __syncthreads();
       continue;
     }
-    double r1[NB * NB / NT];                    // R1, kept in registers across pass 2
-#pragma unroll
-    for (int q = 0; q < NB * NB / NT; ++q) {
-      const int e = t + NT * q, i = e / NB, j = e % NB;
-      r1[q] = S.Gs[i][j];
+    // R1 waits in the output R (upper n x n) across pass 2
+    for (int e = t; e < n * n; e += NT) {
+      const int i = e % n, j = e / n;
+      R[(int64_t)j * it.ldr + i] = (T)S.f.Gs[i][j];
     }
     __syncthreads();
     f = cholqr_pass_wg<T>(A, it.lda, Q, it.ldq, Q, it.ldq, m, n, U64, 0.0, c_retry, max_retries, S);
@@ -248,18 +358,17 @@ __global__ __launch_bounds__(NT) void batch_kernel(const oqr_batch_item* __restr
       __syncthreads();
       continue;
     }
-    // R = R2 R1: R2 in Gs, R1 into Ws
-#pragma unroll
-    for (int q = 0; q < NB * NB / NT; ++q) {
-      const int e = t + NT * q, i = e / NB, j = e % NB;
-      S.Ws[i][j] = r1[q];
+    // R = R2 R1: R2 in Gs, R1 (back from R) into Ws
+    for (int e = t; e < NB * NB; e += NT) {
+      const int i = e % NB, j = e / NB;
+      S.f.Ws[i][j] = (i < n && j < n) ? (double)R[(int64_t)j * it.ldr + i] : 0.0;
     }
     __syncthreads();
     for (int e = t; e < n * n; e += NT) {
       const int i = e % n, j = e / n;
       double s = 0.0;
       if (i <= j)
-        for (int k = i; k <= j; ++k) s += S.Gs[i][k] * S.Ws[k][j];
+        for (int k = i; k <= j; ++k) s += S.f.Gs[i][k] * S.f.Ws[k][j];
       R[(int64_t)j * it.ldr + i] = (T)s;
     }
     if (t == 0) info[id] = 0;
