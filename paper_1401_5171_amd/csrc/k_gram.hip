@@ -206,6 +206,223 @@ __global__ __launch_bounds__(NT) void gram_split_kernel(const double* __restrict
     }
 }
 
+// ---- all upper tiles per workgroup (n <= 128) ---------------------------------------------------
+// One workgroup owns a chunk of rows and every upper 64x64 tile of G, so X and Y are read once.  Tile
+// loads are unconditional buffer loads (rows past m read as zero) issued one K step ahead and consumed
+// only at the next LDS store.  One buffer resource per 64-column block keeps offsets below 2 GB.
+constexpr int NCH_FULL = 512;    // target number of row chunks
+
+struct FullPlan {
+  int chunks, kc;
+};
+FullPlan full_plan(int64_t m, int kstep) {
+  FullPlan p;
+  int64_t kc = (m + NCH_FULL - 1) / NCH_FULL;
+  if (kc < 256) kc = 256;
+  kc = (kc + kstep - 1) / kstep * kstep;
+  p.kc = (int)kc;
+  p.chunks = ceil_div(m, kc);
+  return p;
+}
+
+__device__ __forceinline__ bufrsrc block_buf(const double* base, int64_t ld, int m, int n, int r0, int c0) {
+  const int cols = min(TB, n - c0);
+  return make_buf(base + (int64_t)c0 * ld + r0, ((int64_t)(cols - 1) * ld + (m - r0)) * 8);
+}
+
+template <int NBT>
+__global__ __launch_bounds__(NT, 2) void gram_full_f64_kernel(const double* __restrict__ X, int64_t ldx,
+                                                             const double* __restrict__ Y, int64_t ldy, int m, int n,
+                                                             int kc, double* __restrict__ partial) {
+  __shared__ double Xs[NBT][BK][TB + 1];
+  __shared__ double Ys[NBT][BK][TB + 1];
+  const int c = blockIdx.x;
+  const int r0 = c * kc, r1 = min(m, r0 + kc);
+  const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+  const int li = lane >> 4, lj = lane & 15;
+  bufrsrc xb[NBT], yb[NBT];
+#pragma unroll
+  for (int b = 0; b < NBT; ++b) {
+    xb[b] = block_buf(X, ldx, m, n, r0, b * TB);
+    yb[b] = block_buf(Y, ldy, m, n, r0, b * TB);
+  }
+  // thread: k = t % BK, columns lc + 16 q (q = 0..3) of each block
+  const int lk = t % BK, lc = t / BK;
+  double rx[NBT][4], ry[NBT][4];
+  auto load = [&](int k0) {
+    const int k = k0 + lk;                    // absolute row
+#pragma unroll
+    for (int b = 0; b < NBT; ++b)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int col = lc + 16 * q;
+        const uint32_t ox = (k < r1) ? (uint32_t)((int64_t)col * ldx + (k - r0)) * 8u : kOOB;
+        const uint32_t oy = (k < r1) ? (uint32_t)((int64_t)col * ldy + (k - r0)) * 8u : kOOB;
+        rx[b][q] = buf_f64(xb[b], ox);
+        ry[b][q] = buf_f64(yb[b], oy);
+      }
+  };
+  constexpr int NTILE = NBT * (NBT + 1) / 2;
+  f64x4 acc[NTILE][4];
+#pragma unroll
+  for (int u = 0; u < NTILE; ++u)
+#pragma unroll
+    for (int q = 0; q < 4; ++q) acc[u][q] = f64x4{0, 0, 0, 0};
+  load(r0);
+  for (int k0 = r0; k0 < r1; k0 += BK) {
+#pragma unroll
+    for (int b = 0; b < NBT; ++b)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        Xs[b][lk][lc + 16 * q] = rx[b][q];
+        Ys[b][lk][lc + 16 * q] = ry[b][q];
+      }
+    __syncthreads();
+    load(k0 + BK);                            // past r1: kOOB, zeros
+#pragma unroll
+    for (int kk = 0; kk < BK; kk += 4) {
+      const int kr = kk + li;
+      int u = 0;
+#pragma unroll
+      for (int I = 0; I < NBT; ++I) {
+        const double a = Xs[I][kr][wave * 16 + lj];
+#pragma unroll
+        for (int J = I; J < NBT; ++J, ++u)
+#pragma unroll
+          for (int q = 0; q < 4; ++q) acc[u][q] = mfma_f64(a, Ys[J][kr][q * 16 + lj], acc[u][q]);
+      }
+    }
+    __syncthreads();
+  }
+  double* P = partial + (int64_t)c * n * n;
+  int u = 0;
+#pragma unroll
+  for (int I = 0; I < NBT; ++I)
+#pragma unroll
+    for (int J = I; J < NBT; ++J, ++u)
+#pragma unroll
+      for (int q = 0; q < 4; ++q)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int i = I * TB + wave * 16 + 4 * r + li;
+          const int j = J * TB + q * 16 + lj;
+          if (i < n && j < n) P[(int64_t)j * n + i] = acc[u][q][r];
+        }
+}
+
+template <int S, int NBT>
+__global__ __launch_bounds__(NT, 2) void gram_full_split_kernel(const double* __restrict__ X, int64_t ldx,
+                                                               const double* __restrict__ Y, int64_t ldy, int m,
+                                                               int n, int kc, double* __restrict__ partial) {
+  __shared__ __attribute__((aligned(16))) unsigned short Xs[NBT][S][TB][BKS + SPAD];
+  __shared__ __attribute__((aligned(16))) unsigned short Ys[NBT][S][TB][BKS + SPAD];
+  const int c = blockIdx.x;
+  const int r0 = c * kc, r1 = min(m, r0 + kc);
+  const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+  bufrsrc xb[NBT], yb[NBT];
+#pragma unroll
+  for (int b = 0; b < NBT; ++b) {
+    xb[b] = block_buf(X, ldx, m, n, r0, b * TB);
+    yb[b] = block_buf(Y, ldy, m, n, r0, b * TB);
+  }
+  // thread: column lc = t / 4 (0..63) of each block, rows (t % 4) * 8 .. +7
+  const int lq = t % 4, lc = t / 4;
+  double rx[NBT][8], ry[NBT][8];
+  auto load = [&](int k0) {
+#pragma unroll
+    for (int b = 0; b < NBT; ++b)
+#pragma unroll
+      for (int e = 0; e < 8; ++e) {
+        const int k = k0 + lq * 8 + e;
+        const uint32_t ox = (k < r1) ? (uint32_t)((int64_t)lc * ldx + (k - r0)) * 8u : kOOB;
+        const uint32_t oy = (k < r1) ? (uint32_t)((int64_t)lc * ldy + (k - r0)) * 8u : kOOB;
+        rx[b][e] = buf_f64(xb[b], ox);
+        ry[b][e] = buf_f64(yb[b], oy);
+      }
+  };
+  constexpr int NTILE = NBT * (NBT + 1) / 2;
+  f32x4 acc[NTILE][4];
+  double dacc[NTILE][4][4];
+#pragma unroll
+  for (int u = 0; u < NTILE; ++u)
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      acc[u][q] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+      for (int r = 0; r < 4; ++r) dacc[u][q][r] = 0.0;
+    }
+  load(r0);
+  int since = 0;
+  for (int k0 = r0; k0 < r1; k0 += BKS) {
+#pragma unroll
+    for (int b = 0; b < NBT; ++b)
+#pragma unroll
+      for (int e = 0; e < 8; ++e) {
+        unsigned short sx[S], sy[S];
+        split_bf16<S>(rx[b][e], sx);
+        split_bf16<S>(ry[b][e], sy);
+#pragma unroll
+        for (int s2 = 0; s2 < S; ++s2) {
+          Xs[b][s2][lc][lq * 8 + e] = sx[s2];
+          Ys[b][s2][lc][lq * 8 + e] = sy[s2];
+        }
+      }
+    __syncthreads();
+    load(k0 + BKS);
+    const int kb = 8 * (lane >> 4);
+    int u = 0;
+#pragma unroll
+    for (int I = 0; I < NBT; ++I) {
+      bf16x8 a[S];
+#pragma unroll
+      for (int s2 = 0; s2 < S; ++s2)
+        a[s2] = __builtin_bit_cast(bf16x8, *reinterpret_cast<const u16x8*>(&Xs[I][s2][wave * 16 + (lane & 15)][kb]));
+#pragma unroll
+      for (int J = I; J < NBT; ++J, ++u) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          bf16x8 b[S];
+#pragma unroll
+          for (int s2 = 0; s2 < S; ++s2)
+            b[s2] = __builtin_bit_cast(bf16x8, *reinterpret_cast<const u16x8*>(&Ys[J][s2][q * 16 + (lane & 15)][kb]));
+#pragma unroll
+          for (int p = S - 1; p >= 0; --p)
+#pragma unroll
+            for (int q2 = S - 1 - p; q2 >= 0; --q2)
+              acc[u][q] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[p], b[q2], acc[u][q], 0, 0, 0);
+        }
+      }
+    }
+    since += BKS;
+    if (since == KT || k0 + BKS >= r1) {
+#pragma unroll
+      for (int u2 = 0; u2 < NTILE; ++u2)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+#pragma unroll
+          for (int r = 0; r < 4; ++r) dacc[u2][q][r] += (double)acc[u2][q][r];
+          acc[u2][q] = f32x4{0.f, 0.f, 0.f, 0.f};
+        }
+      since = 0;
+    }
+    __syncthreads();
+  }
+  double* P = partial + (int64_t)c * n * n;
+  int u = 0;
+#pragma unroll
+  for (int I = 0; I < NBT; ++I)
+#pragma unroll
+    for (int J = I; J < NBT; ++J, ++u)
+#pragma unroll
+      for (int q = 0; q < 4; ++q)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int i = I * TB + wave * 16 + 4 * (lane >> 4) + r;
+          const int j = J * TB + q * 16 + (lane & 15);
+          if (i < n && j < n) P[(int64_t)j * n + i] = dacc[u][q][r];
+        }
+}
+
 // G(i, j) = G(j, i) = sum_c partial[c](i, j) for i <= j, summed in chunk order.
 __global__ void gram_reduce_kernel(const double* __restrict__ partial, int n, int chunks, double* __restrict__ G) {
   const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -222,7 +439,13 @@ __global__ void gram_reduce_kernel(const double* __restrict__ partial, int n, in
 
 size_t gram_partial_bytes(int64_t m, int64_t n) {
   GramPlan p = plan(m, n);
-  return (size_t)p.chunks * n * n * sizeof(double);
+  size_t b = (size_t)p.chunks * n * n * sizeof(double);
+  if (n <= 2 * TB) {
+    const FullPlan f = full_plan(m, BK), g = full_plan(m, BKS);
+    const size_t bf = (size_t)(f.chunks > g.chunks ? f.chunks : g.chunks) * n * n * sizeof(double);
+    if (bf > b) b = bf;
+  }
+  return b;
 }
 
 static hipError_t reduce(const double* partial, int64_t n, int chunks, double* G, hipStream_t s) {
@@ -233,6 +456,16 @@ static hipError_t reduce(const double* partial, int64_t n, int chunks, double* G
 
 hipError_t launch_gram_f64(const double* X, int64_t ldx, const double* Y, int64_t ldy, int64_t m, int64_t n,
                            double* partial, double* G, hipStream_t s) {
+  if (n <= 2 * TB) {
+    const FullPlan f = full_plan(m, BK);
+    if (n <= TB)
+      gram_full_f64_kernel<1><<<f.chunks, NT, 0, s>>>(X, ldx, Y, ldy, (int)m, (int)n, f.kc, partial);
+    else
+      gram_full_f64_kernel<2><<<f.chunks, NT, 0, s>>>(X, ldx, Y, ldy, (int)m, (int)n, f.kc, partial);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    return reduce(partial, n, f.chunks, G, s);
+  }
   GramPlan p = plan(m, n);
   gram_f64_kernel<<<dim3(p.tiles, p.chunks), NT, 0, s>>>(X, ldx, Y, ldy, (int)m, (int)n, p.nb, p.kc, partial);
   hipError_t e = hipGetLastError();
@@ -242,6 +475,20 @@ hipError_t launch_gram_f64(const double* X, int64_t ldx, const double* Y, int64_
 
 hipError_t launch_gram_split(const double* X, int64_t ldx, const double* Y, int64_t ldy, int64_t m, int64_t n,
                              int slices, double* partial, double* G, hipStream_t s) {
+  if (n <= 2 * TB) {
+    const FullPlan f = full_plan(m, BKS);
+    const int M = (int)m, N = (int)n;
+    if (n <= TB) {
+      if (slices == 2) gram_full_split_kernel<2, 1><<<f.chunks, NT, 0, s>>>(X, ldx, Y, ldy, M, N, f.kc, partial);
+      else gram_full_split_kernel<3, 1><<<f.chunks, NT, 0, s>>>(X, ldx, Y, ldy, M, N, f.kc, partial);
+    } else {
+      if (slices == 2) gram_full_split_kernel<2, 2><<<f.chunks, NT, 0, s>>>(X, ldx, Y, ldy, M, N, f.kc, partial);
+      else gram_full_split_kernel<3, 2><<<f.chunks, NT, 0, s>>>(X, ldx, Y, ldy, M, N, f.kc, partial);
+    }
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    return reduce(partial, n, f.chunks, G, s);
+  }
   GramPlan p = plan(m, n);
   if (slices == 2)
     gram_split_kernel<2><<<dim3(p.tiles, p.chunks), NT, 0, s>>>(X, ldx, Y, ldy, (int)m, (int)n, p.nb, p.kc, partial);

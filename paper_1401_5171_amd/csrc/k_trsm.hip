@@ -149,16 +149,27 @@ __global__ __launch_bounds__(NT, 2) void trsm_kernel(const double* Z, int64_t ld
       double x[8];
 #pragma unroll
       for (int e = 0; e < 8; ++e) x[e] = Qs[(j0 + sub + 4 * e) * LDQ + row];
-#pragma unroll
+      // the operands of step c + 1 are read from LDS during step c (one wave per SIMD hides nothing)
+      double rzc[8], rzn[8], ric = rinv[0], rin = 1.0;
+      #pragma unroll
+      for (int e = 0; e < 8; ++e) rzc[e] = RZ[0][sub * 8 + e];
+      #pragma unroll
       for (int c = 0; c < JB; ++c) {
+        if (c + 1 < JB) {
+      #pragma unroll
+          for (int e = 0; e < 8; ++e) rzn[e] = RZ[c + 1][sub * 8 + e];
+          rin = rinv[c + 1];
+        }
         const int owner = c & 3, ec = c >> 2;
-        const double q = quad_bcast(x[ec] * rinv[c], owner);
-        const double* rz = &RZ[c][sub * 8];
+        const double q = quad_bcast(x[ec] * ric, owner);
         // columns sub + 4e <= c are final: e below (c - 3) / 4 is skipped for every lane
-#pragma unroll
+      #pragma unroll
         for (int e = 0; e < 8; ++e)
-          if (4 * e + 3 > c) x[e] = __builtin_fma(-q, rz[e], x[e]);
+          if (4 * e + 3 > c) x[e] = __builtin_fma(-q, rzc[e], x[e]);
         x[ec] = (sub == owner) ? q : x[ec];
+      #pragma unroll
+        for (int e = 0; e < 8; ++e) rzc[e] = rzn[e];
+        ric = rin;
       }
 #pragma unroll
       for (int e = 0; e < 8; ++e) Qs[(j0 + sub + 4 * e) * LDQ + row] = x[e];
@@ -175,32 +186,194 @@ __global__ __launch_bounds__(NT, 2) void trsm_kernel(const double* Z, int64_t ld
   }
 }
 
-// W = A Z for the 7-point operator: one thread per (grid point, column).
-__global__ void stencil_apply_kernel(const double* __restrict__ Z, int64_t ldz, double* __restrict__ W, int64_t ldw,
-                                     int nx, int ny, int nz, double center, double off, int64_t n) {
-  const int64_t m = (int64_t)nx * ny * nz;
-  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (idx >= m * n) return;
-  const int64_t j = idx / m, p = idx % m;
-  const int x = (int)(p % nx);
-  const int y = (int)((p / nx) % ny);
-  const int zc = (int)(p / ((int64_t)nx * ny));
-  const double* z = Z + j * ldz;
-  const int64_t sy = nx, sz = (int64_t)nx * ny;
-  double nb = 0.0;
-  if (x > 0) nb += z[p - 1];
-  if (x < nx - 1) nb += z[p + 1];
-  if (y > 0) nb += z[p - sy];
-  if (y < ny - 1) nb += z[p + sy];
-  if (zc > 0) nb += z[p - sz];
-  if (zc < nz - 1) nb += z[p + sz];
-  W[j * ldw + p] = center * z[p] + off * nb;
+// Persistent variant for n <= NMAX <= 128 and many row tiles: one workgroup per CU walks the tiles
+// blockIdx.x, + gridDim.x, ...  R is the same for every tile, so each wave keeps the R fragments of
+// its MFMA updates in registers and the diagonal blocks stay in LDS for the whole launch; the next
+// tile's Z is loaded into registers while the current tile is solved.  Same operations in the same
+// order as trsm_kernel<NMAX, 64>, so the results are identical.
+template <int NMAX>
+__global__ __launch_bounds__(NT, 1) void trsm_persist_kernel(const double* Z, int64_t ldz,
+                                                             const double* __restrict__ R, int64_t ldr, double* Q,
+                                                             int64_t ldq, int m, int n, int ntiles,
+                                                             const int32_t* __restrict__ info) {
+  constexpr int BMR = 64, LDQ = BMR + 1, NBLK = NMAX / JB;
+  constexpr int NF = 8 * NBLK * (NBLK - 1) / 2;   // R fragments per lane and half: sum over J of 8 J
+  __shared__ double Qs[NMAX * LDQ];
+  __shared__ __attribute__((aligned(16))) double RZ[NBLK][JB][JB];
+  __shared__ double rinv[NBLK][JB];
+  if (info[0] != 0) return;
+  const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+  const int li = lane >> 4, lj = lane & 15;
+  const int nblk = (n + JB - 1) / JB;
+  // diagonal blocks, once
+  for (int idx = t; idx < NBLK * JB * JB; idx += NT) {
+    const int J = idx / (JB * JB), c = (idx / JB) % JB, q = idx % JB, sub = q >> 3, e = q & 7;
+    const int col = sub + 4 * e, gr = J * JB + c, gc = J * JB + col;
+    RZ[J][c][q] = (col > c && gc < n) ? R[(int64_t)gc * ldr + gr] : 0.0;
+  }
+  for (int idx = t; idx < NBLK * JB; idx += NT) {
+    const int g = idx;
+    rinv[idx / JB][idx % JB] = (g < n) ? 1.0 / R[(int64_t)g * ldr + g] : 1.0;
+  }
+  // off-diagonal R fragments, once: rf[h][off(J) + s] = R(4 s + li, j0 + 16 h + lj), s < 8 J
+  double rf[2][NF > 0 ? NF : 1];
+#pragma unroll
+  for (int J = 1; J < NBLK; ++J) {
+    const int off = 8 * J * (J - 1) / 2;
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int jc = J * JB + 16 * h + lj;
+#pragma unroll
+      for (int s2 = 0; s2 < 8 * J; ++s2) {
+        const int k = 4 * s2 + li;
+        rf[h][off + s2] = (jc < n && k < n) ? R[(int64_t)jc * ldr + k] : 0.0;
+      }
+    }
+  }
+  // Z tile prefetch: thread (row i = t % 64, columns jq + 4u)
+  constexpr int PU = NMAX / 4;
+  const int pi = t % BMR, pj = t / BMR;
+  double zr[PU];
+  auto prefetch = [&](int tile) {
+    const int row = min(tile * BMR + pi, m - 1);
+#pragma unroll
+    for (int u = 0; u < PU; ++u) zr[u] = Z[(int64_t)min(pj + 4 * u, n - 1) * ldz + row];
+  };
+  const int row = t >> 2, sub = t & 3;      // substitution: 4 lanes per row
+  int tile = blockIdx.x;
+  if (tile < ntiles) prefetch(tile);
+  for (; tile < ntiles; tile += gridDim.x) {
+    const int i0 = tile * BMR;
+#pragma unroll
+    for (int u = 0; u < PU; ++u) Qs[(pj + 4 * u) * LDQ + pi] = (pj + 4 * u < n) ? zr[u] : 0.0;
+    __syncthreads();
+    if (tile + (int)gridDim.x < ntiles) prefetch(tile + gridDim.x);
+#pragma unroll
+    for (int J = 0; J < NBLK; ++J) {
+      if (J >= nblk) break;
+      const int j0 = J * JB;
+      if (J > 0) {
+        const int off = 8 * J * (J - 1) / 2;
+        f64x4 acc[2];
+#pragma unroll
+        for (int h = 0; h < 2; ++h)
+#pragma unroll
+          for (int r = 0; r < 4; ++r) acc[h][r] = Qs[(j0 + 16 * h + lj) * LDQ + wave * 16 + 4 * r + li];
+#pragma unroll
+        for (int s2 = 0; s2 < 8 * J; ++s2) {
+          const double a = -Qs[(4 * s2 + li) * LDQ + wave * 16 + lj];
+          acc[0] = mfma_f64(a, rf[0][off + s2], acc[0]);
+          acc[1] = mfma_f64(a, rf[1][off + s2], acc[1]);
+        }
+#pragma unroll
+        for (int h = 0; h < 2; ++h)
+#pragma unroll
+          for (int r = 0; r < 4; ++r) Qs[(j0 + 16 * h + lj) * LDQ + wave * 16 + 4 * r + li] = acc[h][r];
+      }
+      __syncthreads();
+      {
+        double x[8];
+#pragma unroll
+        for (int e = 0; e < 8; ++e) x[e] = Qs[(j0 + sub + 4 * e) * LDQ + row];
+        // the operands of step c + 1 are read from LDS during step c (one wave per SIMD hides nothing)
+        double rzc[8], rzn[8], ric = rinv[J][0], rin = 1.0;
+        #pragma unroll
+        for (int e = 0; e < 8; ++e) rzc[e] = RZ[J][0][sub * 8 + e];
+        #pragma unroll
+        for (int c = 0; c < JB; ++c) {
+          if (c + 1 < JB) {
+        #pragma unroll
+            for (int e = 0; e < 8; ++e) rzn[e] = RZ[J][c + 1][sub * 8 + e];
+            rin = rinv[J][c + 1];
+          }
+          const int owner = c & 3, ec = c >> 2;
+          const double q = quad_bcast(x[ec] * ric, owner);
+          // columns sub + 4e <= c are final: e below (c - 3) / 4 is skipped for every lane
+        #pragma unroll
+          for (int e = 0; e < 8; ++e)
+            if (4 * e + 3 > c) x[e] = __builtin_fma(-q, rzc[e], x[e]);
+          x[ec] = (sub == owner) ? q : x[ec];
+        #pragma unroll
+          for (int e = 0; e < 8; ++e) rzc[e] = rzn[e];
+          ric = rin;
+        }
+#pragma unroll
+        for (int e = 0; e < 8; ++e) Qs[(j0 + sub + 4 * e) * LDQ + row] = x[e];
+      }
+      __syncthreads();
+    }
+    if (i0 + pi < m) {
+      for (int j = pj; j < n; j += 4) Q[(int64_t)j * ldq + i0 + pi] = Qs[j * LDQ + pi];
+    }
+    __syncthreads();
+  }
+}
+
+// W = A Z for the 7-point operator (Dirichlet boundary, index p = x + nx (y + ny z)).
+// A thread owns one (x, y) point of one column and marches through z: the values at z-1, z and z+1
+// stay in registers, so each plane is read from HBM once; the four in-plane neighbours come from
+// lines that the same and adjacent waves load (cache hits).  Centres are fetched two planes ahead,
+// neighbours one plane ahead, with buffer loads whose out-of-grid offsets read as zero.
+__global__ __launch_bounds__(256) void stencil_march_kernel(const double* __restrict__ Z, int64_t ldz,
+                                                             double* __restrict__ W, int64_t ldw, int nx, int ny,
+                                                             int nz, double center, double off) {
+  const int64_t sxy = (int64_t)nx * ny;
+  const int64_t m = sxy * nz;
+  const int j = blockIdx.y;
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;   // point of the plane
+  if (idx >= sxy) return;
+  const int x = (int)(idx % nx), y = (int)(idx / nx);
+  const bufrsrc zb = make_buf(Z + (int64_t)j * ldz, m * 8);
+  double* w = W + (int64_t)j * ldw + idx;
+  const bool xl = x > 0, xr = x < nx - 1, yl = y > 0, yr = y < ny - 1;
+  auto at = [&](int zz, int d, bool ok) -> uint32_t {
+    return (ok && zz >= 0 && zz < nz) ? (uint32_t)(((int64_t)zz * sxy + idx + d) * 8) : kOOB;
+  };
+  double cm = 0.0;
+  double c0 = buf_f64(zb, at(0, 0, true));
+  double cp = buf_f64(zb, at(1, 0, true));
+  double n0 = buf_f64(zb, at(0, -1, xl)), n1 = buf_f64(zb, at(0, 1, xr));
+  double n2 = buf_f64(zb, at(0, -nx, yl)), n3 = buf_f64(zb, at(0, nx, yr));
+  for (int z = 0; z < nz; ++z) {
+    const double cpp = buf_f64(zb, at(z + 2, 0, true));
+    const double p0 = buf_f64(zb, at(z + 1, -1, xl)), p1 = buf_f64(zb, at(z + 1, 1, xr));
+    const double p2 = buf_f64(zb, at(z + 1, -nx, yl)), p3 = buf_f64(zb, at(z + 1, nx, yr));
+    w[(int64_t)z * sxy] = center * c0 + off * (((n0 + n1) + (n2 + n3)) + (cm + cp));
+    cm = c0;
+    c0 = cp;
+    cp = cpp;
+    n0 = p0;
+    n1 = p1;
+    n2 = p2;
+    n3 = p3;
+  }
 }
 
 }  // namespace
 
+static int cu_count() {
+  static int cached[64] = {0};
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 256;
+  if (cached[dev] == 0) {
+    int v = 0;
+    if (hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && v > 0) cached[dev] = v;
+  }
+  return cached[dev] > 0 ? cached[dev] : 256;
+}
+
 hipError_t launch_trsm(const double* Z, int64_t ldz, const double* R, int64_t ldr, double* Q, int64_t ldq,
                        int64_t m, int64_t n, const int32_t* info, hipStream_t s) {
+  const int64_t ntiles = (m + 63) / 64;
+  const int cus = cu_count();
+  if (n <= 128 && ntiles >= 4 * cus && ntiles < 0x7fffffff) {
+    const int grid = (n <= 64) ? 2 * cus : cus;   // 188 / 388 VGPRs: two or one workgroup per CU
+    if (n <= 64)
+      trsm_persist_kernel<64><<<grid, NT, 0, s>>>(Z, ldz, R, ldr, Q, ldq, (int)m, (int)n, (int)ntiles, info);
+    else
+      trsm_persist_kernel<128><<<grid, NT, 0, s>>>(Z, ldz, R, ldr, Q, ldq, (int)m, (int)n, (int)ntiles, info);
+    return hipGetLastError();
+  }
   if (n <= 64)
     trsm_kernel<64, 64><<<ceil_div(m, 64), NT, 0, s>>>(Z, ldz, R, ldr, Q, ldq, (int)m, (int)n, info);
   else if (n <= 128)
@@ -212,10 +385,11 @@ hipError_t launch_trsm(const double* Z, int64_t ldz, const double* R, int64_t ld
 
 hipError_t launch_stencil_apply(const oqr_op* op, const double* Z, int64_t ldz, double* W, int64_t ldw, int64_t n,
                                 hipStream_t s) {
-  const int64_t m = (int64_t)op->nx * op->ny * op->nz;
-  const int64_t total = m * n;
-  stencil_apply_kernel<<<(unsigned)((total + 255) / 256), 256, 0, s>>>(Z, ldz, W, ldw, op->nx, op->ny, op->nz,
-                                                                        op->center, op->off, n);
+  const int64_t sxy = (int64_t)op->nx * op->ny;
+  if (sxy == 0 || n == 0) return hipSuccess;
+  if (sxy * op->nz * 8 > 0x7fffffffll) return hipErrorInvalidValue;   // 32-bit buffer offsets per column
+  stencil_march_kernel<<<dim3((unsigned)((sxy + 255) / 256), (unsigned)n), 256, 0, s>>>(
+      Z, ldz, W, ldw, op->nx, op->ny, op->nz, op->center, op->off);
   return hipGetLastError();
 }
 

@@ -178,6 +178,25 @@ def test_stencil_cholqr2_fp64(grid, n):
     assert metrics.r_forward_error(r, r0) <= 10 * n * U * np.linalg.cond(r0)
 
 
+@pytest.mark.parametrize("n", [40, 100])
+def test_stencil_large_grid_persistent_paths(n):
+    """m = 135135 rows (a ragged last 64-row tile, more than 2000 tiles): the z-marching stencil, the
+    all-tiles Gram and the persistent substitution with R held in registers."""
+    grid = (65, 63, 33)
+    st = W.laplacian7(*grid)
+    z = W.gaussian_scaled(W.rng_for(3, 1, *grid), st.m, n, 1e4)
+    q0, r0 = reference.stencil_eqr(st, z)
+    banner(f"stencil large grid={grid} n={n}")
+    op = oqr.Stencil7(*grid, st.center, st.off)
+    q, r = (to_host(x) for x in oqr.cholqr2(op, to_dev_colmajor(z)))
+    assert metrics.residual_f(z, q, r) <= 1e-12
+    assert metrics.orth_loss(st, q) <= 1e-12
+    assert metrics.r_forward_error(r, r0) <= 10 * n * U * np.linalg.cond(r0)
+    q1, r1 = (to_host(x) for x in oqr.cholqr2(op, to_dev_colmajor(z), pass1="bf16x3"))
+    assert metrics.residual_f(z, q1, r1) <= 1e-12
+    assert metrics.orth_loss(st, q1) <= 1e-12
+
+
 def test_stencil_single_pass_reaches_fp64_on_column_scaled_z():
     """Column scaling alone (kappa(Z) from diag(s)) is harmless to CHOLQR: one FP64 pass suffices."""
     grid, n = (24, 24, 12), 64
