@@ -148,6 +148,7 @@ struct PassWs {
   double* R1;         // n x n (first pass of CholQR2)
   double* R2;         // n x n (second pass)
   unsigned short* zs; // bf16 slices of Z (dense reduced precision)
+  double* kpart;      // split-K partial products of the dense GEMMs (may be empty)
   double* shifts;     // [2] shift used per pass
 };
 
@@ -165,6 +166,8 @@ size_t pass_ws(const oqr_op* A, int64_t m, int64_t n, const oqr_opts& o, bool tw
     if (two && o.pass2 != OQR_P_FP64 && slices_of(o.pass2) > maxs) maxs = slices_of(o.pass2);
   }
   w.zs = c.take<unsigned short>((size_t)maxs * split_ld(m) * n);
+  const size_t kp = A->kind == OQR_OP_DENSE ? gemm_kpart_bytes(m, n) : 0;
+  w.kpart = kp ? c.take<double>(kp / sizeof(double)) : nullptr;
   w.shifts = c.take<double>(2);
   if (out) *out = w;
   return c.off;
@@ -177,10 +180,10 @@ int cholqr_pass(const oqr_op* A, const double* Z, int64_t ldz, int64_t m, int64_
   if (A->kind == OQR_OP_DENSE) {
     const double* a = (const double*)A->a;
     if (prec == OQR_P_FP64) {
-      OQR_TRACED(K_GEMM_F64, s, launch_gemm_f64(a, A->lda, Z, ldz, w.W, m, m, n, s));
+      OQR_TRACED(K_GEMM_F64, s, launch_gemm_f64(a, A->lda, Z, ldz, w.W, m, m, n, w.kpart, s));
     } else {
       OQR_TRACED(K_SPLIT_Z, s, launch_split_z(Z, ldz, w.zs, m, n, slices_of(prec), s));
-      OQR_TRACED(K_GEMM_SPLIT, s, launch_gemm_split(a, A->lda, w.zs, w.W, m, m, n, slices_of(prec), s));
+      OQR_TRACED(K_GEMM_SPLIT, s, launch_gemm_split(a, A->lda, w.zs, w.W, m, m, n, slices_of(prec), w.kpart, s));
     }
     OQR_TRACED(K_GRAM, s, launch_gram_f64(Z, ldz, w.W, m, m, n, w.partial, w.G, s));
   } else {

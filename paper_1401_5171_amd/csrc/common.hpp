@@ -58,6 +58,24 @@ __device__ __forceinline__ T sel_load(const T* base, int64_t idx, bool valid) {
   return valid ? v : T(0);
 }
 
+// Broadcast lane O of every group of four lanes to the whole group (DPP quad_perm).
+template <int O>
+__device__ __forceinline__ double quad_bcast(double v) {
+  constexpr int ctrl = O | (O << 2) | (O << 4) | (O << 6);
+  const long long b = __builtin_bit_cast(long long, v);
+  const int lo = __builtin_amdgcn_mov_dpp((int)(b & 0xffffffffll), ctrl, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_mov_dpp((int)(b >> 32), ctrl, 0xF, 0xF, false);
+  return __builtin_bit_cast(double, ((long long)hi << 32) | (unsigned int)lo);
+}
+__device__ __forceinline__ double quad_bcast(double v, int o) {
+  switch (o) {
+    case 0: return quad_bcast<0>(v);
+    case 1: return quad_bcast<1>(v);
+    case 2: return quad_bcast<2>(v);
+    default: return quad_bcast<3>(v);
+  }
+}
+
 // Raw buffer loads: a buffer resource (base, size in bytes) and 32-bit byte offsets.  An offset
 // at or beyond the size returns zero, which gives bounds-checked tile loads without branches or
 // selects; kOOB marks a lane whose element lies outside the matrix.
@@ -90,13 +108,19 @@ void trace_post(int kid, hipStream_t s);
 
 // ---- launchers implemented in the kernel translation units --------------------------------------
 
-// W (m x n, ldw) = A (m x m, lda) * Z (m x n, ldz), FP64 MFMA.
+// Compute units of the current device (queried once per device).
+int device_cu_count();
+
+// W (m x n, ldw) = A (m x m, lda) * Z (m x n, ldz), FP64 MFMA.  When the tile grid is too small for
+// the device, K is split over workgroups into FP64 partial products in kpart (gemm_kpart_bytes; null
+// disables the split) that are then summed in a fixed order.
+size_t gemm_kpart_bytes(int64_t m, int64_t n);
 hipError_t launch_gemm_f64(const double* A, int64_t lda, const double* Z, int64_t ldz, double* W, int64_t ldw,
-                           int64_t m, int64_t n, hipStream_t s);
+                           int64_t m, int64_t n, double* kpart, hipStream_t s);
 // W = A * Z with A split on the fly into `slices` bfloat16 slices and Z pre-split (zs: slices x n
 // columns of split_ld(m) bf16 each); FP32 MFMA accumulation over K tiles of 256, FP64 across tiles.
 hipError_t launch_gemm_split(const double* A, int64_t lda, const unsigned short* zs, double* W, int64_t ldw,
-                             int64_t m, int64_t n, int slices, hipStream_t s);
+                             int64_t m, int64_t n, int slices, double* kpart, hipStream_t s);
 // zs[s][j*m + i] = slice s of Z(i, j).
 hipError_t launch_split_z(const double* Z, int64_t ldz, unsigned short* zs, int64_t m, int64_t n, int slices,
                           hipStream_t s);

@@ -580,7 +580,7 @@ int chol_a_run(const oqr_op* A, const double* Z, int64_t ldz, int64_t m64, int64
     OQR_TRY(hipGetLastError());
   }
   // W = C Z  (C upper, zero below the diagonal)
-  OQR_TRY(launch_gemm_f64(C, m, Z, ldz, W, m, m, n, s));
+  OQR_TRY(launch_gemm_f64(C, m, Z, ldz, W, m, m, n, nullptr, s));
   // [Y, R] = qr(W): Y goes to Q
   OQR_TRY(householder_qr(W, m, m, n, tau, R, ldr, Q, ldq, s));
   // Q = C^{-1} Y (block back-substitution from the bottom)
@@ -791,14 +791,14 @@ int eig_a_run(const oqr_op* A, const double* Z, int64_t ldz, int64_t m64, int64_
   // X = V^T Z; W = D^{1/2} X; [Y, R] = qr(W); U = D^{-1/2} Y; Q = V U
   transpose_kernel<<<dim3(ceil_div(m, 32), ceil_div(m, 32)), dim3(32, 8), 0, s>>>(V, m, Vt, m, m);
   OQR_TRY(hipGetLastError());
-  OQR_TRY(launch_gemm_f64(Vt, m, Z, ldz, X, m, m, n, s));
+  OQR_TRY(launch_gemm_f64(Vt, m, Z, ldz, X, m, m, n, nullptr, s));
   const int64_t mn = (int64_t)m * n;
   diag_scale_kernel<<<(unsigned)((mn + 255) / 256), 256, 0, s>>>(X, m, m, n, d, 0, info);
   OQR_TRY(hipGetLastError());
   OQR_TRY(householder_qr(X, m, m, n, tau, R, ldr, U, m, s));
   diag_scale_kernel<<<(unsigned)((mn + 255) / 256), 256, 0, s>>>(U, m, m, n, d, 1, info);
   OQR_TRY(hipGetLastError());
-  OQR_TRY(launch_gemm_f64(V, m, U, m, Q, ldq, m, n, s));
+  OQR_TRY(launch_gemm_f64(V, m, U, m, Q, ldq, m, n, nullptr, s));
   return OQR_OK;
 }
 

@@ -475,16 +475,7 @@ int oqr_cholqr2_batched(int64_t batch, const oqr_batch_item* items_dev, int32_t 
     identity_order_kernel<<<(unsigned)((batch + 255) / 256), 256, 0, s>>>((int)batch, order, counter, info_dev);
   if (hipGetLastError() != hipSuccess) return OQR_E_HIP;
   // compute-unit count, queried once per device (outside any graph capture: the first call)
-  static int cu_count[64] = {0};
-  int dev = 0, cus = 256;
-  if (hipGetDevice(&dev) == hipSuccess && dev >= 0 && dev < 64) {
-    if (cu_count[dev] == 0) {
-      int v = 0;
-      if (hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && v > 0)
-        cu_count[dev] = v;
-    }
-    if (cu_count[dev] > 0) cus = cu_count[dev];
-  }
+  const int cus = device_cu_count();
   int64_t grid = (int64_t)cus * cfg.wg_per_cu;
   if (grid > batch) grid = batch;
   trace_pre(K_BATCH, s);

@@ -33,6 +33,7 @@ __global__ __launch_bounds__(NTC) void chol_kernel(const double* __restrict__ G,
   __shared__ double Dk[2][CB][CB + 1];
   __shared__ double P[CB][OQR_MAX_N + 2];     // block row K: P[p][j] = entry (k0 + p, j), j absolute column
   __shared__ double red[NW];
+  __shared__ double rdiag[CB];                // 1 / r_kk of the current diagonal block
   __shared__ double s_dmax;
   __shared__ int s_fail;
   const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
@@ -138,13 +139,14 @@ __global__ __launch_bounds__(NTC) void chol_kernel(const double* __restrict__ G,
           if (t == 0) s_fail = k0 + k + 1;
           break;
         }
-        const double rkk = sqrt(piv);
+        const double rkk = sqrt(piv), ri = 1.0 / rkk;   // one reciprocal per pivot
+        if (t == 0) rdiag[k] = ri;
 #pragma unroll
         for (int e = 0; e < DPT; ++e) {
           const int di = (t + NTC * e) >> 5, dj = (t + NTC * e) & 31;
           double nv = Dk[cur][di][dj];
-          if (di == k && dj >= k) nv = (dj == k) ? rkk : nv / rkk;
-          else if (di > k && dj >= di) nv = nv - (Dk[cur][k][di] / rkk) * (Dk[cur][k][dj] / rkk);
+          if (di == k && dj >= k) nv = (dj == k) ? rkk : nv * ri;
+          else if (di > k && dj >= di) nv = nv - (Dk[cur][k][di] * ri) * (Dk[cur][k][dj] * ri);
           Dk[nxt][di][dj] = nv;
         }
         __syncthreads();
@@ -169,9 +171,8 @@ __global__ __launch_bounds__(NTC) void chol_kernel(const double* __restrict__ G,
 #pragma unroll
           for (int p = 0; p < CB; ++p) {
             const int owner = p & 3, ep = p >> 2;
-            // branch-free: every lane divides, the owner's quotient is broadcast
-            const double qo = x[ep] / Dk[0][p][p];
-            const double q = __shfl(qo, (lane & ~3) | owner);
+            // branch-free: every lane scales, the owner's value is broadcast
+            const double q = quad_bcast(x[ep] * rdiag[p], owner);
             if (sub == owner) x[ep] = q;
 #pragma unroll
             for (int e = 0; e < 8; ++e) {
@@ -240,6 +241,17 @@ __global__ void fill_i32_kernel(int32_t* p, int32_t v, int64_t count) {
 }
 
 }  // namespace
+
+int device_cu_count() {
+  static int cached[64] = {0};
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 256;
+  if (cached[dev] == 0) {
+    int v = 0;
+    if (hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && v > 0) cached[dev] = v;
+  }
+  return cached[dev] > 0 ? cached[dev] : 256;
+}
 
 hipError_t launch_chol_small(const double* G, int64_t n, double* R, int64_t ldr, double unit, double c_first,
                              double c_retry, int max_retries, int32_t* info, double* shift_used, hipStream_t s) {

@@ -24,12 +24,16 @@ constexpr int APAD = 1, BPAD = 1;
 template <int CB>
 __global__ __launch_bounds__(NT, 2) void gemm_f64_kernel(const double* __restrict__ A, int64_t lda,
                                                           const double* __restrict__ Z, int64_t ldz,
-                                                          double* __restrict__ W, int64_t ldw, int m, int n) {
+                                                          double* __restrict__ W, int64_t ldw, int m, int n,
+                                                          int kchunk, int64_t wstride) {
   constexpr int BN = 64 * CB;                   // columns per workgroup
   __shared__ double As[BK64][BM + APAD];
   __shared__ double Bs[BK64][BN + BPAD];
   const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
   const int i0 = blockIdx.x * BM, j0 = blockIdx.y * BN;
+  // K slice [kb, ke) of this workgroup (split K: partial products into W + z * wstride)
+  const int kb = blockIdx.z * kchunk, ke = min(m, kb + kchunk);
+  W += blockIdx.z * wstride;
   const int wc = wave * 16 * CB;
 
   f64x4 acc[4][CB];
@@ -52,10 +56,10 @@ __global__ __launch_bounds__(NT, 2) void gemm_f64_kernel(const double* __restric
   for (int r = 0; r < BR; ++r)
     boff[r] = (j0 + bj + 16 * r < n) ? (uint32_t)(((int64_t)(bj + 16 * r) * ldz + bk) * 8) : kOOB;
   auto load = [&](int k0) {
-    // A rows i0.., columns k0..: the size bound cuts k >= m; Z rows k0.., columns j0..
-    const bufrsrc abuf = make_buf(A + (int64_t)k0 * lda + i0, (int64_t)(m - k0) * lda * 8);
+    // A rows i0.., columns k0..: the size bound cuts k >= ke; Z rows k0.., columns j0..
+    const bufrsrc abuf = make_buf(A + (int64_t)min(k0, ke) * lda + i0, (int64_t)(ke - min(k0, ke)) * lda * 8);
     const bufrsrc zbuf = make_buf(Z + (int64_t)j0 * ldz + k0, (int64_t)(n - j0) * ldz * 8);
-    const bool kin = k0 + bk < m;
+    const bool kin = k0 + bk < ke;
 #pragma unroll
     for (int r = 0; r < AR; ++r) ra[r] = buf_f64(abuf, aoff[r]);
 #pragma unroll
@@ -68,10 +72,10 @@ __global__ __launch_bounds__(NT, 2) void gemm_f64_kernel(const double* __restric
     for (int r = 0; r < BR; ++r) Bs[bk][bj + 16 * r] = rb[r];
   };
 
-  load(0);
+  load(kb);
   store();
   __syncthreads();
-  for (int k0 = 0; k0 < m; k0 += BK64) {
+  for (int k0 = kb; k0 < ke; k0 += BK64) {
     load(k0 + BK64);                   // past the end: guarded loads return zeros
 #pragma unroll
     for (int kk = 0; kk < BK64; kk += 4) {
@@ -115,7 +119,8 @@ constexpr int SROW = BKS + 8;   // LDS row stride of an A slice (bf16 elements)
 template <int S, int CB>
 __global__ __launch_bounds__(NT, 1) void gemm_split_kernel(const double* __restrict__ A, int64_t lda,
                                                             const unsigned short* __restrict__ zs,
-                                                            double* __restrict__ W, int64_t ldw, int m, int n) {
+                                                            double* __restrict__ W, int64_t ldw, int m, int n,
+                                                            int kchunk, int64_t wstride) {
   constexpr int BN = 64 * CB;
   __shared__ __attribute__((aligned(16))) unsigned short As[2][S][BM][SROW];
   __shared__ double Dacc[NT / 64][4 * CB * 4][64];     // FP64 accumulators: [wave][slot][lane]
@@ -124,6 +129,9 @@ __global__ __launch_bounds__(NT, 1) void gemm_split_kernel(const double* __restr
   const int wc = j0 + wave * 16 * CB;
   const int64_t mp = split_ld(m);             // ld of the slices of Z (rows padded with zeros)
   const int64_t slice_stride = mp * n;
+  // K slice [kb, ke) (kchunk is a multiple of BKS; the last slice ends at m)
+  const int kb = blockIdx.z * kchunk, ke = min(m, kb + kchunk);
+  W += blockIdx.z * wstride;
 
   f32x4 acc[4][CB];
 #pragma unroll
@@ -143,7 +151,8 @@ __global__ __launch_bounds__(NT, 1) void gemm_split_kernel(const double* __restr
   for (int e = 0; e < 8; ++e) aoff[e] = (i0 + ai < m) ? (uint32_t)(((int64_t)(ak * 8 + e) * lda + ai) * 8) : kOOB;
   double ra0[8], ra1[8], ra2[8];
   auto load_a = [&](double (&ra)[8], int k0) {
-    const bufrsrc abuf = make_buf(A + (int64_t)min(k0, m) * lda + i0, (int64_t)(m - k0) * lda * 8);
+    k0 += kb;
+    const bufrsrc abuf = make_buf(A + (int64_t)min(k0, ke) * lda + i0, (int64_t)(ke - min(k0, ke)) * lda * 8);
 #pragma unroll
     for (int e = 0; e < 8; ++e) ra[e] = buf_f64(abuf, aoff[e]);
   };
@@ -176,8 +185,10 @@ __global__ __launch_bounds__(NT, 1) void gemm_split_kernel(const double* __restr
   }
   uint4 bf0[S][CB], bf1[S][CB], bf2[S][CB];
   auto load_b = [&](int k0, uint4 (&dst)[S][CB]) {
-    // rows k0 .. k0 + 31 of every slice; past the padded end the buffer is empty (zeros)
-    const bufrsrc zbuf = make_buf(zs + min((int64_t)k0, mp), k0 < mp ? (int64_t)(S * slice_stride - k0) * 2 : 0);
+    // rows k0 .. k0 + 31 of every slice; past the slice (or the padded end) the buffer is empty
+    k0 += kb;
+    const bool live = k0 < ke || (ke == m && k0 < mp);
+    const bufrsrc zbuf = make_buf(zs + min((int64_t)k0, mp), live ? (int64_t)(S * slice_stride - k0) * 2 : 0);
 #pragma unroll
     for (int s = 0; s < S; ++s)
 #pragma unroll
@@ -187,7 +198,7 @@ __global__ __launch_bounds__(NT, 1) void gemm_split_kernel(const double* __restr
 
   // K steps, padded to a multiple of 6 (3 A register stages x 2 B fragment buffers); steps past the
   // end of K read empty buffers and contribute zeros, so no load sits under a branch.
-  const int nsteps = ((m + BKS - 1) / BKS + 5) / 6 * 6;
+  const int nsteps = ((ke - kb + BKS - 1) / BKS + 5) / 6 * 6;
   // One K step, a single basic block: request B(st+2) and A(st+3); read the A fragments of buffer
   // st & 1; convert A(st+1) into the other buffer while the MFMAs run; one barrier.  B is requested
   // before A: memory counters retire in order, so the wait for B(st+1) at the next step must not
@@ -286,32 +297,87 @@ __global__ void split_z_kernel(const double* __restrict__ Z, int64_t ldz, unsign
 
 int col_blocks(int64_t n) { return n <= 64 ? 1 : (n <= 128 ? 2 : 4); }
 
+// W(i, j) = sum_z P[z](i, j) (ld m), z ascending.
+__global__ void ksum_kernel(const double* __restrict__ P, int ks, int64_t m, int64_t n, double* __restrict__ W,
+                            int64_t ldw) {
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= m * n) return;
+  double s = 0.0;
+  for (int z = 0; z < ks; ++z) s += P[(int64_t)z * m * n + idx];
+  W[(idx / m) * ldw + idx % m] = s;
+}
+
+struct KSplit {
+  int ks, kchunk;
+};
+// Split K when the row x column tiles leave CUs idle (fewer than two workgroups per CU).
+KSplit ksplit(int64_t m, int64_t n) {
+  const int cb = col_blocks(n);
+  const int64_t wgs = (int64_t)ceil_div(m, BM) * ceil_div(n, 64 * cb);
+  const int64_t target = 2 * (int64_t)device_cu_count();
+  KSplit k{1, (int)m};
+  if (wgs >= target || m < 2048) return k;
+  int ks = (int)((target + wgs - 1) / wgs);
+  if (ks > 8) ks = 8;
+  if (ks > m / 1024) ks = (int)(m / 1024);
+  if (ks < 2) return k;
+  int64_t chunk = (m + ks - 1) / ks;
+  chunk = (chunk + 95) / 96 * 96;              // a multiple of both K steps
+  k.ks = (int)((m + chunk - 1) / chunk);
+  k.kchunk = (int)chunk;
+  return k;
+}
+
 }  // namespace
 
-hipError_t launch_gemm_f64(const double* A, int64_t lda, const double* Z, int64_t ldz, double* W, int64_t ldw,
-                           int64_t m, int64_t n, hipStream_t s) {
-  const int cb = col_blocks(n);
-  dim3 grid(ceil_div(m, BM), ceil_div(n, 64 * cb));
-  switch (cb) {
-    case 1: gemm_f64_kernel<1><<<grid, NT, 0, s>>>(A, lda, Z, ldz, W, ldw, (int)m, (int)n); break;
-    case 2: gemm_f64_kernel<2><<<grid, NT, 0, s>>>(A, lda, Z, ldz, W, ldw, (int)m, (int)n); break;
-    default: gemm_f64_kernel<4><<<grid, NT, 0, s>>>(A, lda, Z, ldz, W, ldw, (int)m, (int)n); break;
-  }
+size_t gemm_kpart_bytes(int64_t m, int64_t n) {
+  const KSplit k = ksplit(m, n);
+  return k.ks > 1 ? (size_t)k.ks * m * n * sizeof(double) : 0;
+}
+
+static hipError_t ksum(const double* P, int ks, int64_t m, int64_t n, double* W, int64_t ldw, hipStream_t s) {
+  const int64_t total = m * n;
+  ksum_kernel<<<(unsigned)((total + 255) / 256), 256, 0, s>>>(P, ks, m, n, W, ldw);
   return hipGetLastError();
 }
 
-hipError_t launch_gemm_split(const double* A, int64_t lda, const unsigned short* zs, double* W, int64_t ldw,
-                             int64_t m, int64_t n, int slices, hipStream_t s) {
+hipError_t launch_gemm_f64(const double* A, int64_t lda, const double* Z, int64_t ldz, double* W, int64_t ldw,
+                           int64_t m, int64_t n, double* kpart, hipStream_t s) {
   const int cb = col_blocks(n);
-  dim3 grid(ceil_div(m, BM), ceil_div(n, 64 * cb));
-#define OQR_SPLIT_CASE(S_, CB_) gemm_split_kernel<S_, CB_><<<grid, NT, 0, s>>>(A, lda, zs, W, ldw, (int)m, (int)n)
+  KSplit k = ksplit(m, n);
+  if (!kpart) k = KSplit{1, (int)m};
+  dim3 grid(ceil_div(m, BM), ceil_div(n, 64 * cb), k.ks);
+  double* out = k.ks > 1 ? kpart : W;
+  const int64_t ldo = k.ks > 1 ? m : ldw, stride = k.ks > 1 ? m * n : 0;
+  switch (cb) {
+    case 1: gemm_f64_kernel<1><<<grid, NT, 0, s>>>(A, lda, Z, ldz, out, ldo, (int)m, (int)n, k.kchunk, stride); break;
+    case 2: gemm_f64_kernel<2><<<grid, NT, 0, s>>>(A, lda, Z, ldz, out, ldo, (int)m, (int)n, k.kchunk, stride); break;
+    default: gemm_f64_kernel<4><<<grid, NT, 0, s>>>(A, lda, Z, ldz, out, ldo, (int)m, (int)n, k.kchunk, stride); break;
+  }
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess || k.ks == 1) return e;
+  return ksum(kpart, k.ks, m, n, W, ldw, s);
+}
+
+hipError_t launch_gemm_split(const double* A, int64_t lda, const unsigned short* zs, double* W, int64_t ldw,
+                             int64_t m, int64_t n, int slices, double* kpart, hipStream_t s) {
+  const int cb = col_blocks(n);
+  KSplit k = ksplit(m, n);
+  if (!kpart) k = KSplit{1, (int)m};
+  dim3 grid(ceil_div(m, BM), ceil_div(n, 64 * cb), k.ks);
+  double* out = k.ks > 1 ? kpart : W;
+  const int64_t ldo = k.ks > 1 ? m : ldw, stride = k.ks > 1 ? m * n : 0;
+#define OQR_SPLIT_CASE(S_, CB_) \
+  gemm_split_kernel<S_, CB_><<<grid, NT, 0, s>>>(A, lda, zs, out, ldo, (int)m, (int)n, k.kchunk, stride)
   if (slices == 2) {
     if (cb == 1) OQR_SPLIT_CASE(2, 1); else if (cb == 2) OQR_SPLIT_CASE(2, 2); else OQR_SPLIT_CASE(2, 4);
   } else {
     if (cb == 1) OQR_SPLIT_CASE(3, 1); else if (cb == 2) OQR_SPLIT_CASE(3, 2); else OQR_SPLIT_CASE(3, 4);
   }
 #undef OQR_SPLIT_CASE
-  return hipGetLastError();
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess || k.ks == 1) return e;
+  return ksum(kpart, k.ks, m, n, W, ldw, s);
 }
 
 hipError_t launch_split_z(const double* Z, int64_t ldz, unsigned short* zs, int64_t m, int64_t n, int slices,

@@ -20,24 +20,6 @@ namespace {
 constexpr int JB = 32;
 constexpr int NT = 256;
 
-// Broadcast lane O of every group of four lanes to the whole group (DPP quad_perm).
-template <int O>
-__device__ __forceinline__ double quad_bcast(double v) {
-  constexpr int ctrl = O | (O << 2) | (O << 4) | (O << 6);
-  const long long b = __builtin_bit_cast(long long, v);
-  const int lo = __builtin_amdgcn_mov_dpp((int)(b & 0xffffffffll), ctrl, 0xF, 0xF, false);
-  const int hi = __builtin_amdgcn_mov_dpp((int)(b >> 32), ctrl, 0xF, 0xF, false);
-  return __builtin_bit_cast(double, ((long long)hi << 32) | (unsigned int)lo);
-}
-__device__ __forceinline__ double quad_bcast(double v, int o) {
-  switch (o) {
-    case 0: return quad_bcast<0>(v);
-    case 1: return quad_bcast<1>(v);
-    case 2: return quad_bcast<2>(v);
-    default: return quad_bcast<3>(v);
-  }
-}
-
 template <int NMAX, int BMR>
 __global__ __launch_bounds__(NT, 2) void trsm_kernel(const double* Z, int64_t ldz, const double* __restrict__ R,
                                                      int64_t ldr, double* Q, int64_t ldq, int m, int n,
@@ -351,21 +333,10 @@ __global__ __launch_bounds__(256) void stencil_march_kernel(const double* __rest
 
 }  // namespace
 
-static int cu_count() {
-  static int cached[64] = {0};
-  int dev = 0;
-  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 256;
-  if (cached[dev] == 0) {
-    int v = 0;
-    if (hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && v > 0) cached[dev] = v;
-  }
-  return cached[dev] > 0 ? cached[dev] : 256;
-}
-
 hipError_t launch_trsm(const double* Z, int64_t ldz, const double* R, int64_t ldr, double* Q, int64_t ldq,
                        int64_t m, int64_t n, const int32_t* info, hipStream_t s) {
   const int64_t ntiles = (m + 63) / 64;
-  const int cus = cu_count();
+  const int cus = device_cu_count();
   if (n <= 128 && ntiles >= 4 * cus && ntiles < 0x7fffffff) {
     const int grid = (n <= 64) ? 2 * cus : cus;   // 188 / 388 VGPRs: two or one workgroup per CU
     if (n <= 64)
