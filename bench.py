@@ -34,7 +34,13 @@ sys.path.insert(0, ROOT)
 
 METRIC = "oblique-QR GFLOP/s & % roofline, mixed vs FP64 CholQR2-A at orth loss ≤1e-12"
 PEAK = {"fp64": 78.6e12, "bf16": 2.5e15, "hbm": 8.0e12}
-TRAFFIC_NOTE = None   # filled from rocprofv3 counter runs (profiles/); null until measured for this kernel
+# HBM bytes per launch of the dominant kernel, from two rocprofv3 counter runs of this script (FETCH_SIZE,
+# then WRITE_SIZE, KiB per dispatch) scaled by what the same counters read for a 1 GiB copy
+# (--workload copycal: FETCH_SIZE x 2.0, WRITE_SIZE x 1.0).  Only for the kernel build they were taken
+# on; workloads without an entry report null.
+TRAFFIC = {
+    ("dense32768", "gemm_f64"): (4776642.7 * 2.0 + 65538.3 * 1.0) * 1024,
+}
 
 
 def log(msg):
@@ -46,7 +52,8 @@ def parse():
     p.add_argument("--gpus", type=int, default=1)
     p.add_argument("--steps", type=int, default=10)
     p.add_argument("--warmup", type=int, default=3)
-    p.add_argument("--workload", default="dense32768", choices=["dense32768", "dense8192", "stencil", "batch"])
+    p.add_argument("--workload", default="dense32768",
+                   choices=["dense32768", "dense8192", "stencil", "batch", "copycal"])
     p.add_argument("--batch-count", type=int, default=4096)
     p.add_argument("--batch-dtype", default="f64", choices=["f64", "f32"], help="storage type of the batch")
     p.add_argument("--tile", type=int, default=-1, help="batched tile id (-1: time every id, keep the best)")
@@ -262,6 +269,22 @@ def cpu_baseline_batch(As, Zs, sizes, budget_s):
             "sample": f"chol_eqr on {done} instances (every 16th of the batch)", "seconds": round(dt, 3)}
 
 
+def run_copycal(torch):
+    """Calibration for HBM counters: three copies of 1 GiB (FP64), so that FETCH_SIZE / WRITE_SIZE
+    per dispatch can be compared with the 1 GiB each copy reads and writes."""
+    nbytes = 1 << 30
+    a = torch.ones(nbytes // 8, dtype=torch.float64, device="cuda")
+    b = torch.empty_like(a)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(3):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / 3
+    print(json.dumps({"metric": "copy calibration", "bytes_read_per_copy": nbytes, "bytes_written_per_copy": nbytes,
+                      "ms_per_copy": round(dt * 1e3, 4), "GBs": round(2 * nbytes / dt / 1e9, 1)}), flush=True)
+
+
 def main():
     args = parse()
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -278,6 +301,8 @@ def main():
     torch.cuda.set_device(0)
     if args.workload == "batch":
         return run_batch(args, torch, oqr)
+    if args.workload == "copycal":
+        return run_copycal(torch)
     A, Z, z_host, m, n, desc, flops, dom_kernel, dom_flops = make_inputs(args.workload, torch)
     dense = not hasattr(A, "nx")
     pass1 = args.pass1 or ("bf16x3")
@@ -310,7 +335,8 @@ def main():
     peak = PEAK["fp64"]
     roof = {"bound": "mfma", "kernel": dom_kernel + (" (FP64, pass 2)" if dense else " (stencil Gram)"),
             "achieved": round(achieved / 1e12, 3), "peak": round(peak / 1e12, 1), "unit": "TFLOP/s",
-            "frac": round(achieved / peak, 4), "traffic": TRAFFIC_NOTE,
+            "frac": round(achieved / peak, 4), "traffic": TRAFFIC.get((args.workload, dom_kernel)),
+            "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE/WRITE_SIZE, copy-calibrated)",
             "per_launch_flops": dom_flops, "avg_launch_ms": round(kernel_ms, 4)}
     line = {
         "metric": METRIC,
