@@ -280,6 +280,149 @@ __global__ __launch_bounds__(NT, 1) void gemm_split_kernel(const double* __restr
       }
 }
 
+// Split bfloat16 product for n in (128, 256]: 512 threads (two waves per SIMD), a 64-row block of W
+// over 256 columns.  Wave (rh, cq) owns rows 32 rh .. + 31 and columns 64 cq .. + 63 (2 x 4 tiles).
+// Per K step of 32 the workgroup stages the A tile (converted to S slices) and the B tile (Z slices,
+// pre-split in HBM) in double-buffered LDS, one barrier per step; the next step's tiles are loaded
+// into registers during the current step's MFMAs.  FP32 accumulation over at most 960 rows of K,
+// folded into FP64 accumulators held in registers.
+constexpr int NT2 = 512;
+constexpr int BN2 = 256;
+
+template <int S>
+__global__ __launch_bounds__(NT2, 1) void gemm_split2_kernel(const double* __restrict__ A, int64_t lda,
+                                                             const unsigned short* __restrict__ zs,
+                                                             double* __restrict__ W, int64_t ldw, int m, int n,
+                                                             int kchunk, int64_t wstride) {
+  __shared__ __attribute__((aligned(16))) unsigned short As[2][S][BM][SROW];
+  __shared__ __attribute__((aligned(16))) unsigned short Bs[2][S][BN2][SROW];
+  const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+  const int rh = wave >> 2, cq = wave & 3;
+  const int i0 = blockIdx.x * BM;
+  const int64_t mp = split_ld(m);
+  const int64_t slice_stride = mp * n;
+  const int kb = blockIdx.z * kchunk, ke = min(m, kb + kchunk);
+  W += blockIdx.z * wstride;
+
+  f32x4 acc[2][4];
+  double dacc[2][4][4];
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+      acc[a][b] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+      for (int r = 0; r < 4; ++r) dacc[a][b][r] = 0.0;
+    }
+  // A tile 64 x 32: thread t loads row ai = t % 64, k = 4 aq .. 4 aq + 3 (aq = t / 64)
+  const int ai = t % BM, aq = t / BM;
+  uint32_t aoff[4];
+#pragma unroll
+  for (int e = 0; e < 4; ++e) aoff[e] = (i0 + ai < m) ? (uint32_t)(((int64_t)(aq * 4 + e) * lda + ai) * 8) : kOOB;
+  double ra[4];
+  auto load_a = [&](int k0) {
+    const bufrsrc abuf = make_buf(A + (int64_t)min(k0, ke) * lda + i0, (int64_t)(ke - min(k0, ke)) * lda * 8);
+#pragma unroll
+    for (int e = 0; e < 4; ++e) ra[e] = buf_f64(abuf, aoff[e]);
+  };
+  // B tile: S slices x 256 columns x 32 rows = S * 1024 chunks of 16 bytes; chunk c = t + 512 u:
+  // slice c / 1024, column (c / 4) % 256, rows 8 (c % 4) .. + 7
+  constexpr int BU = S * 1024 / NT2;
+  uint32_t boff[BU];
+#pragma unroll
+  for (int u = 0; u < BU; ++u) {
+    const int c = t + NT2 * u, sl = c / 1024, col = (c / 4) % BN2, q = c % 4;
+    boff[u] = (col < n) ? (uint32_t)(((int64_t)sl * slice_stride + (int64_t)col * mp + 8 * q) * 2) : kOOB;
+  }
+  uint4 rb[BU];
+  auto load_b = [&](int k0) {
+    const bool live = k0 < ke || (ke == m && k0 < mp);
+    const bufrsrc zbuf = make_buf(zs + min((int64_t)k0, mp), live ? (int64_t)(S * slice_stride - k0) * 2 : 0);
+#pragma unroll
+    for (int u = 0; u < BU; ++u) rb[u] = buf_b128(zbuf, boff[u]);
+  };
+  auto store = [&](int buf) {
+    // A: FP64 -> FP32 -> S bf16 slices (RNE, two per v_cvt_pk_bf16_f32); remainders exact in FP32
+    f32x2 r[2] = {f32x2{(float)ra[0], (float)ra[1]}, f32x2{(float)ra[2], (float)ra[3]}};
+#pragma unroll
+    for (int sl = 0; sl < S; ++sl) {
+      unsigned w[2];
+#pragma unroll
+      for (int q = 0; q < 2; ++q) {
+        w[q] = __builtin_bit_cast(unsigned, __builtin_convertvector(r[q], bf16x2));
+        if (sl + 1 < S) {
+          r[q].x -= __uint_as_float(w[q] << 16);
+          r[q].y -= __uint_as_float(w[q] & 0xffff0000u);
+        }
+      }
+      *reinterpret_cast<uint2*>(&As[buf][sl][ai][aq * 4]) = make_uint2(w[0], w[1]);
+    }
+#pragma unroll
+    for (int u = 0; u < BU; ++u) {
+      const int c = t + NT2 * u, sl = c / 1024, col = (c / 4) % BN2, q = c % 4;
+      *reinterpret_cast<uint4*>(&Bs[buf][sl][col][8 * q]) = rb[u];
+    }
+  };
+  auto fold = [&]() {
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+      for (int b = 0; b < 4; ++b) {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) dacc[a][b][r] += (double)acc[a][b][r];
+        acc[a][b] = f32x4{0.f, 0.f, 0.f, 0.f};
+      }
+  };
+
+  const int nsteps = (ke - kb + BKS - 1) / BKS;
+  load_a(kb);
+  load_b(kb);
+  store(0);
+  __syncthreads();
+  load_a(kb + BKS);
+  load_b(kb + BKS);
+  const int kq = 8 * (lane >> 4);
+  for (int st = 0; st < nsteps; ++st) {
+    const int cur = st & 1;
+    bf16x8 af[S][2];
+#pragma unroll
+    for (int p = 0; p < S; ++p)
+#pragma unroll
+      for (int a = 0; a < 2; ++a)
+        af[p][a] = __builtin_bit_cast(bf16x8, *reinterpret_cast<const u16x8*>(&As[cur][p][32 * rh + 16 * a + (lane & 15)][kq]));
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+      bf16x8 bf[S];
+#pragma unroll
+      for (int q = 0; q < S; ++q)
+        bf[q] = __builtin_bit_cast(bf16x8, *reinterpret_cast<const u16x8*>(&Bs[cur][q][64 * cq + 16 * b + (lane & 15)][kq]));
+#pragma unroll
+      for (int p = 0; p < S; ++p)
+#pragma unroll
+        for (int q = 0; q < S - p; ++q)
+#pragma unroll
+          for (int a = 0; a < 2; ++a)
+            acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[p][a], bf[q], acc[a][b], 0, 0, 0);
+    }
+    if (st % 30 == 29) fold();                // FP32 accumulation over at most 960 rows of K
+    store(cur ^ 1);                           // the tiles of step st + 1 (loaded during this step)
+    load_a(kb + (st + 2) * BKS);
+    load_b(kb + (st + 2) * BKS);
+    __syncthreads();
+  }
+  fold();
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 4; ++b)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int i = i0 + 32 * rh + 16 * a + 4 * (lane >> 4) + r;
+        const int j = 64 * cq + 16 * b + (lane & 15);
+        if (i < m && j < n) W[(int64_t)j * ldw + i] = dacc[a][b][r];
+      }
+}
+
 // zs[s][j][i] (ld = split_ld(m)) = slice s of Z(i, j); rows m..ld-1 are zero.
 __global__ void split_z_kernel(const double* __restrict__ Z, int64_t ldz, unsigned short* __restrict__ zs,
                                int64_t m, int64_t n, int slices) {
@@ -367,6 +510,15 @@ hipError_t launch_gemm_split(const double* A, int64_t lda, const unsigned short*
   dim3 grid(ceil_div(m, BM), ceil_div(n, 64 * cb), k.ks);
   double* out = k.ks > 1 ? kpart : W;
   const int64_t ldo = k.ks > 1 ? m : ldw, stride = k.ks > 1 ? m * n : 0;
+  if (cb == 4) {
+    if (slices == 2)
+      gemm_split2_kernel<2><<<grid, NT2, 0, s>>>(A, lda, zs, out, ldo, (int)m, (int)n, k.kchunk, stride);
+    else
+      gemm_split2_kernel<3><<<grid, NT2, 0, s>>>(A, lda, zs, out, ldo, (int)m, (int)n, k.kchunk, stride);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess || k.ks == 1) return e;
+    return ksum(kpart, k.ks, m, n, W, ldw, s);
+  }
 #define OQR_SPLIT_CASE(S_, CB_) \
   gemm_split_kernel<S_, CB_><<<grid, NT, 0, s>>>(A, lda, zs, out, ldo, (int)m, (int)n, k.kchunk, stride)
   if (slices == 2) {

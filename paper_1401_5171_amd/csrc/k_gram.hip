@@ -423,16 +423,25 @@ __global__ __launch_bounds__(NT, 2) void gram_full_split_kernel(const double* __
         }
 }
 
-// G(i, j) = G(j, i) = sum_c partial[c](i, j) for i <= j, summed in chunk order.
+// G(i, j) = G(j, i) = sum_c partial[c](i, j) for i <= j.  Eight interleaved partial sums (chunk c goes
+// to sum c mod 8) keep eight loads in flight; they are combined in a fixed order, so the result does
+// not depend on timing.
 __global__ void gram_reduce_kernel(const double* __restrict__ partial, int n, int chunks, double* __restrict__ G) {
   const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (idx >= (int64_t)n * n) return;
   const int j = (int)(idx / n), i = (int)(idx % n);
   if (i > j) return;
-  double s = 0.0;
-  for (int c = 0; c < chunks; ++c) s += partial[(int64_t)c * n * n + idx];
-  G[(int64_t)j * n + i] = s;
-  G[(int64_t)i * n + j] = s;
+  const int64_t nn = (int64_t)n * n;
+  double s[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  int c = 0;
+  for (; c + 8 <= chunks; c += 8) {
+#pragma unroll
+    for (int u = 0; u < 8; ++u) s[u] += partial[(int64_t)(c + u) * nn + idx];
+  }
+  for (int u = 0; c < chunks; ++c, ++u) s[u] += partial[(int64_t)c * nn + idx];
+  const double t = ((s[0] + s[1]) + (s[2] + s[3])) + ((s[4] + s[5]) + (s[6] + s[7]));
+  G[(int64_t)j * n + i] = t;
+  G[(int64_t)i * n + j] = t;
 }
 
 }  // namespace
