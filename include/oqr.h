@@ -117,7 +117,8 @@ typedef struct oqr_opts {
 
 /* Algorithms, for the workspace query. */
 typedef enum {
-  OQR_ALG_CHOLQR = 0, OQR_ALG_CHOLQR2 = 1, OQR_ALG_CHOL_A = 2, OQR_ALG_EIG_A = 3, OQR_ALG_GS = 4
+  OQR_ALG_CHOLQR = 0, OQR_ALG_CHOLQR2 = 1, OQR_ALG_CHOL_A = 2, OQR_ALG_EIG_A = 3, OQR_ALG_GS = 4,
+  OQR_ALG_PRE_CHOLQR = 5
 } oqr_alg;
 
 /* Largest n the single-instance kernels support. */
@@ -138,14 +139,22 @@ int oqr_cholqr(const oqr_op* A, const double* Z, int64_t ldz, int64_t m, int64_t
                void* ws, size_t ws_bytes, int32_t* info_dev, void* stream);
 
 /* CholQR2-A: CHOLQR-A twice, (Q1, R1) = CHOLQR(A, Z) in precision pass1,
- * (Q, R2) = CHOLQR(A, Q1) in precision pass2, R = R2 R1.  The repetition is
- * the device PRE-CHOLQR (Algorithm 2, Section 3) uses to remove the kappa(Z)
- * dependence of the loss of orthogonality; the analysis of Theorem 2.1 with
- * Z = Q1 gives loss c m n u ||A|| ||Q||^2.  info_dev reports the first pass
- * that failed (its pivot index). */
+ * (Q, R2) = CHOLQR(A, Q1) in precision pass2, R = R2 R1.  Like the
+ * preconditioning step of PRE-CHOLQR (Algorithm 2, Section 3), the first
+ * pass removes the kappa(Z) dependence of the loss of orthogonality; the
+ * analysis of Theorem 2.1 with Z = Q1 gives loss c m n u ||A|| ||Q||^2.
+ * info_dev reports the first pass that failed (its pivot index). */
 int oqr_cholqr2(const oqr_op* A, const double* Z, int64_t ldz, int64_t m, int64_t n,
                 double* Q, int64_t ldq, double* R, int64_t ldr, const oqr_opts* opts,
                 void* ws, size_t ws_bytes, int32_t* info_dev, void* stream);
+
+/* PRE-CHOLQR-A (Algorithm 2, Section 3): Householder QR of Z in the Euclidean
+ * product, Z = Y U (Y orthonormal, diag(U) > 0), then CHOLQR-A on Y in FP64,
+ * Y = Q S, and R = S U.  Dense or stencil A.  info_dev as oqr_cholqr.  Q may
+ * alias Z. */
+int oqr_pre_cholqr(const oqr_op* A, const double* Z, int64_t ldz, int64_t m, int64_t n,
+                   double* Q, int64_t ldq, double* R, int64_t ldr, const oqr_opts* opts,
+                   void* ws, size_t ws_bytes, int32_t* info_dev, void* stream);
 
 /* CHOL-EQR (Algorithm 3, Section 4), dense A only: C = chol(A) upper
  * (A = C^T C), W = C Z, Householder [Y, R] = qr(W) with positive diag(R),

@@ -27,11 +27,11 @@ OQR_F64, OQR_F32 = 0, 1
 OQR_OP_DENSE, OQR_OP_STENCIL7 = 0, 1
 PREC = {"fp64": 0, "fp32": 1, "bf16x2": 2, "bf16x3": 3}
 GS = {"cgs": 0, "mgs_row": 1, "mgs_col": 2, "cgs2": 3}
-ALG = {"cholqr": 0, "cholqr2": 1, "chol_a": 2, "eig_a": 3, "gs": 4}
+ALG = {"cholqr": 0, "cholqr2": 1, "chol_a": 2, "eig_a": 3, "gs": 4, "pre_cholqr": 5}
 MAX_N = 256
 
 EXPORTS = (
-    "oqr_default_opts", "oqr_workspace_bytes", "oqr_cholqr", "oqr_cholqr2", "oqr_chol_a", "oqr_eig_a",
+    "oqr_default_opts", "oqr_workspace_bytes", "oqr_cholqr", "oqr_cholqr2", "oqr_pre_cholqr", "oqr_chol_a", "oqr_eig_a",
     "oqr_gs", "oqr_check", "oqr_batched_workspace_bytes", "oqr_cholqr2_batched", "oqr_batched_tile_count",
     "oqr_status_string", "oqr_version", "oqr_trace_start", "oqr_trace_stop",
 )
@@ -73,7 +73,7 @@ def lib():
         L = ctypes.CDLL(LIB_PATH)
         vp, i64, i32, sz = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32, ctypes.c_size_t
         sig = [ctypes.POINTER(_Op), vp, i64, i64, i64, vp, i64, vp, i64, ctypes.POINTER(_Opts), vp, sz, vp, vp]
-        for name in ("oqr_cholqr", "oqr_cholqr2", "oqr_chol_a", "oqr_eig_a", "oqr_gs"):
+        for name in ("oqr_cholqr", "oqr_cholqr2", "oqr_pre_cholqr", "oqr_chol_a", "oqr_eig_a", "oqr_gs"):
             f = getattr(L, name)
             f.argtypes = sig
             f.restype = ctypes.c_int
@@ -318,6 +318,11 @@ def cholqr(A, Z, prec="fp64", shift_c=1.0, max_retries=3):
 def cholqr2(A, Z, pass1="fp64", pass2="fp64", shift_c=1.0, max_retries=3):
     """CholQR2-A (CHOLQR-A twice, R = R2 R1): returns (Q, R)."""
     return _run("cholqr2", A, Z, pass1=pass1, pass2=pass2, shift_c=shift_c, max_retries=max_retries)
+
+
+def pre_cholqr(A, Z, prec="fp64", shift_c=1.0, max_retries=3):
+    """PRE-CHOLQR-A (Algorithm 2): Householder QR Z = Y U, CHOLQR-A on Y, R = S U; returns (Q, R)."""
+    return _run("pre_cholqr", A, Z, pass1=prec, shift_c=shift_c, max_retries=max_retries)
 
 
 def chol_a(A, Z):

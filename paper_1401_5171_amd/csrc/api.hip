@@ -200,6 +200,12 @@ int cholqr_pass(const oqr_op* A, const double* Z, int64_t ldz, int64_t m, int64_
   return OQR_OK;
 }
 
+// PRE-CHOLQR workspace: one CholQR pass, then the Householder copy of Z, tau and U.
+size_t pre_ws(const oqr_op* A, int64_t m, int64_t n, const oqr_opts& o) {
+  return align256(pass_ws(A, m, n, o, false, nullptr, nullptr)) + align256((size_t)m * n * sizeof(double)) +
+         align256((size_t)(n + 8) * sizeof(double)) + align256((size_t)n * n * sizeof(double));
+}
+
 int resolve_opts(const oqr_opts* in, oqr_opts* out) {
   *out = in ? *in : defaults();
   if (!prec_ok(out->pass1) || !prec_ok(out->pass2)) {
@@ -284,6 +290,7 @@ size_t oqr_workspace_bytes(int32_t alg, const oqr_op* A, int64_t m, int64_t n, c
     case OQR_ALG_CHOL_A: return A->kind == OQR_OP_DENSE ? chol_a_workspace_bytes(m, n) : 0;
     case OQR_ALG_EIG_A: return A->kind == OQR_OP_DENSE ? eig_a_workspace_bytes(m, n) : 0;
     case OQR_ALG_GS: return gs_workspace_bytes(A, m, n);
+    case OQR_ALG_PRE_CHOLQR: return pre_ws(A, m, n, o);
     default: return 0;
   }
 }
@@ -303,6 +310,32 @@ int oqr_cholqr(const oqr_op* A, const double* Z, int64_t ldz, int64_t m, int64_t
   if ((rc = ws_check(ws, ws_bytes, need))) return rc;
   pass_ws(A, m, n, o, false, &w, ws);
   return cholqr_pass(A, Z, ldz, m, n, Q, ldq, R, ldr, o.pass1, o, w, w.shifts, info_dev, s);
+}
+
+int oqr_pre_cholqr(const oqr_op* A, const double* Z, int64_t ldz, int64_t m, int64_t n, double* Q, int64_t ldq,
+                   double* R, int64_t ldr, const oqr_opts* opts, void* ws, size_t ws_bytes, int32_t* info_dev,
+                   void* stream) {
+  int rc = check_common(A, Z, ldz, m, n, Q, ldq, R, ldr, info_dev);
+  if (rc) return rc;
+  oqr_opts o;
+  if ((rc = resolve_opts(opts, &o))) return rc;
+  hipStream_t s = (hipStream_t)stream;
+  if (launch_fill_i32(info_dev, 0, 1, s) != hipSuccess) return OQR_E_HIP;
+  if (n == 0) return OQR_OK;
+  if ((rc = ws_check(ws, ws_bytes, pre_ws(A, m, n, o)))) return rc;
+  PassWs w;
+  char* base = (char*)ws;
+  const size_t pw = align256(pass_ws(A, m, n, o, false, &w, base));
+  double* Wh = (double*)(base + pw);
+  double* tau = (double*)(base + pw + align256((size_t)m * n * sizeof(double)));
+  double* U = (double*)((char*)tau + align256((size_t)(n + 8) * sizeof(double)));
+  // Z = Y U (Householder, Euclidean product); Y goes to Q (Z has been copied, so Q may alias Z)
+  if (launch_copy_matrix(Z, ldz, Wh, m, m, n, s) != hipSuccess) return OQR_E_HIP;
+  if (launch_householder_qr(Wh, m, m, n, tau, U, n, Q, ldq, s) != hipSuccess) return OQR_E_HIP;
+  // Y = Q S (CHOLQR-A), R = S U
+  if ((rc = cholqr_pass(A, Q, ldq, m, n, Q, ldq, w.R1, n, o.pass1, o, w, w.shifts, info_dev, s))) return rc;
+  if (launch_trmm_upper(w.R1, n, U, n, R, ldr, n, info_dev, s) != hipSuccess) return OQR_E_HIP;
+  return OQR_OK;
 }
 
 int oqr_cholqr2(const oqr_op* A, const double* Z, int64_t ldz, int64_t m, int64_t n, double* Q, int64_t ldq,

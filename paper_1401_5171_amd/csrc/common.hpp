@@ -146,6 +146,10 @@ hipError_t launch_trsm(const double* Z, int64_t ldz, const double* R, int64_t ld
 // R = R2 * R1 (upper x upper).
 hipError_t launch_trmm_upper(const double* R2, int64_t ld2, const double* R1, int64_t ld1, double* R, int64_t ldr,
                              int64_t n, const int32_t* info, hipStream_t s);
+// Householder QR of W (m x n, overwritten by the reflectors): R (n x n, positive diagonal) and the
+// explicit orthonormal factor Y (m x n).  tau: n doubles.
+hipError_t launch_householder_qr(double* W, int64_t ldw, int64_t m, int64_t n, double* tau, double* R, int64_t ldr,
+                                 double* Y, int64_t ldy, hipStream_t s);
 hipError_t launch_copy_matrix(const double* X, int64_t ldx, double* Y, int64_t ldy, int64_t m, int64_t n,
                               hipStream_t s);
 hipError_t launch_fill_i32(int32_t* p, int32_t v, int64_t count, hipStream_t s);

@@ -275,6 +275,11 @@ hipError_t householder_qr(double* W, int64_t ldw, int m, int n, double* tau, dou
 
 }  // namespace
 
+hipError_t launch_householder_qr(double* W, int64_t ldw, int64_t m, int64_t n, double* tau, double* R, int64_t ldr,
+                                 double* Y, int64_t ldy, hipStream_t s) {
+  return householder_qr(W, ldw, (int)m, (int)n, tau, R, ldr, Y, ldy, s);
+}
+
 // =================================================================================================
 // Gram-Schmidt in the A inner product
 // =================================================================================================
