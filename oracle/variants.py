@@ -53,12 +53,20 @@ def trsm_right_upper(z: np.ndarray, r: np.ndarray) -> np.ndarray:
     return scipy.linalg.solve_triangular(r, z.T, trans="T", lower=False, check_finite=False).T
 
 
-def cholqr(a, z: np.ndarray, shift: float = 0.0, return_info: bool = False):
-    """CHOLQR (Algorithm 1).  The Gram matrix is symmetrised, (C + C^T)/2,
-    and `shift` is added to its diagonal before the factorisation."""
+def cholqr(a, z: np.ndarray, shift: float = 0.0, return_info: bool = False, gram: str = "sym"):
+    """CHOLQR (Algorithm 1).  C = Z^T (A Z) is symmetric only in exact arithmetic:
+    gram="sym" factors (C + C^T)/2; gram="upper" factors the symmetric matrix
+    built from the upper triangle of C, which is what the listing's chol(C) reads
+    (MATLAB's chol uses the upper triangle only).  `shift` is added to the
+    diagonal before the factorisation."""
     b = _apply(a, z)
     c = z.T @ b
-    c = 0.5 * (c + c.T)
+    if gram == "sym":
+        c = 0.5 * (c + c.T)
+    elif gram == "upper":
+        c = np.triu(c) + np.triu(c, 1).T
+    else:
+        raise ValueError(gram)
     if shift:
         c = c + shift * np.eye(c.shape[0])
     r, info = chol_info(c)
@@ -70,17 +78,17 @@ def cholqr(a, z: np.ndarray, shift: float = 0.0, return_info: bool = False):
     return (q, r, 0) if return_info else (q, r)
 
 
-def cholqr2(a, z: np.ndarray, shift1: float = 0.0):
+def cholqr2(a, z: np.ndarray, shift1: float = 0.0, gram: str = "sym"):
     """CHOLQR twice: (Q1, R1) = CHOLQR(A, Z); (Q, R2) = CHOLQR(A, Q1); R = R2 R1."""
-    q1, r1 = cholqr(a, z, shift=shift1)
-    q, r2 = cholqr(a, q1)
+    q1, r1 = cholqr(a, z, shift=shift1, gram=gram)
+    q, r2 = cholqr(a, q1, gram=gram)
     return q, np.triu(r2 @ r1)
 
 
-def pre_cholqr(a, z: np.ndarray):
+def pre_cholqr(a, z: np.ndarray, gram: str = "sym"):
     """PRE-CHOLQR (Algorithm 2)."""
     y, s = householder_qr(z)
-    q, u = cholqr(a, y)
+    q, u = cholqr(a, y, gram=gram)
     return q, np.triu(u @ s)
 
 

@@ -155,6 +155,34 @@ def test_uniqueness_across_independent_routes():
         assert metrics.r_forward_error(r, r0) < 100 * U * kap * 200, f.__name__
 
 
+@pytest.mark.parametrize("seed,m,n", [(0, 8, 3), (1, 14, 4), (3, 32, 5)])
+def test_upper_triangle_gram_matches_50_digit_definition(seed, m, n):
+    """Algorithm 1 with the listing's chol(C) reading the upper triangle of C = Z^T (A Z): one pass
+    within u kappa(R)^2 of the exact factor, two passes within u kappa(R)."""
+    a, z = tiny(seed, m, n, ka=1e3, kz=1e2)
+    qe, re = exact.exact_oblique_qr(a, z)
+    kap = np.linalg.cond(re)
+    r1 = variants.cholqr(a, z, gram="upper")[1]
+    assert metrics.r_forward_error(r1, re) <= 50 * m * n * U * kap ** 2
+    r2 = variants.cholqr2(a, z, gram="upper")[1]
+    assert metrics.r_forward_error(r2, re) <= 50 * m * n * U * kap
+
+
+def test_gram_conventions_agree_when_the_gram_is_exact():
+    """Small integers: every product and sum is exact, so C is exactly symmetric and both readings of
+    chol(C) factor the same matrix, bit for bit; R^T R reproduces Z^T A Z."""
+    rng = np.random.default_rng(5)
+    b = rng.integers(-3, 4, size=(12, 12)).astype(np.float64)
+    a = b.T @ b + 12 * np.eye(12)
+    z = rng.integers(-2, 3, size=(12, 4)).astype(np.float64)
+    rs = variants.cholqr(a, z, gram="sym")[1]
+    ru = variants.cholqr(a, z, gram="upper")[1]
+    assert np.array_equal(rs, ru)
+    assert np.allclose(ru.T @ ru, z.T @ a @ z, rtol=1e-14, atol=0)
+    with pytest.raises(ValueError):
+        variants.cholqr(a, z, gram="lower")
+
+
 # ---- 4. the 7-point stencil ----------------------------------------------------------------
 
 def test_stencil_apply_matches_assembled_matrix():
