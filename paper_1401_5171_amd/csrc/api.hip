@@ -165,7 +165,7 @@ size_t pass_ws(const oqr_op* A, int64_t m, int64_t n, const oqr_opts& o, bool tw
     if (o.pass1 != OQR_P_FP64) maxs = slices_of(o.pass1);
     if (two && o.pass2 != OQR_P_FP64 && slices_of(o.pass2) > maxs) maxs = slices_of(o.pass2);
   }
-  w.zs = c.take<unsigned short>((size_t)maxs * split_ld(m) * n);
+  w.zs = c.take<unsigned short>(maxs ? split_z_elems(m, n, maxs) : 0);
   const size_t kp = A->kind == OQR_OP_DENSE ? gemm_kpart_bytes(m, n) : 0;
   w.kpart = kp ? c.take<double>(kp / sizeof(double)) : nullptr;
   w.shifts = c.take<double>(2);

@@ -121,7 +121,8 @@ hipError_t launch_gemm_f64(const double* A, int64_t lda, const double* Z, int64_
 // columns of split_ld(m) bf16 each); FP32 MFMA accumulation over K tiles of 256, FP64 across tiles.
 hipError_t launch_gemm_split(const double* A, int64_t lda, const unsigned short* zs, double* W, int64_t ldw,
                              int64_t m, int64_t n, int slices, double* kpart, hipStream_t s);
-// zs[s][j*m + i] = slice s of Z(i, j).
+// Slices of Z for launch_gemm_split (layout chosen by n; split_z_elems bf16 elements).
+size_t split_z_elems(int64_t m, int64_t n, int slices);
 hipError_t launch_split_z(const double* Z, int64_t ldz, unsigned short* zs, int64_t m, int64_t n, int slices,
                           hipStream_t s);
 // W = A Z for the 7-point stencil (FP64).

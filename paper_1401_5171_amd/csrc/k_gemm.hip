@@ -282,12 +282,15 @@ __global__ __launch_bounds__(NT, 1) void gemm_split_kernel(const double* __restr
 
 // Split bfloat16 product for n in (128, 256]: 512 threads (two waves per SIMD), a 64-row block of W
 // over 256 columns.  Wave (rh, cq) owns rows 32 rh .. + 31 and columns 64 cq .. + 63 (2 x 4 tiles).
-// Per K step of 32 the workgroup stages the A tile (converted to S slices) and the B tile (Z slices,
-// pre-split in HBM) in double-buffered LDS, one barrier per step; the next step's tiles are loaded
-// into registers during the current step's MFMAs.  FP32 accumulation over at most 960 rows of K,
-// folded into FP64 accumulators held in registers.
+// Per K step of 32 the workgroup stages the A tile (converted to S slices) and the B tile (the K step's
+// slices of Z, one contiguous block of the tiled layout) in double-buffered LDS, one barrier per step;
+// the tiles of the next two steps are in flight in registers (two alternating sets).  B rows in LDS
+// are 64 bytes with the 16-byte chunk index XOR-ed by (column / 2) mod 4.  FP32 accumulation over at
+// most 960 rows of K, folded into FP64 accumulators held in registers.
 constexpr int NT2 = 512;
 constexpr int BN2 = 256;
+
+__device__ __forceinline__ int bsw(int col, int ch) { return col * BKS + 8 * (ch ^ ((col >> 1) & 3)); }
 
 template <int S>
 __global__ __launch_bounds__(NT2, 1) void gemm_split2_kernel(const double* __restrict__ A, int64_t lda,
@@ -295,12 +298,12 @@ __global__ __launch_bounds__(NT2, 1) void gemm_split2_kernel(const double* __res
                                                              double* __restrict__ W, int64_t ldw, int m, int n,
                                                              int kchunk, int64_t wstride) {
   __shared__ __attribute__((aligned(16))) unsigned short As[2][S][BM][SROW];
-  __shared__ __attribute__((aligned(16))) unsigned short Bs[2][S][BN2][SROW];
+  __shared__ __attribute__((aligned(16))) unsigned short Bs[2][S][BN2 * BKS];
   const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
   const int rh = wave >> 2, cq = wave & 3;
   const int i0 = blockIdx.x * BM;
   const int64_t mp = split_ld(m);
-  const int64_t slice_stride = mp * n;
+  constexpr int64_t TILE = (int64_t)S * BN2 * BKS;   // bf16 elements of one K step of the tiled slices
   const int kb = blockIdx.z * kchunk, ke = min(m, kb + kchunk);
   W += blockIdx.z * wstride;
 
@@ -319,29 +322,28 @@ __global__ __launch_bounds__(NT2, 1) void gemm_split2_kernel(const double* __res
   uint32_t aoff[4];
 #pragma unroll
   for (int e = 0; e < 4; ++e) aoff[e] = (i0 + ai < m) ? (uint32_t)(((int64_t)(aq * 4 + e) * lda + ai) * 8) : kOOB;
-  double ra[4];
-  auto load_a = [&](int k0) {
-    const bufrsrc abuf = make_buf(A + (int64_t)min(k0, ke) * lda + i0, (int64_t)(ke - min(k0, ke)) * lda * 8);
-#pragma unroll
-    for (int e = 0; e < 4; ++e) ra[e] = buf_f64(abuf, aoff[e]);
-  };
   // B tile: S slices x 256 columns x 32 rows = S * 1024 chunks of 16 bytes; chunk c = t + 512 u:
-  // slice c / 1024, column (c / 4) % 256, rows 8 (c % 4) .. + 7
+  // slice c / 1024, column (c / 4) % 256, rows 8 (c % 4) .. + 7 (offsets inside the contiguous tile)
   constexpr int BU = S * 1024 / NT2;
   uint32_t boff[BU];
 #pragma unroll
   for (int u = 0; u < BU; ++u) {
     const int c = t + NT2 * u, sl = c / 1024, col = (c / 4) % BN2, q = c % 4;
-    boff[u] = (col < n) ? (uint32_t)(((int64_t)sl * slice_stride + (int64_t)col * mp + 8 * q) * 2) : kOOB;
+    boff[u] = (col < n) ? (uint32_t)((((int64_t)sl * BN2 + col) * BKS + 8 * q) * 2) : kOOB;
   }
-  uint4 rb[BU];
-  auto load_b = [&](int k0) {
+  double ra0[4], ra1[4];
+  uint4 rb0[BU], rb1[BU];
+  auto load = [&](int k0, double (&ra)[4], uint4 (&rb)[BU]) {
+    const bufrsrc abuf = make_buf(A + (int64_t)min(k0, ke) * lda + i0, (int64_t)(ke - min(k0, ke)) * lda * 8);
+#pragma unroll
+    for (int e = 0; e < 4; ++e) ra[e] = buf_f64(abuf, aoff[e]);
+    // the K step's tile of slices; past the slice (or the padded end) the buffer is empty
     const bool live = k0 < ke || (ke == m && k0 < mp);
-    const bufrsrc zbuf = make_buf(zs + min((int64_t)k0, mp), live ? (int64_t)(S * slice_stride - k0) * 2 : 0);
+    const bufrsrc zbuf = make_buf(zs + (live ? (int64_t)(k0 / BKS) * TILE : 0), live ? TILE * 2 : 0);
 #pragma unroll
     for (int u = 0; u < BU; ++u) rb[u] = buf_b128(zbuf, boff[u]);
   };
-  auto store = [&](int buf) {
+  auto store = [&](int buf, const double (&ra)[4], const uint4 (&rb)[BU]) {
     // A: FP64 -> FP32 -> S bf16 slices (RNE, two per v_cvt_pk_bf16_f32); remainders exact in FP32
     f32x2 r[2] = {f32x2{(float)ra[0], (float)ra[1]}, f32x2{(float)ra[2], (float)ra[3]}};
 #pragma unroll
@@ -360,7 +362,7 @@ __global__ __launch_bounds__(NT2, 1) void gemm_split2_kernel(const double* __res
 #pragma unroll
     for (int u = 0; u < BU; ++u) {
       const int c = t + NT2 * u, sl = c / 1024, col = (c / 4) % BN2, q = c % 4;
-      *reinterpret_cast<uint4*>(&Bs[buf][sl][col][8 * q]) = rb[u];
+      *reinterpret_cast<uint4*>(&Bs[buf][sl][bsw(col, q)]) = rb[u];
     }
   };
   auto fold = [&]() {
@@ -373,16 +375,8 @@ __global__ __launch_bounds__(NT2, 1) void gemm_split2_kernel(const double* __res
         acc[a][b] = f32x4{0.f, 0.f, 0.f, 0.f};
       }
   };
-
-  const int nsteps = (ke - kb + BKS - 1) / BKS;
-  load_a(kb);
-  load_b(kb);
-  store(0);
-  __syncthreads();
-  load_a(kb + BKS);
-  load_b(kb + BKS);
   const int kq = 8 * (lane >> 4);
-  for (int st = 0; st < nsteps; ++st) {
+  auto compute = [&](int st) {
     const int cur = st & 1;
     bf16x8 af[S][2];
 #pragma unroll
@@ -395,7 +389,8 @@ __global__ __launch_bounds__(NT2, 1) void gemm_split2_kernel(const double* __res
       bf16x8 bf[S];
 #pragma unroll
       for (int q = 0; q < S; ++q)
-        bf[q] = __builtin_bit_cast(bf16x8, *reinterpret_cast<const u16x8*>(&Bs[cur][q][64 * cq + 16 * b + (lane & 15)][kq]));
+        bf[q] = __builtin_bit_cast(bf16x8,
+                                   *reinterpret_cast<const u16x8*>(&Bs[cur][q][bsw(64 * cq + 16 * b + (lane & 15), kq / 8)]));
 #pragma unroll
       for (int p = 0; p < S; ++p)
 #pragma unroll
@@ -405,9 +400,23 @@ __global__ __launch_bounds__(NT2, 1) void gemm_split2_kernel(const double* __res
             acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[p][a], bf[q], acc[a][b], 0, 0, 0);
     }
     if (st % 30 == 29) fold();                // FP32 accumulation over at most 960 rows of K
-    store(cur ^ 1);                           // the tiles of step st + 1 (loaded during this step)
-    load_a(kb + (st + 2) * BKS);
-    load_b(kb + (st + 2) * BKS);
+  };
+
+  // K steps padded to an even count (steps past the end load empty buffers and add zeros)
+  const int nsteps = ((ke - kb + BKS - 1) / BKS + 1) / 2 * 2;
+  load(kb, ra0, rb0);
+  store(0, ra0, rb0);
+  __syncthreads();
+  load(kb + BKS, ra0, rb0);
+  load(kb + 2 * BKS, ra1, rb1);
+  for (int st = 0; st < nsteps; st += 2) {
+    compute(st);
+    store(1, ra0, rb0);                       // tiles of step st + 1
+    load(kb + (st + 3) * BKS, ra0, rb0);
+    __syncthreads();
+    compute(st + 1);
+    store(0, ra1, rb1);                       // tiles of step st + 2
+    load(kb + (st + 4) * BKS, ra1, rb1);
     __syncthreads();
   }
   fold();
@@ -423,9 +432,11 @@ __global__ __launch_bounds__(NT2, 1) void gemm_split2_kernel(const double* __res
       }
 }
 
-// zs[s][j][i] (ld = split_ld(m)) = slice s of Z(i, j); rows m..ld-1 are zero.
+// Slices of Z, rows m..split_ld(m)-1 zero.  Column layout (n <= 128): zs[s][j][i] (ld split_ld(m)).
+// Tiled layout (n > 128, read by gemm_split2_kernel): zs[i / 32][s][j][i % 32] with 256 columns per
+// tile, so that the slices of one 32-row K step form one contiguous block.
 __global__ void split_z_kernel(const double* __restrict__ Z, int64_t ldz, unsigned short* __restrict__ zs,
-                               int64_t m, int64_t n, int slices) {
+                               int64_t m, int64_t n, int slices, int tiled) {
   const int64_t mp = split_ld(m);
   int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (idx >= mp * n) return;
@@ -433,7 +444,8 @@ __global__ void split_z_kernel(const double* __restrict__ Z, int64_t ldz, unsign
   double r = (i < m) ? Z[j * ldz + i] : 0.0;
   for (int s = 0; s < slices; ++s) {
     unsigned short b = bf16_bits((float)r);
-    zs[(int64_t)s * mp * n + idx] = b;
+    const int64_t o = tiled ? (((i / BKS) * slices + s) * BN2 + j) * BKS + i % BKS : (int64_t)s * mp * n + idx;
+    zs[o] = b;
     r -= (double)bf16_to_f32(b);
   }
 }
@@ -522,9 +534,9 @@ hipError_t launch_gemm_split(const double* A, int64_t lda, const unsigned short*
 #define OQR_SPLIT_CASE(S_, CB_) \
   gemm_split_kernel<S_, CB_><<<grid, NT, 0, s>>>(A, lda, zs, out, ldo, (int)m, (int)n, k.kchunk, stride)
   if (slices == 2) {
-    if (cb == 1) OQR_SPLIT_CASE(2, 1); else if (cb == 2) OQR_SPLIT_CASE(2, 2); else OQR_SPLIT_CASE(2, 4);
+    if (cb == 1) OQR_SPLIT_CASE(2, 1); else OQR_SPLIT_CASE(2, 2);
   } else {
-    if (cb == 1) OQR_SPLIT_CASE(3, 1); else if (cb == 2) OQR_SPLIT_CASE(3, 2); else OQR_SPLIT_CASE(3, 4);
+    if (cb == 1) OQR_SPLIT_CASE(3, 1); else OQR_SPLIT_CASE(3, 2);
   }
 #undef OQR_SPLIT_CASE
   hipError_t e = hipGetLastError();
@@ -532,10 +544,14 @@ hipError_t launch_gemm_split(const double* A, int64_t lda, const unsigned short*
   return ksum(kpart, k.ks, m, n, W, ldw, s);
 }
 
+size_t split_z_elems(int64_t m, int64_t n, int slices) {
+  return (size_t)slices * split_ld(m) * (col_blocks(n) == 4 ? BN2 : n);
+}
+
 hipError_t launch_split_z(const double* Z, int64_t ldz, unsigned short* zs, int64_t m, int64_t n, int slices,
                           hipStream_t s) {
   int64_t total = split_ld(m) * n;
-  split_z_kernel<<<(unsigned)((total + 255) / 256), 256, 0, s>>>(Z, ldz, zs, m, n, slices);
+  split_z_kernel<<<(unsigned)((total + 255) / 256), 256, 0, s>>>(Z, ldz, zs, m, n, slices, col_blocks(n) == 4);
   return hipGetLastError();
 }
 

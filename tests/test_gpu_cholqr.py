@@ -251,6 +251,26 @@ def test_mixed_first_pass_matches_emulated_error_level():
     assert metrics.residual_f(z, q, r) <= 1e-12       # FP64 substitution keeps the residual at FP64 level
 
 
+@pytest.mark.parametrize("m,n", [(4096, 256), (3001, 200)])
+def test_mixed_wide_n(m, n):
+    """n > 128 takes the 512-thread split product over K-step-tiled slices of Z: one BF16x3 pass at the
+    emulated error level, and BF16x3 + FP64 CholQR2 at FP64 orthogonality (ragged m and n included)."""
+    from oracle import mixed
+    a, z = dense_case(2, m, n, 1e4, 1e3, seed=8, kind="butterfly")
+    banner(f"mixed wide n m={m} n={n}")
+    qe, re, info, s = mixed.cholqr_pass(a, z, "bf16x3", shift_c=1.0)
+    assert info == 0
+    q, r = run_dense("cholqr", a, z, prec="bf16x3", shift_c=1.0)
+    le, lg = metrics.orth_loss(a, qe), metrics.orth_loss(a, q)
+    assert le / 10 <= lg <= 10 * le, (le, lg)
+    assert metrics.residual_f(z, q, r) <= 1e-12
+    q2, r2 = run_dense("cholqr2", a, z, pass1="bf16x3", pass2="fp64")
+    q0, r0 = reference.chol_eqr(a, z)
+    assert metrics.residual_f(z, q2, r2) <= 1e-12
+    assert metrics.orth_loss(a, q2) <= 1e-12
+    assert metrics.r_forward_error(r2, r0) <= 10 * n * U * np.linalg.cond(r0)
+
+
 def test_fully_mixed_cholqr2_meets_mixed_tolerance():
     """Both passes BF16x3: orthogonality <= max(1e-6, 10 u_p ||A|| ||Q||^2) with u_p = 2^-24."""
     a, z = dense_case(2, 1500, 40, 1e5, 1e3, seed=7, kind="butterfly")
