@@ -178,6 +178,16 @@ int oqr_gs(const oqr_op* A, const double* Z, int64_t ldz, int64_t m, int64_t n,
            double* Q, int64_t ldq, double* R, int64_t ldr, const oqr_opts* opts,
            void* ws, size_t ws_bytes, int32_t* info_dev, void* stream);
 
+/* Generalised least squares (Section 1): X = R^{-1} Q^T A B, the minimiser of
+ * ||Z x - b||_A for each column b of B, from an oblique QR (Q, R) of Z
+ * computed by any of the entry points above.  B: m x k (ldb >= m), X: n x k
+ * (ldx >= n), Q m x n, R n x n upper; all device memory, X must not overlap
+ * B, Q or R.  FP64.  Returns OQR_E_ARG for bad sizes or pointers. */
+size_t oqr_gls_workspace_bytes(const oqr_op* A, int64_t m, int64_t n, int64_t k);
+int oqr_gls(const oqr_op* A, const double* Q, int64_t ldq, const double* R, int64_t ldr, int64_t m, int64_t n,
+            const double* B, int64_t ldb, int64_t k, double* X, int64_t ldx, void* ws, size_t ws_bytes,
+            void* stream);
+
 /* Error measures of Section 7, computed on the device in FP64 (a report, not
  * a reference): out_dev[0] = ||I - Q^T A Q||_F (upper bound of the 2-norm
  * and within sqrt(n) of it), out_dev[1] = ||Z - Q R||_F / ||Z||_F. */

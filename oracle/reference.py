@@ -89,3 +89,33 @@ def oblique_qr(a_or_stencil, z: np.ndarray):
     if hasattr(a_or_stencil, "nx"):
         return stencil_eqr(a_or_stencil, z)
     return chol_eqr(a_or_stencil, z)
+
+
+def gls(a_or_stencil, z: np.ndarray, b: np.ndarray) -> np.ndarray:
+    """Generalised least squares (Section 1): x minimising ||Z x - b||_A.
+
+    Computed by whitening, independently of any oblique QR: with A = C^T C
+    (Cholesky; for the stencil, C = D^{1/2} S from the exact DST-I eigenbasis),
+    ||Z x - b||_A = ||C Z x - C b||_2, solved by LAPACK least squares.  b may hold
+    several right-hand sides as columns."""
+    z = np.asarray(z, dtype=np.float64)
+    b = np.asarray(b, dtype=np.float64)
+    vec = b.ndim == 1
+    if vec:
+        b = b[:, None]
+    if hasattr(a_or_stencil, "nx"):
+        st = a_or_stencil
+        lam = _st.eigenvalues(st)
+        shp = (st.nz, st.ny, st.nx)
+
+        def whiten(x):
+            out = np.empty_like(x)
+            for j in range(x.shape[1]):
+                out[:, j] = (np.sqrt(lam) * scipy.fft.dstn(x[:, j].reshape(shp), type=1, norm="ortho")).ravel()
+            return out
+        cz, cb = whiten(z), whiten(b)
+    else:
+        c = np.linalg.cholesky(np.asarray(a_or_stencil, dtype=np.float64)).T
+        cz, cb = c @ z, c @ b
+    x = np.linalg.lstsq(cz, cb, rcond=None)[0]
+    return x[:, 0] if vec else x

@@ -33,7 +33,7 @@ MAX_N = 256
 EXPORTS = (
     "oqr_default_opts", "oqr_workspace_bytes", "oqr_cholqr", "oqr_cholqr2", "oqr_pre_cholqr", "oqr_chol_a", "oqr_eig_a",
     "oqr_gs", "oqr_check", "oqr_batched_workspace_bytes", "oqr_cholqr2_batched", "oqr_batched_tile_count",
-    "oqr_status_string", "oqr_version", "oqr_trace_start", "oqr_trace_stop",
+    "oqr_status_string", "oqr_version", "oqr_trace_start", "oqr_trace_stop", "oqr_gls", "oqr_gls_workspace_bytes",
 )
 
 
@@ -79,6 +79,10 @@ def lib():
             f.restype = ctypes.c_int
         L.oqr_workspace_bytes.argtypes = [i32, ctypes.POINTER(_Op), i64, i64, ctypes.POINTER(_Opts)]
         L.oqr_workspace_bytes.restype = sz
+        L.oqr_gls.argtypes = [ctypes.POINTER(_Op), vp, i64, vp, i64, i64, i64, vp, i64, i64, vp, i64, vp, sz, vp]
+        L.oqr_gls.restype = ctypes.c_int
+        L.oqr_gls_workspace_bytes.argtypes = [ctypes.POINTER(_Op), i64, i64, i64]
+        L.oqr_gls_workspace_bytes.restype = sz
         L.oqr_check.argtypes = [ctypes.POINTER(_Op), vp, i64, i64, i64, vp, i64, vp, i64, vp, sz, vp, vp]
         L.oqr_check.restype = ctypes.c_int
         L.oqr_batched_workspace_bytes.argtypes = [i64, i32, i32, i32]
@@ -338,6 +342,30 @@ def eig_a(A, Z):
 def gs(A, Z, variant="cgs"):
     """Gram-Schmidt in the A inner product (cgs, mgs_row, mgs_col, cgs2): returns (Q, R)."""
     return _run("gs", A, Z, gs_variant=variant)
+
+
+def gls(A, Q, R, B):
+    """Generalised least squares (Section 1): X = R^{-1} Q^T A B minimises ||Z x - b||_A for every
+    column b of B, given the oblique QR (Q, R) of Z.  B may be a vector.  Returns X (n, k) or (n,)."""
+    torch = _torch()
+    op, m = make_op(A)
+    Q, R = colmajor(Q), colmajor(R)
+    vec = B.dim() == 1
+    Bm = colmajor(B[:, None] if vec else B)
+    n, k = Q.shape[1], Bm.shape[1]
+    if Q.shape[0] != m or R.shape != (n, n) or Bm.shape[0] != m:
+        raise ValueError("shapes of A, Q, R and B do not match")
+    X = torch.empty(k, n, dtype=torch.float64, device=Q.device).t()
+    L = lib()
+    nbytes = L.oqr_gls_workspace_bytes(ctypes.byref(op), m, n, k)
+    if nbytes == 0:
+        raise OQRError("gls workspace query failed")
+    ws = torch.empty(int(nbytes), dtype=torch.uint8, device=Q.device)
+    s = torch.cuda.current_stream(Q.device).cuda_stream
+    rc = L.oqr_gls(ctypes.byref(op), Q.data_ptr(), _ld(Q), R.data_ptr(), _ld(R), m, n, Bm.data_ptr(), _ld(Bm), k,
+                   X.data_ptr(), _ld(X), ws.data_ptr(), ws.numel(), s)
+    _raise(rc, "oqr_gls")
+    return X[:, 0] if vec else X
 
 
 def check(A, Z, Q, R):

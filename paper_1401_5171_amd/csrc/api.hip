@@ -59,6 +59,9 @@ int check_run(const oqr_op* A, const double* Z, int64_t ldz, int64_t m, int64_t 
 size_t gs_workspace_bytes(const oqr_op* A, int64_t m, int64_t n);
 int gs_run(const oqr_op* A, const double* Z, int64_t ldz, int64_t m, int64_t n, double* Q, int64_t ldq, double* R,
            int64_t ldr, int variant, void* ws, int32_t* info, hipStream_t s);
+size_t gls_workspace_bytes(const oqr_op* A, int64_t m, int64_t n, int64_t k);
+int gls_run(const oqr_op* A, const double* Q, int64_t ldq, const double* R, int64_t ldr, int64_t m, int64_t n,
+            const double* B, int64_t ldb, int64_t k, double* X, int64_t ldx, void* ws, hipStream_t s);
 size_t chol_a_workspace_bytes(int64_t m, int64_t n);
 int chol_a_run(const oqr_op* A, const double* Z, int64_t ldz, int64_t m, int64_t n, double* Q, int64_t ldq,
                double* R, int64_t ldr, void* ws, int32_t* info, hipStream_t s);
@@ -401,6 +404,23 @@ int oqr_eig_a(const oqr_op* A, const double* Z, int64_t ldz, int64_t m, int64_t 
   if (n == 0) return OQR_OK;
   if ((rc = ws_check(ws, ws_bytes, eig_a_workspace_bytes(m, n)))) return rc;
   return eig_a_run(A, Z, ldz, m, n, Q, ldq, R, ldr, ws, info_dev, s);
+}
+
+size_t oqr_gls_workspace_bytes(const oqr_op* A, int64_t m, int64_t n, int64_t k) {
+  if (!A || m < n || n < 1 || n > OQR_MAX_N || k < 0 || check_op(A, m) != OQR_OK) return 0;
+  return gls_workspace_bytes(A, m, n, k > 0 ? k : 1);
+}
+
+int oqr_gls(const oqr_op* A, const double* Q, int64_t ldq, const double* R, int64_t ldr, int64_t m, int64_t n,
+            const double* B, int64_t ldb, int64_t k, double* X, int64_t ldx, void* ws, size_t ws_bytes, void* stream) {
+  if (!A || !Q || !R || !B || !X) return OQR_E_ARG;
+  if (m < n || n < 1 || n > OQR_MAX_N || k < 0) return OQR_E_ARG;
+  if (ldq < m || ldr < n || ldb < m || ldx < n) return OQR_E_ARG;
+  if (check_op(A, m) != OQR_OK) return OQR_E_ARG;
+  if (k == 0) return OQR_OK;
+  int rc;
+  if ((rc = ws_check(ws, ws_bytes, gls_workspace_bytes(A, m, n, k)))) return rc;
+  return gls_run(A, Q, ldq, R, ldr, m, n, B, ldb, k, X, ldx, ws, (hipStream_t)stream);
 }
 
 int oqr_check(const oqr_op* A, const double* Z, int64_t ldz, int64_t m, int64_t n, const double* Q, int64_t ldq,

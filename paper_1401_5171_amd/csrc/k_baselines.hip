@@ -387,6 +387,54 @@ int gs_run(const oqr_op* A, const double* Z, int64_t ldz, int64_t m64, int64_t n
 }
 
 // =================================================================================================
+// Generalised least squares (Section 1): X = R^{-1} Q^T (A B)
+// =================================================================================================
+namespace {
+// X(:, c) = R^{-1} Y(:, c) by back-substitution, one thread per right-hand side.
+__global__ void back_subst_kernel(const double* __restrict__ R, int64_t ldr, int n, const double* __restrict__ Y,
+                                  int k, double* __restrict__ X, int64_t ldx) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= k) return;
+  const double* y = Y + (int64_t)c * n;
+  double* x = X + (int64_t)c * ldx;
+  for (int i = n - 1; i >= 0; --i) {
+    double s = y[i];
+    for (int j = i + 1; j < n; ++j) s -= R[(int64_t)j * ldr + i] * x[j];
+    x[i] = s / R[(int64_t)i * ldr + i];
+  }
+}
+}  // namespace
+
+size_t gls_workspace_bytes(const oqr_op* A, int64_t m, int64_t n, int64_t k) {
+  (void)A;
+  return align256((size_t)m * k * sizeof(double)) + align256((size_t)n * k * sizeof(double)) +
+         align256((size_t)ceil_div(m, CH) * n * sizeof(double));
+}
+
+int gls_run(const oqr_op* A, const double* Q, int64_t ldq, const double* R, int64_t ldr, int64_t m64, int64_t n64,
+            const double* B, int64_t ldb, int64_t k64, double* X, int64_t ldx, void* ws, hipStream_t s) {
+  const int m = (int)m64, n = (int)n64, k = (int)k64;
+  char* p = (char*)ws;
+  double* Wb = (double*)p;
+  p += align256((size_t)m * k * sizeof(double));
+  double* Y = (double*)p;
+  p += align256((size_t)n * k * sizeof(double));
+  double* part = (double*)p;
+  // W = A B
+  if (A->kind == OQR_OP_STENCIL7) {
+    OQR_TRY(launch_stencil_apply(A, B, ldb, Wb, m, k, s));
+  } else {
+    OQR_TRY(launch_gemm_f64((const double*)A->a, A->lda, B, ldb, Wb, m, m, k, nullptr, s));
+  }
+  // Y = Q^T W, column by column (chunked dot products summed in chunk order)
+  for (int c = 0; c < k; ++c)
+    OQR_TRY(cols_dot(Q, ldq, Wb + (int64_t)c * m, m, 0, m, n, part, Y + (int64_t)c * n, 1, 1.0, nullptr, s));
+  back_subst_kernel<<<ceil_div(k, 64), 64, 0, s>>>(R, ldr, n, Y, k, X, ldx);
+  OQR_TRY(hipGetLastError());
+  return OQR_OK;
+}
+
+// =================================================================================================
 // CHOL-EQR: C = chol(A) (blocked, upper), W = C Z, [Y, R] = qr(W), Q = C^{-1} Y
 // =================================================================================================
 namespace {

@@ -183,6 +183,47 @@ def test_gram_conventions_agree_when_the_gram_is_exact():
         variants.cholqr(a, z, gram="lower")
 
 
+# ---- generalised least squares (Section 1) --------------------------------------------------
+
+def test_gls_exact_when_b_is_in_the_range_of_z():
+    a, z = tiny(11, 30, 5, ka=1e3, kz=1e2)
+    xs = np.arange(1.0, 6.0)
+    x = reference.gls(a, z, z @ xs)
+    assert np.abs(x - xs).max() <= 100 * U * np.linalg.cond(z) * np.abs(xs).max()
+
+
+def test_gls_satisfies_the_normal_equations():
+    """Z^T A (Z x - b) = 0 (the A-orthogonality of the residual), and the definition's own formula
+    R^{-1} Q^T A b with (Q, R) from the 50-digit oblique QR."""
+    a, z = tiny(12, 24, 4, ka=1e4, kz=1e2)
+    b = np.random.default_rng(3).standard_normal((24, 2))
+    x = reference.gls(a, z, b)
+    g = z.T @ a @ (z @ x - b)
+    assert np.abs(g).max() <= 1e-9 * np.abs(z.T @ a @ b).max()
+    qe, re = exact.exact_oblique_qr(a, z)
+    xe = np.linalg.solve(re, qe.T @ a @ b)
+    assert np.abs(x - xe).max() <= 1e-9 * np.abs(xe).max()
+
+
+def test_gls_with_identity_is_ordinary_least_squares():
+    rng = np.random.default_rng(4)
+    z = rng.standard_normal((40, 6))
+    b = rng.standard_normal(40)
+    x = reference.gls(np.eye(40), z, b)
+    xo = np.linalg.pinv(z) @ b
+    assert np.abs(x - xo).max() <= 1e-12 * np.abs(xo).max()
+
+
+def test_gls_stencil_whitening_matches_dense():
+    st = W.laplacian7(5, 4, 3)
+    rng = np.random.default_rng(6)
+    z = rng.standard_normal((st.m, 4))
+    b = rng.standard_normal(st.m)
+    x1 = reference.gls(st, z, b)
+    x2 = reference.gls(stencil.dense(st), z, b)
+    assert np.abs(x1 - x2).max() <= 1e-10 * np.abs(x2).max()
+
+
 # ---- 4. the 7-point stencil ----------------------------------------------------------------
 
 def test_stencil_apply_matches_assembled_matrix():
