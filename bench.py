@@ -17,7 +17,7 @@ time taken from HIP events recorded around each launch inside the timed
 region.  The CPU baseline times the CPU oracle (CHOL-EQR, Algorithm 3) on the
 leading m' x m' sub-problem.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload dense32768|dense8192|stencil|batch]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload dense32768|dense8192|stencil|tridiag|batch]
 
 The batch workload (4096 independent instances, m log-uniform in [256, 4096], n in {8, 16, 32, 64},
 kappa(A_i) log-uniform in [1e2, 1e8], Gaussian Z_i) times one persistent launch of the batched
@@ -53,7 +53,7 @@ def parse():
     p.add_argument("--steps", type=int, default=10)
     p.add_argument("--warmup", type=int, default=3)
     p.add_argument("--workload", default="dense32768",
-                   choices=["dense32768", "dense8192", "stencil", "batch", "copycal"])
+                   choices=["dense32768", "dense8192", "stencil", "tridiag", "batch", "copycal"])
     p.add_argument("--batch-count", type=int, default=4096)
     p.add_argument("--batch-dtype", default="f64", choices=["f64", "f32"], help="storage type of the batch")
     p.add_argument("--tile", type=int, default=-1, help="batched tile id (-1: time every id, keep the best)")
@@ -82,6 +82,16 @@ def make_inputs(wl, torch):
                     seeds=f"SeedSequence([15171, {cfg}, 0])")
         flops = 2.0 * m * m * n + 2.0 * m * n * n
         return A, Z, z, m, n, desc, flops, "gemm_f64", 2.0 * m * m * n
+    if wl == "tridiag":
+        m, n = 100000, 64
+        t = W.laplacian1d(m, 1e-3)
+        z = W.tall_skinny(W.rng_for(6, 0), m, n, 1e3)
+        Z = torch.from_numpy(np.ascontiguousarray(z.T)).to(dev).t()
+        A = oqr.Tridiag(t.diag, t.sub, device=dev)
+        A.host = t
+        desc = dict(workload=f"tridiagonal A (1D Dirichlet Laplacian + 1e-3 I) m={m} n={n} kappa(Z)=1e3",
+                    m=m, n=n, operator="tridiag")
+        return A, Z, z, m, n, desc, 2.0 * m * n * n, "trsm", 1.0 * m * n * n
     nx, ny, nz, n = 128, 128, 64, 128
     st = W.laplacian7(nx, ny, nz)
     rng = W.rng_for(3, 0)
@@ -120,11 +130,47 @@ def breakdown(plan, Z, Q, R, torch):
     return out
 
 
+def time_variants(A, Z, m, n, flops, torch, reps=3):
+    """Every algorithm behind the ABI on the same input (the paper's performance comparison):
+    ms per factorisation (best of `reps`), GFLOP/s at the normalised count, orthogonality (F)."""
+    import paper_1401_5171_amd as oqr
+    out = {}
+    specs = [("cholqr", "cholqr", {}), ("cholqr2", "cholqr2", {}), ("pre_cholqr", "pre_cholqr", {}),
+             ("chol_eqr", "chol_a", {}), ("cgs", "gs", {"gs_variant": "cgs"}), ("cgs2", "gs", {"gs_variant": "cgs2"}),
+             ("mgs_row", "gs", {"gs_variant": "mgs_row"}), ("mgs_col", "gs", {"gs_variant": "mgs_col"})]
+    for name, alg, kw in specs:
+        plan = oqr.Plan(alg, A, n, **kw)
+        Q = torch.empty(n, m, dtype=torch.float64, device="cuda").t()
+        R = torch.empty(n, n, dtype=torch.float64, device="cuda").t()
+        plan.run(Z, Q, R)
+        torch.cuda.synchronize()
+        best = float("inf")
+        for _ in range(reps):
+            t0 = time.perf_counter()
+            plan.run(Z, Q, R)
+            torch.cuda.synchronize()
+            best = min(best, time.perf_counter() - t0)
+        orth, _ = oqr.check(A, Z, Q, R)
+        out[name] = {"ms": round(best * 1e3, 3), "gflops": round(flops / best / 1e9, 2), "orth_loss_fro": orth,
+                     "info": int(plan.info.item())}
+        log(f"variant {name}: {best * 1e3:.3f} ms, orth {orth:.2e}")
+    return out
+
+
 def cpu_baseline(A, z, n, ms, torch):
     """CPU oracle (CHOL-EQR) on the leading ms x ms block of A and the first ms rows of Z."""
     import numpy as np
     from threadpoolctl import threadpool_info
     from oracle import reference
+    if hasattr(A, "host"):
+        t = time.perf_counter()
+        reference.tridiag_eqr(A.host, np.asfortranarray(z))
+        dt = time.perf_counter() - t
+        f = 2.0 * A.m * n * n
+        sample = f"tridiag_eqr (banded CHOL-EQR) on the whole problem, m={A.m}, n={n}"
+        threads = max([i.get("num_threads", 1) for i in threadpool_info()] + [1])
+        return {"value": round(f / dt / 1e9, 3), "unit": "GFLOP/s", "cores": int(threads), "kind": "oracle",
+                "sample": sample, "seconds": round(dt, 3)}
     if hasattr(A, "nx"):
         from oracle import stencil as ost
         import workloads as W
@@ -304,7 +350,7 @@ def main():
     if args.workload == "copycal":
         return run_copycal(torch)
     A, Z, z_host, m, n, desc, flops, dom_kernel, dom_flops = make_inputs(args.workload, torch)
-    dense = not hasattr(A, "nx")
+    dense = not hasattr(A, "nx") and not hasattr(A, "host")
     pass1 = args.pass1 or ("bf16x3")
     Q = torch.empty(n, m, dtype=torch.float64, device="cuda").t()
     R = torch.empty(n, n, dtype=torch.float64, device="cuda").t()
@@ -333,7 +379,8 @@ def main():
     kernel_ms = mx["kernel_avg_ms"] if mx["kernel_launches"] else res["fp64"]["kernel_avg_ms"]
     achieved = dom_flops / (kernel_ms * 1e-3)
     peak = PEAK["fp64"]
-    roof = {"bound": "mfma", "kernel": dom_kernel + (" (FP64, pass 2)" if dense else " (stencil Gram)"),
+    label = " (FP64, pass 2)" if dense else (" (FP64 substitution)" if dom_kernel == "trsm" else " (stencil Gram)")
+    roof = {"bound": "mfma", "kernel": dom_kernel + label,
             "achieved": round(achieved / 1e12, 3), "peak": round(peak / 1e12, 1), "unit": "TFLOP/s",
             "frac": round(achieved / peak, 4), "traffic": TRAFFIC.get((args.workload, dom_kernel)),
             "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE/WRITE_SIZE, copy-calibrated)",
@@ -363,6 +410,8 @@ def main():
         "breakdown_ms": {"mixed": mx["breakdown_ms"], "fp64": res["fp64"]["breakdown_ms"]},
         "roofline": roof,
     }
+    if args.workload == "tridiag":
+        line["variants"] = time_variants(A, Z, m, n, flops, torch)
     if args.cpu_sample:
         log("timing the CPU oracle sample")
         line["cpu_baseline"] = cpu_baseline(A, z_host, n, min(args.cpu_sample, m), torch)

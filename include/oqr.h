@@ -56,7 +56,8 @@ typedef enum { OQR_F64 = 0, OQR_F32 = 1 } oqr_dtype;
 /* Kind of operator A. */
 typedef enum {
   OQR_OP_DENSE = 0,       /* explicit m x m symmetric matrix */
-  OQR_OP_STENCIL7 = 1     /* matrix-free 7-point operator on an nx x ny x nz grid */
+  OQR_OP_STENCIL7 = 1,    /* matrix-free 7-point operator on an nx x ny x nz grid */
+  OQR_OP_TRIDIAG = 2      /* symmetric tridiagonal matrix (the sparse workload of Section 8) */
 } oqr_op_kind;
 
 /* The operator A.
@@ -66,7 +67,10 @@ typedef enum {
  *            (A z)_p = center*z_p + off*(sum of z_q over the face neighbours
  *            q of p inside the grid) -- homogeneous Dirichlet boundary.  The
  *            Dirichlet 3D Laplacian (h = 1) plus s*I is center = 6 + s,
- *            off = -1.  a and lda are ignored. */
+ *            off = -1.  a and lda are ignored.
+ *   tridiag: a = device pointer to 2m-1 doubles, the diagonal d (m values)
+ *            followed by the off-diagonal e (m-1 values): A(i,i) = d_i,
+ *            A(i,i+1) = A(i+1,i) = e_i; lda must equal m (the offset of e). */
 typedef struct oqr_op {
   int32_t kind;
   int32_t dtype;
@@ -156,10 +160,11 @@ int oqr_pre_cholqr(const oqr_op* A, const double* Z, int64_t ldz, int64_t m, int
                    double* Q, int64_t ldq, double* R, int64_t ldr, const oqr_opts* opts,
                    void* ws, size_t ws_bytes, int32_t* info_dev, void* stream);
 
-/* CHOL-EQR (Algorithm 3, Section 4), dense A only: C = chol(A) upper
- * (A = C^T C), W = C Z, Householder [Y, R] = qr(W) with positive diag(R),
- * Q = C^{-1} Y.  info_dev = k if the k-th pivot of chol(A) failed
- * (no shift is applied to A).  FP64 throughout. */
+/* CHOL-EQR (Algorithm 3, Section 4), dense or tridiagonal A: C = chol(A)
+ * upper (A = C^T C; upper bidiagonal for a tridiagonal A), W = C Z,
+ * Householder [Y, R] = qr(W) with positive diag(R), Q = C^{-1} Y.
+ * info_dev = k if the k-th pivot of chol(A) failed (no shift is applied to
+ * A).  FP64 throughout.  Stencil operators: OQR_E_UNSUPPORTED. */
 int oqr_chol_a(const oqr_op* A, const double* Z, int64_t ldz, int64_t m, int64_t n,
                double* Q, int64_t ldq, double* R, int64_t ldr, const oqr_opts* opts,
                void* ws, size_t ws_bytes, int32_t* info_dev, void* stream);

@@ -84,10 +84,31 @@ def stencil_eqr(st, z: np.ndarray):
     return q, r
 
 
+def tridiag_eqr(t, z: np.ndarray):
+    """CHOL-EQR (Algorithm 3) for a symmetric tridiagonal A with banded primitives: C = the upper
+    bidiagonal Cholesky factor (A = C^T C, LAPACK pbtrf via scipy), W = C Z, [Y, R] = qr(W),
+    Q = C^{-1} Y by banded back-substitution."""
+    d = np.asarray(t.diag, dtype=np.float64)
+    e = np.asarray(t.sub, dtype=np.float64)
+    m = d.shape[0]
+    ab = np.zeros((2, m))
+    ab[0, 1:] = e                                  # upper form: superdiagonal, then diagonal
+    ab[1, :] = d
+    cb = scipy.linalg.cholesky_banded(ab, lower=False)
+    z = np.asarray(z, dtype=np.float64)
+    w = cb[1, :, None] * z
+    w[:-1] += cb[0, 1:, None] * z[1:]              # W = C Z (C upper bidiagonal)
+    y, r = householder_qr(w)
+    q = scipy.linalg.solve_banded((0, 1), cb, y)
+    return q, r
+
+
 def oblique_qr(a_or_stencil, z: np.ndarray):
-    """The oracle's answer (Q, R) for a dense SPD array or a Stencil7 descriptor."""
+    """The oracle's answer (Q, R) for a dense SPD array, a Stencil7 or a Tridiag descriptor."""
     if hasattr(a_or_stencil, "nx"):
         return stencil_eqr(a_or_stencil, z)
+    if hasattr(a_or_stencil, "sub"):
+        return tridiag_eqr(a_or_stencil, z)
     return chol_eqr(a_or_stencil, z)
 
 
@@ -103,6 +124,20 @@ def gls(a_or_stencil, z: np.ndarray, b: np.ndarray) -> np.ndarray:
     vec = b.ndim == 1
     if vec:
         b = b[:, None]
+    if hasattr(a_or_stencil, "sub"):
+        t = a_or_stencil
+        m = t.m
+        ab = np.zeros((2, m))
+        ab[0, 1:] = t.sub
+        ab[1, :] = t.diag
+        cb = scipy.linalg.cholesky_banded(ab, lower=False)
+
+        def cmul(x):
+            out = cb[1, :, None] * x
+            out[:-1] += cb[0, 1:, None] * x[1:]
+            return out
+        x = np.linalg.lstsq(cmul(z), cmul(b), rcond=None)[0]
+        return x[:, 0] if vec else x
     if hasattr(a_or_stencil, "nx"):
         st = a_or_stencil
         lam = _st.eigenvalues(st)

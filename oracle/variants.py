@@ -45,6 +45,9 @@ def _apply(a, x):
     if hasattr(a, "nx"):
         from . import stencil
         return stencil.apply(a, x)
+    if hasattr(a, "sub"):
+        from . import tridiag
+        return tridiag.apply(a, x)
     return a @ x
 
 

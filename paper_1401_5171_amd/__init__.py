@@ -24,7 +24,7 @@ LIB_PATH = os.path.join(_HERE, "liboqr.so")
 
 OQR_OK, OQR_E_ARG, OQR_E_NOT_SPD, OQR_E_HIP, OQR_E_WORKSPACE, OQR_E_UNSUPPORTED = range(6)
 OQR_F64, OQR_F32 = 0, 1
-OQR_OP_DENSE, OQR_OP_STENCIL7 = 0, 1
+OQR_OP_DENSE, OQR_OP_STENCIL7, OQR_OP_TRIDIAG = 0, 1, 2
 PREC = {"fp64": 0, "fp32": 1, "bf16x2": 2, "bf16x3": 3}
 GS = {"cgs": 0, "mgs_row": 1, "mgs_col": 2, "cgs2": 3}
 ALG = {"cholqr": 0, "cholqr2": 1, "chol_a": 2, "eig_a": 3, "gs": 4, "pre_cholqr": 5}
@@ -127,6 +127,22 @@ class Stencil7:
         return self.nx * self.ny * self.nz
 
 
+class Tridiag:
+    """Symmetric tridiagonal operator: A(i, i) = diag[i], A(i, i+1) = A(i+1, i) = sub[i].  The two
+    arrays (numpy or torch) are copied into one device buffer [diag, sub] (the layout of the C ABI)."""
+
+    def __init__(self, diag, sub, device=None):
+        torch = _torch()
+        d = torch.as_tensor(diag, dtype=torch.float64)
+        e = torch.as_tensor(sub, dtype=torch.float64)
+        if d.dim() != 1 or e.dim() != 1 or e.numel() != max(d.numel() - 1, 0) or d.numel() < 1:
+            raise ValueError("need diag (m,) and sub (m - 1,)")
+        dev = device or (d.device if d.is_cuda else torch.device("cuda", torch.cuda.current_device()))
+        self.buf = torch.cat([d.to(dev), e.to(dev)]).contiguous()
+        self.m = int(d.numel())
+        self.device = self.buf.device
+
+
 def _torch():
     import torch
     return torch
@@ -151,6 +167,10 @@ def _ld(x):
 def make_op(A) -> Tuple[_Op, int]:
     """oqr_op for a dense symmetric float64 tensor or a Stencil7; returns (op, m)."""
     op = _Op()
+    if isinstance(A, Tridiag):
+        op.kind, op.dtype = OQR_OP_TRIDIAG, OQR_F64
+        op.a, op.lda = A.buf.data_ptr(), A.m
+        return op, A.m
     if isinstance(A, Stencil7) or hasattr(A, "nx"):
         op.kind, op.dtype = OQR_OP_STENCIL7, OQR_F64
         op.nx, op.ny, op.nz = int(A.nx), int(A.ny), int(A.nz)

@@ -63,6 +63,9 @@ size_t gls_workspace_bytes(const oqr_op* A, int64_t m, int64_t n, int64_t k);
 int gls_run(const oqr_op* A, const double* Q, int64_t ldq, const double* R, int64_t ldr, int64_t m, int64_t n,
             const double* B, int64_t ldb, int64_t k, double* X, int64_t ldx, void* ws, hipStream_t s);
 size_t chol_a_workspace_bytes(int64_t m, int64_t n);
+size_t chol_a_tridiag_workspace_bytes(int64_t m, int64_t n);
+int chol_a_tridiag_run(const oqr_op* A, const double* Z, int64_t ldz, int64_t m, int64_t n, double* Q, int64_t ldq,
+                       double* R, int64_t ldr, void* ws, int32_t* info, hipStream_t s);
 int chol_a_run(const oqr_op* A, const double* Z, int64_t ldz, int64_t m, int64_t n, double* Q, int64_t ldq,
                double* R, int64_t ldr, void* ws, int32_t* info, hipStream_t s);
 size_t eig_a_workspace_bytes(int64_t m, int64_t n);
@@ -103,6 +106,9 @@ int check_op(const oqr_op* A, int64_t m) {
     if (A->dtype != OQR_F64) return OQR_E_UNSUPPORTED;
   } else if (A->kind == OQR_OP_STENCIL7) {
     if (A->nx < 1 || A->ny < 1 || A->nz < 1 || op_m(A) != m) return OQR_E_ARG;
+  } else if (A->kind == OQR_OP_TRIDIAG) {
+    if (!A->a || A->lda != m || m < 1) return OQR_E_ARG;
+    if (A->dtype != OQR_F64) return OQR_E_UNSUPPORTED;
   } else {
     return OQR_E_ARG;
   }
@@ -190,7 +196,7 @@ int cholqr_pass(const oqr_op* A, const double* Z, int64_t ldz, int64_t m, int64_
     }
     OQR_TRACED(K_GRAM, s, launch_gram_f64(Z, ldz, w.W, m, m, n, w.partial, w.G, s));
   } else {
-    OQR_TRACED(K_STENCIL, s, launch_stencil_apply(A, Z, ldz, w.W, m, n, s));
+    OQR_TRACED(K_STENCIL, s, launch_sparse_apply(A, Z, ldz, w.W, m, n, s));
     if (prec == OQR_P_FP64)
       OQR_TRACED(K_GRAM, s, launch_gram_f64(Z, ldz, w.W, m, m, n, w.partial, w.G, s));
     else
@@ -290,7 +296,9 @@ size_t oqr_workspace_bytes(int32_t alg, const oqr_op* A, int64_t m, int64_t n, c
   switch (alg) {
     case OQR_ALG_CHOLQR: return pass_ws(A, m, n, o, false, nullptr, nullptr);
     case OQR_ALG_CHOLQR2: return pass_ws(A, m, n, o, true, nullptr, nullptr);
-    case OQR_ALG_CHOL_A: return A->kind == OQR_OP_DENSE ? chol_a_workspace_bytes(m, n) : 0;
+    case OQR_ALG_CHOL_A:
+      return A->kind == OQR_OP_DENSE ? chol_a_workspace_bytes(m, n)
+                                     : A->kind == OQR_OP_TRIDIAG ? chol_a_tridiag_workspace_bytes(m, n) : 0;
     case OQR_ALG_EIG_A: return A->kind == OQR_OP_DENSE ? eig_a_workspace_bytes(m, n) : 0;
     case OQR_ALG_GS: return gs_workspace_bytes(A, m, n);
     case OQR_ALG_PRE_CHOLQR: return pre_ws(A, m, n, o);
@@ -381,12 +389,16 @@ int oqr_chol_a(const oqr_op* A, const double* Z, int64_t ldz, int64_t m, int64_t
                void* stream) {
   int rc = check_common(A, Z, ldz, m, n, Q, ldq, R, ldr, info_dev);
   if (rc) return rc;
-  if (A->kind != OQR_OP_DENSE) return OQR_E_UNSUPPORTED;
+  if (A->kind == OQR_OP_STENCIL7) return OQR_E_UNSUPPORTED;
   oqr_opts o;
   if ((rc = resolve_opts(opts, &o))) return rc;
   hipStream_t s = (hipStream_t)stream;
   if (launch_fill_i32(info_dev, 0, 1, s) != hipSuccess) return OQR_E_HIP;
   if (n == 0) return OQR_OK;
+  if (A->kind == OQR_OP_TRIDIAG) {
+    if ((rc = ws_check(ws, ws_bytes, chol_a_tridiag_workspace_bytes(m, n)))) return rc;
+    return chol_a_tridiag_run(A, Z, ldz, m, n, Q, ldq, R, ldr, ws, info_dev, s);
+  }
   if ((rc = ws_check(ws, ws_bytes, chol_a_workspace_bytes(m, n)))) return rc;
   return chol_a_run(A, Z, ldz, m, n, Q, ldq, R, ldr, ws, info_dev, s);
 }

@@ -125,8 +125,8 @@ hipError_t launch_gemm_split(const double* A, int64_t lda, const unsigned short*
 size_t split_z_elems(int64_t m, int64_t n, int slices);
 hipError_t launch_split_z(const double* Z, int64_t ldz, unsigned short* zs, int64_t m, int64_t n, int slices,
                           hipStream_t s);
-// W = A Z for the 7-point stencil (FP64).
-hipError_t launch_stencil_apply(const oqr_op* op, const double* Z, int64_t ldz, double* W, int64_t ldw,
+// W = A Z for a matrix-free operator (7-point stencil or tridiagonal), FP64.
+hipError_t launch_sparse_apply(const oqr_op* op, const double* Z, int64_t ldz, double* W, int64_t ldw,
                                 int64_t n, hipStream_t s);
 
 // Gram: partial[c] = (X^T Y) restricted to row chunk c, upper 64x64 tiles; then G = sum_c partial[c].

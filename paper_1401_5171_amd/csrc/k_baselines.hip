@@ -176,7 +176,7 @@ struct OpCtx {
 };
 
 hipError_t apply_vec(const OpCtx& op, const double* x, double* y, const int32_t* info, hipStream_t s) {
-  if (op.A->kind == OQR_OP_STENCIL7) return launch_stencil_apply(op.A, x, op.m, y, op.m, 1, s);
+  if (op.A->kind != OQR_OP_DENSE) return launch_sparse_apply(op.A, x, op.m, y, op.m, 1, s);
   const int nch = ceil_div(op.m, GKC);
   gemv_partial_kernel<<<dim3(ceil_div(op.m, NT), nch), NT, 0, s>>>((const double*)op.A->a, op.A->lda, x, op.m,
                                                                   op.gemv_partial, info);
@@ -421,8 +421,8 @@ int gls_run(const oqr_op* A, const double* Q, int64_t ldq, const double* R, int6
   p += align256((size_t)n * k * sizeof(double));
   double* part = (double*)p;
   // W = A B
-  if (A->kind == OQR_OP_STENCIL7) {
-    OQR_TRY(launch_stencil_apply(A, B, ldb, Wb, m, k, s));
+  if (A->kind != OQR_OP_DENSE) {
+    OQR_TRY(launch_sparse_apply(A, B, ldb, Wb, m, k, s));
   } else {
     OQR_TRY(launch_gemm_f64((const double*)A->a, A->lda, B, ldb, Wb, m, m, k, nullptr, s));
   }
@@ -643,6 +643,114 @@ int chol_a_run(const oqr_op* A, const double* Z, int64_t ldz, int64_t m64, int64
     back_block_kernel<<<ceil_div(n, 64), NT, 0, s>>>(C, m, m, b0, bb, Q, ldq, n, info);
     OQR_TRY(hipGetLastError());
   }
+  return OQR_OK;
+}
+
+// =================================================================================================
+// CHOL-EQR for a tridiagonal A: C upper bidiagonal (c_i on the diagonal, f_i above), A = C^T C
+// =================================================================================================
+namespace {
+
+// Pivots of the tridiagonal Cholesky (LDL^T form), sequential: p_0 = d_0, p_{i+1} = d_{i+1} - e_i^2 / p_i.
+// The reciprocal comes from v_rcp_f64 refined by two Newton steps (a short dependent chain).  info =
+// first pivot (1-based) that is not positive.
+__global__ void tridiag_pivots_kernel(const double* __restrict__ t, int m, double* __restrict__ p,
+                                      int32_t* __restrict__ info) {
+  if (threadIdx.x != 0 || blockIdx.x != 0 || info[0]) return;
+  double pi = t[0];
+  for (int i = 0; i < m; ++i) {
+    if (!(pi > 0.0)) {
+      info[0] = i + 1;
+      return;
+    }
+    p[i] = pi;
+    if (i + 1 < m) {
+      double r = __builtin_amdgcn_rcp(pi);
+      r = __builtin_fma(r, __builtin_fma(-pi, r, 1.0), r);
+      r = __builtin_fma(r, __builtin_fma(-pi, r, 1.0), r);
+      const double e = t[m + i];
+      pi = t[i + 1] - e * e * r;
+    }
+  }
+}
+
+// c_i = sqrt(p_i), rc_i = 1 / c_i, f_i = e_i / c_i
+__global__ void tridiag_factor_kernel(const double* __restrict__ t, const double* __restrict__ p, int m,
+                                      double* __restrict__ c, double* __restrict__ rc, double* __restrict__ f,
+                                      const int32_t* __restrict__ info) {
+  if (info[0]) return;
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= m) return;
+  const double ci = sqrt(p[i]), ri = 1.0 / ci;
+  c[i] = ci;
+  rc[i] = ri;
+  if (i + 1 < m) f[i] = t[m + i] * ri;
+}
+
+// W = C Z: w_i = c_i z_i + f_i z_{i+1}
+__global__ void bidiag_apply_kernel(const double* __restrict__ c, const double* __restrict__ f, int m,
+                                    const double* __restrict__ Z, int64_t ldz, double* __restrict__ W, int64_t ldw,
+                                    int n, const int32_t* __restrict__ info) {
+  if (info[0]) return;
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= (int64_t)m * n) return;
+  const int64_t j = idx / m;
+  const int i = (int)(idx % m);
+  const double* z = Z + j * ldz;
+  double w = c[i] * z[i];
+  if (i + 1 < m) w += f[i] * z[i + 1];
+  W[j * ldw + i] = w;
+}
+
+// Q = C^{-1} Y in place (Q holds Y): q_{m-1} = y_{m-1} / c_{m-1}, q_i = (y_i - f_i q_{i+1}) / c_i,
+// one thread per column.
+__global__ void bidiag_back_kernel(const double* __restrict__ rc, const double* __restrict__ f, int m,
+                                   double* __restrict__ Q, int64_t ldq, int n, const int32_t* __restrict__ info) {
+  if (info[0]) return;
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= n) return;
+  double* q = Q + (int64_t)j * ldq;
+  double next = q[m - 1] * rc[m - 1];
+  q[m - 1] = next;
+  for (int i = m - 2; i >= 0; --i) {
+    next = __builtin_fma(-f[i], next, q[i]) * rc[i];
+    q[i] = next;
+  }
+}
+
+}  // namespace
+
+size_t chol_a_tridiag_workspace_bytes(int64_t m, int64_t n) {
+  return align256((size_t)m * sizeof(double)) * 4 + align256((size_t)m * n * sizeof(double)) +
+         align256((size_t)(n + 8) * sizeof(double));
+}
+
+int chol_a_tridiag_run(const oqr_op* A, const double* Z, int64_t ldz, int64_t m64, int64_t n64, double* Q,
+                       int64_t ldq, double* R, int64_t ldr, void* ws, int32_t* info, hipStream_t s) {
+  const int m = (int)m64, n = (int)n64;
+  const double* t = (const double*)A->a;
+  char* p = (char*)ws;
+  auto take = [&](size_t bytes) {
+    char* r = p;
+    p += align256(bytes);
+    return (double*)r;
+  };
+  double* piv = take((size_t)m * sizeof(double));
+  double* c = take((size_t)m * sizeof(double));
+  double* rc = take((size_t)m * sizeof(double));
+  double* f = take((size_t)m * sizeof(double));
+  double* Wt = take((size_t)m * n * sizeof(double));
+  double* tau = take((size_t)(n + 8) * sizeof(double));
+  tridiag_pivots_kernel<<<1, 64, 0, s>>>(t, m, piv, info);
+  OQR_TRY(hipGetLastError());
+  tridiag_factor_kernel<<<ceil_div(m, 256), 256, 0, s>>>(t, piv, m, c, rc, f, info);
+  OQR_TRY(hipGetLastError());
+  const int64_t mn = (int64_t)m * n;
+  bidiag_apply_kernel<<<(unsigned)((mn + 255) / 256), 256, 0, s>>>(c, f, m, Z, ldz, Wt, m, n, info);
+  OQR_TRY(hipGetLastError());
+  OQR_TRY(householder_qr(Wt, m, m, n, tau, R, ldr, Q, ldq, s));
+  bidiag_back_kernel<<<ceil_div(n, 64), 64, 0, s>>>(rc, f, m, Q, ldq, n, info);
+  OQR_TRY(hipGetLastError());
   return OQR_OK;
 }
 

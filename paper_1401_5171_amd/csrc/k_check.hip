@@ -93,7 +93,7 @@ int check_run(const oqr_op* A, const double* Z, int64_t ldz, int64_t m, int64_t 
   if (A->kind == OQR_OP_DENSE)
     e = launch_gemm_f64((const double*)A->a, A->lda, Q, ldq, W, m, m, n, nullptr, s);
   else
-    e = launch_stencil_apply(A, Q, ldq, W, m, n, s);
+    e = launch_sparse_apply(A, Q, ldq, W, m, n, s);
   if (e != hipSuccess) return OQR_E_HIP;
   if (launch_gram_f64(Q, ldq, W, m, m, n, partial, G, s) != hipSuccess) return OQR_E_HIP;
   const int nb = ceil_div(m, NT);

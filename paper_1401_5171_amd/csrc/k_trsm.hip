@@ -354,10 +354,30 @@ hipError_t launch_trsm(const double* Z, int64_t ldz, const double* R, int64_t ld
   return hipGetLastError();
 }
 
-hipError_t launch_stencil_apply(const oqr_op* op, const double* Z, int64_t ldz, double* W, int64_t ldw, int64_t n,
-                                hipStream_t s) {
+// W = A Z for a symmetric tridiagonal A stored as t = [diagonal (m), off-diagonal (m - 1)].
+__global__ void tridiag_apply_kernel(const double* __restrict__ t, int64_t m, const double* __restrict__ Z,
+                                     int64_t ldz, double* __restrict__ W, int64_t ldw, int64_t n) {
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= m * n) return;
+  const int64_t j = idx / m, i = idx % m;
+  const double* z = Z + j * ldz;
+  double w = t[i] * z[i];
+  if (i > 0) w += t[m + i - 1] * z[i - 1];
+  if (i + 1 < m) w += t[m + i] * z[i + 1];
+  W[j * ldw + i] = w;
+}
+
+hipError_t launch_sparse_apply(const oqr_op* op, const double* Z, int64_t ldz, double* W, int64_t ldw, int64_t n,
+                               hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  if (op->kind == OQR_OP_TRIDIAG) {
+    const int64_t m = op->lda, total = m * n;
+    if (m == 0) return hipSuccess;
+    tridiag_apply_kernel<<<(unsigned)((total + 255) / 256), 256, 0, s>>>((const double*)op->a, m, Z, ldz, W, ldw, n);
+    return hipGetLastError();
+  }
   const int64_t sxy = (int64_t)op->nx * op->ny;
-  if (sxy == 0 || n == 0) return hipSuccess;
+  if (sxy == 0) return hipSuccess;
   if (sxy * op->nz * 8 > 0x7fffffffll) return hipErrorInvalidValue;   // 32-bit buffer offsets per column
   stencil_march_kernel<<<dim3((unsigned)((sxy + 255) / 256), (unsigned)n), 256, 0, s>>>(
       Z, ldz, W, ldw, op->nx, op->ny, op->nz, op->center, op->off);

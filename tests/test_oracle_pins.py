@@ -11,7 +11,7 @@ import numpy as np
 import pytest
 
 import workloads as W
-from oracle import exact, metrics, mixed, reference, stencil, variants
+from oracle import exact, metrics, mixed, reference, stencil, tridiag, variants
 
 U = 2.0 ** -53
 
@@ -181,6 +181,43 @@ def test_gram_conventions_agree_when_the_gram_is_exact():
     assert np.allclose(ru.T @ ru, z.T @ a @ z, rtol=1e-14, atol=0)
     with pytest.raises(ValueError):
         variants.cholqr(a, z, gram="lower")
+
+
+# ---- the tridiagonal operator (Section 8's sparse workload) ----------------------------------
+
+def test_tridiag_apply_matches_assembled_matrix():
+    rng = np.random.default_rng(8)
+    t = W.Tridiag(rng.uniform(3, 4, 30), rng.uniform(-1, 1, 29))
+    x = rng.standard_normal((30, 3))
+    assert np.allclose(tridiag.apply(t, x), tridiag.dense(t) @ x, rtol=0, atol=1e-14)
+    assert np.allclose(tridiag.apply(t, x[:, 0]), tridiag.dense(t) @ x[:, 0], rtol=0, atol=1e-14)
+
+
+def test_laplacian1d_eigenvalues_closed_form():
+    """Constant diagonal d and off-diagonal e: eigenvalues d + 2 e cos(pi k / (m + 1)), k = 1..m."""
+    t = W.laplacian1d(50, shift=1e-2)
+    lam = np.sort(2.01 - 2.0 * np.cos(np.pi * np.arange(1, 51) / 51))
+    assert np.allclose(np.linalg.eigvalsh(tridiag.dense(t)), lam, rtol=1e-13, atol=1e-14)
+
+
+def test_tridiag_eqr_matches_dense_route():
+    """The banded CHOL-EQR (bidiagonal factor, banded solve) against the dense CHOL-EQR."""
+    t = W.laplacian1d(200, shift=1e-2)
+    z = W.tall_skinny(W.rng_for(94), 200, 6, 1e2)
+    q, r = reference.tridiag_eqr(t, z)
+    q0, r0 = reference.chol_eqr(tridiag.dense(t), z)
+    kap = np.linalg.cond(r0)
+    assert metrics.r_forward_error(r, r0) <= 100 * 6 * U * kap
+    assert np.abs(q - q0).max() <= 100 * 6 * U * kap * np.abs(q0).max() * 20
+    assert metrics.orth_loss(t, q) <= 1e-13
+
+
+def test_gls_tridiag_matches_dense():
+    t = W.laplacian1d(60, shift=1e-1)
+    rng = np.random.default_rng(9)
+    z = rng.standard_normal((60, 5))
+    b = rng.standard_normal(60)
+    assert np.allclose(reference.gls(t, z, b), reference.gls(tridiag.dense(t), z, b), rtol=1e-10, atol=0)
 
 
 # ---- generalised least squares (Section 1) --------------------------------------------------

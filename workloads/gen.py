@@ -30,7 +30,7 @@ BASE_SEED = 15171
 __all__ = [
     "BASE_SEED", "rng_for", "logspace_to", "haar", "Butterfly", "butterfly",
     "spd_from_eigs", "spd_from_eigs_torch", "dense_spd", "dense_spd_device", "tall_skinny", "gaussian_scaled",
-    "paper_case", "Stencil7", "laplacian7", "BatchInstance", "batch_plan",
+    "paper_case", "Stencil7", "laplacian7", "Tridiag", "laplacian1d", "BatchInstance", "batch_plan",
     "batch_instance", "batch_instance_device", "CONFIGS",
 ]
 
@@ -260,6 +260,23 @@ class Stencil7:
 def laplacian7(nx: int, ny: int, nz: int, shift: float = 1e-3) -> Stencil7:
     """Dirichlet 7-point Laplacian (h = 1) plus shift * I."""
     return Stencil7(nx, ny, nz, 6.0 + shift, -1.0)
+
+
+@dataclasses.dataclass(frozen=True, eq=False)
+class Tridiag:
+    """Symmetric tridiagonal operator: A(i, i) = diag[i], A(i, i+1) = A(i+1, i) = sub[i]."""
+
+    diag: np.ndarray
+    sub: np.ndarray
+
+    @property
+    def m(self) -> int:
+        return int(self.diag.shape[0])
+
+
+def laplacian1d(m: int, shift: float = 1e-3) -> Tridiag:
+    """Dirichlet 1D Laplacian (h = 1) plus shift * I: diagonal 2 + shift, off-diagonal -1."""
+    return Tridiag(np.full(m, 2.0 + shift), np.full(max(m - 1, 0), -1.0))
 
 
 @dataclasses.dataclass(frozen=True)
