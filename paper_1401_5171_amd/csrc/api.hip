@@ -209,10 +209,10 @@ int cholqr_pass(const oqr_op* A, const double* Z, int64_t ldz, int64_t m, int64_
   return OQR_OK;
 }
 
-// PRE-CHOLQR workspace: one CholQR pass, then the Householder copy of Z, tau and U.
+// PRE-CHOLQR workspace: one CholQR pass, then the Householder copy of Z, U and the Euclidean QR's own.
 size_t pre_ws(const oqr_op* A, int64_t m, int64_t n, const oqr_opts& o) {
   return align256(pass_ws(A, m, n, o, false, nullptr, nullptr)) + align256((size_t)m * n * sizeof(double)) +
-         align256((size_t)(n + 8) * sizeof(double)) + align256((size_t)n * n * sizeof(double));
+         align256((size_t)n * n * sizeof(double)) + align256(euclid_qr_ws_bytes(m, n));
 }
 
 int resolve_opts(const oqr_opts* in, oqr_opts* out) {
@@ -338,11 +338,11 @@ int oqr_pre_cholqr(const oqr_op* A, const double* Z, int64_t ldz, int64_t m, int
   char* base = (char*)ws;
   const size_t pw = align256(pass_ws(A, m, n, o, false, &w, base));
   double* Wh = (double*)(base + pw);
-  double* tau = (double*)(base + pw + align256((size_t)m * n * sizeof(double)));
-  double* U = (double*)((char*)tau + align256((size_t)(n + 8) * sizeof(double)));
+  double* U = (double*)(base + pw + align256((size_t)m * n * sizeof(double)));
+  void* qr_ws = (char*)U + align256((size_t)n * n * sizeof(double));
   // Z = Y U (Householder, Euclidean product); Y goes to Q (Z has been copied, so Q may alias Z)
   if (launch_copy_matrix(Z, ldz, Wh, m, m, n, s) != hipSuccess) return OQR_E_HIP;
-  if (launch_householder_qr(Wh, m, m, n, tau, U, n, Q, ldq, s) != hipSuccess) return OQR_E_HIP;
+  if (launch_euclid_qr(Wh, m, m, n, qr_ws, U, n, Q, ldq, s) != hipSuccess) return OQR_E_HIP;
   // Y = Q S (CHOLQR-A), R = S U
   if ((rc = cholqr_pass(A, Q, ldq, m, n, Q, ldq, w.R1, n, o.pass1, o, w, w.shifts, info_dev, s))) return rc;
   if (launch_trmm_upper(w.R1, n, U, n, R, ldr, n, info_dev, s) != hipSuccess) return OQR_E_HIP;

@@ -151,6 +151,12 @@ hipError_t launch_trmm_upper(const double* R2, int64_t ld2, const double* R1, in
 // explicit orthonormal factor Y (m x n).  tau: n doubles.
 hipError_t launch_householder_qr(double* W, int64_t ldw, int64_t m, int64_t n, double* tau, double* R, int64_t ldr,
                                  double* Y, int64_t ldy, hipStream_t s);
+// Euclidean QR of W (m x n, m >= n, overwritten): U (n x n, positive diagonal) and the explicit
+// orthonormal factor Y (m x n).  A Householder TSQR tree for n <= 64, the column-by-column kernels
+// above; ws: euclid_qr_ws_bytes(m, n).
+size_t euclid_qr_ws_bytes(int64_t m, int64_t n);
+hipError_t launch_euclid_qr(double* W, int64_t ldw, int64_t m, int64_t n, void* ws, double* U, int64_t ldu, double* Y,
+                            int64_t ldy, hipStream_t s);
 hipError_t launch_copy_matrix(const double* X, int64_t ldx, double* Y, int64_t ldy, int64_t m, int64_t n,
                               hipStream_t s);
 hipError_t launch_fill_i32(int32_t* p, int32_t v, int64_t count, hipStream_t s);

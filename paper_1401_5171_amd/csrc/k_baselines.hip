@@ -603,7 +603,7 @@ size_t chol_a_workspace_bytes(int64_t m, int64_t n) {
   size_t b = 0;
   b += align256((size_t)m * m * sizeof(double));   // C
   b += align256((size_t)m * n * sizeof(double));   // W
-  b += align256((size_t)(n + 8) * sizeof(double)); // tau
+  b += align256(euclid_qr_ws_bytes(m, n));         // the Euclidean QR
   return b;
 }
 
@@ -615,7 +615,7 @@ int chol_a_run(const oqr_op* A, const double* Z, int64_t ldz, int64_t m64, int64
   p += align256((size_t)m * m * sizeof(double));
   double* W = (double*)p;
   p += align256((size_t)m * n * sizeof(double));
-  double* tau = (double*)p;
+  void* qr_ws = p;
   const int64_t mm = (int64_t)m * m;
   copy_upper_kernel<<<(unsigned)((mm + 255) / 256), 256, 0, s>>>((const double*)A->a, A->lda, C, m, m);
   OQR_TRY(hipGetLastError());
@@ -635,7 +635,7 @@ int chol_a_run(const oqr_op* A, const double* Z, int64_t ldz, int64_t m64, int64
   // W = C Z  (C upper, zero below the diagonal)
   OQR_TRY(launch_gemm_f64(C, m, Z, ldz, W, m, m, n, nullptr, s));
   // [Y, R] = qr(W): Y goes to Q
-  OQR_TRY(householder_qr(W, m, m, n, tau, R, ldr, Q, ldq, s));
+  OQR_TRY(launch_euclid_qr(W, m, m, n, qr_ws, R, ldr, Q, ldq, s));
   // Q = C^{-1} Y (block back-substitution from the bottom)
   const int nb = ceil_div(m, PB);
   for (int b = nb - 1; b >= 0; --b) {
@@ -722,7 +722,7 @@ __global__ void bidiag_back_kernel(const double* __restrict__ rc, const double* 
 
 size_t chol_a_tridiag_workspace_bytes(int64_t m, int64_t n) {
   return align256((size_t)m * sizeof(double)) * 4 + align256((size_t)m * n * sizeof(double)) +
-         align256((size_t)(n + 8) * sizeof(double));
+         align256(euclid_qr_ws_bytes(m, n));
 }
 
 int chol_a_tridiag_run(const oqr_op* A, const double* Z, int64_t ldz, int64_t m64, int64_t n64, double* Q,
@@ -740,7 +740,7 @@ int chol_a_tridiag_run(const oqr_op* A, const double* Z, int64_t ldz, int64_t m6
   double* rc = take((size_t)m * sizeof(double));
   double* f = take((size_t)m * sizeof(double));
   double* Wt = take((size_t)m * n * sizeof(double));
-  double* tau = take((size_t)(n + 8) * sizeof(double));
+  double* qr_ws = take(euclid_qr_ws_bytes(m, n));
   tridiag_pivots_kernel<<<1, 64, 0, s>>>(t, m, piv, info);
   OQR_TRY(hipGetLastError());
   tridiag_factor_kernel<<<ceil_div(m, 256), 256, 0, s>>>(t, piv, m, c, rc, f, info);
@@ -748,7 +748,7 @@ int chol_a_tridiag_run(const oqr_op* A, const double* Z, int64_t ldz, int64_t m6
   const int64_t mn = (int64_t)m * n;
   bidiag_apply_kernel<<<(unsigned)((mn + 255) / 256), 256, 0, s>>>(c, f, m, Z, ldz, Wt, m, n, info);
   OQR_TRY(hipGetLastError());
-  OQR_TRY(householder_qr(Wt, m, m, n, tau, R, ldr, Q, ldq, s));
+  OQR_TRY(launch_euclid_qr(Wt, m, m, n, qr_ws, R, ldr, Q, ldq, s));
   bidiag_back_kernel<<<ceil_div(n, 64), 64, 0, s>>>(rc, f, m, Q, ldq, n, info);
   OQR_TRY(hipGetLastError());
   return OQR_OK;
@@ -907,7 +907,7 @@ size_t eig_a_workspace_bytes(int64_t m, int64_t n) {
   b += align256((size_t)m * n * sizeof(double)) * 2;    // X/W, U
   b += align256((size_t)(m + 8) * sizeof(double));      // d
   b += align256((size_t)(m + 2) * sizeof(double));      // rotations (c, s) per pair
-  b += align256((size_t)(n + 8) * sizeof(double));      // tau
+  b += align256(euclid_qr_ws_bytes(m, n));              // the Euclidean QR
   b += align256(64);                                    // counters
   return b;
 }
@@ -928,7 +928,7 @@ int eig_a_run(const oqr_op* A, const double* Z, int64_t ldz, int64_t m64, int64_
   double* U = (double*)take((size_t)m * n * sizeof(double));
   double* d = (double*)take((size_t)(m + 8) * sizeof(double));
   double* cs = (double*)take((size_t)(m + 2) * sizeof(double));
-  double* tau = (double*)take((size_t)(n + 8) * sizeof(double));
+  void* qr_ws = take(euclid_qr_ws_bytes(m, n));
   int32_t* cnt = (int32_t*)take(64);          // [0] rotated, [1] done, [2] sweeps
   OQR_TRY(launch_copy_matrix((const double*)A->a, A->lda, Ac, m, m, m, s));
   eye_kernel<<<(unsigned)(((int64_t)m * m + 255) / 256), 256, 0, s>>>(V, m, m, m);
@@ -956,7 +956,7 @@ int eig_a_run(const oqr_op* A, const double* Z, int64_t ldz, int64_t m64, int64_
   const int64_t mn = (int64_t)m * n;
   diag_scale_kernel<<<(unsigned)((mn + 255) / 256), 256, 0, s>>>(X, m, m, n, d, 0, info);
   OQR_TRY(hipGetLastError());
-  OQR_TRY(householder_qr(X, m, m, n, tau, R, ldr, U, m, s));
+  OQR_TRY(launch_euclid_qr(X, m, m, n, qr_ws, R, ldr, U, m, s));
   diag_scale_kernel<<<(unsigned)((mn + 255) / 256), 256, 0, s>>>(U, m, m, n, d, 1, info);
   OQR_TRY(hipGetLastError());
   OQR_TRY(launch_gemm_f64(V, m, U, m, Q, ldq, m, n, nullptr, s));

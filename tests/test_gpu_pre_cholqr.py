@@ -100,3 +100,48 @@ def test_pre_cholqr_in_place():
     torch.cuda.synchronize()
     assert int(plan.info.item()) == 0
     check_against_oracle(a, z, to_host(Z), to_host(R))
+
+
+def identity_op(m):
+    """A = I as a tridiagonal operator (d = 1, e = 0): PRE-CHOLQR is then the Euclidean QR itself."""
+    return oqr.Tridiag(np.ones(m), np.zeros(m - 1))
+
+
+def lapack_qr(z):
+    qn, rn = np.linalg.qr(z)
+    sg = np.where(np.diag(rn) < 0, -1.0, 1.0)
+    return qn * sg, (rn.T * sg).T
+
+
+@pytest.mark.parametrize("m,n", [(1029, 64), (100000, 64), (70001, 16), (5000, 33), (3000, 1), (20000, 40),
+                                 (300, 64), (257, 64)])
+def test_euclidean_qr_tree_against_lapack(m, n):
+    """The Euclidean QR for n <= 64 is a tree of Householder QRs (blocks of 256-1024 rows, their
+    triangles stacked level by level): against LAPACK's QR of the same Z, sign-fixed, with one or
+    several levels, a last block with fewer rows than n (1029 = 4 * 256 + 5; 257), a single block
+    (300) and n = 1."""
+    z = W.tall_skinny(W.rng_for(75, m, n), m, n, 1e6 if n > 1 else 1.0)
+    qn, rn = lapack_qr(z)
+    banner(f"euclidean qr tree m={m} n={n}")
+    q, r = (to_host(x) for x in oqr.pre_cholqr(identity_op(m), to_dev_colmajor(z)))
+    bar = 100 * n * U * np.linalg.cond(rn)
+    assert metrics.r_forward_error(r, rn) <= bar
+    assert np.abs(q - qn).max() <= bar
+    assert np.linalg.norm(q.T @ q - np.eye(n)) <= 1e-13 * max(1, n / 8)
+    assert metrics.residual_f(z, q, r) <= 1e-13
+
+
+@pytest.mark.parametrize("m,n", [(3000, 8), (40000, 48)])
+def test_euclidean_qr_rank_deficient(m, n):
+    """A zero column and a repeated column: the Householder factor stays orthonormal (tau = 0 for the
+    zero column, as in LAPACK), Z = Q R holds, and the Cholesky step of PRE-CHOLQR sees Y^T Y = I."""
+    z = W.tall_skinny(W.rng_for(76, m, n), m, n, 1e2)
+    z[:, 3] = 0.0
+    z[:, 5] = z[:, 1]
+    banner(f"euclidean qr rank deficient m={m} n={n}")
+    Q, R = oqr.pre_cholqr(identity_op(m), to_dev_colmajor(z))
+    q, r = to_host(Q), to_host(R)
+    assert np.all(np.isfinite(q)) and np.all(np.isfinite(r))
+    assert np.linalg.norm(q.T @ q - np.eye(n)) <= 1e-13
+    assert metrics.residual_f(z, q, r) <= 1e-13
+    assert abs(r[3, 3]) <= 1e-13 * np.abs(r).max() and abs(r[5, 5]) <= 1e-13 * np.abs(r).max()
