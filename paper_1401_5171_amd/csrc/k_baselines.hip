@@ -9,6 +9,7 @@
 // O(m^3) products run on the FP64 MFMA kernels of the hot path where they fit.
 #include "common.hpp"
 
+#include <climits>
 #include <math.h>
 
 namespace oqr {
@@ -651,27 +652,154 @@ int chol_a_run(const oqr_op* A, const double* Z, int64_t ldz, int64_t m64, int64
 // =================================================================================================
 namespace {
 
-// Pivots of the tridiagonal Cholesky (LDL^T form), sequential: p_0 = d_0, p_{i+1} = d_{i+1} - e_i^2 / p_i.
-// The reciprocal comes from v_rcp_f64 refined by two Newton steps (a short dependent chain).  info =
-// first pivot (1-based) that is not positive.
-__global__ void tridiag_pivots_kernel(const double* __restrict__ t, int m, double* __restrict__ p,
-                                      int32_t* __restrict__ info) {
-  if (threadIdx.x != 0 || blockIdx.x != 0 || info[0]) return;
-  double pi = t[0];
-  for (int i = 0; i < m; ++i) {
-    if (!(pi > 0.0)) {
-      info[0] = i + 1;
-      return;
+// Pivots of the tridiagonal Cholesky (LDL^T form): p_0 = d_0, p_i = d_i - e_{i-1}^2 / p_{i-1}.  The
+// recurrence is evaluated in chunks of TK pivots: each map p -> d - e^2 / p is the 2 x 2 matrix
+// [d, -e^2; 1, 0] acting on homogeneous (x, y) with p = x / y, so (1) every chunk forms the product of
+// its maps (one wave per chunk, a product tree over the lanes), (2) one workgroup scans these products
+// to the homogeneous start value of every chunk, (3) every chunk runs the recurrence itself from its
+// start.  Products are rescaled by powers of two (exact).  info = first pivot (1-based) that is not
+// positive.
+constexpr int TK = 256;
+constexpr int SCAN_NT = 1024;
+
+struct M2 {
+  double a, b, c, d;   // [a b; c d]
+};
+
+__device__ __forceinline__ M2 m2_mul(const M2& x, const M2& y) {   // x * y
+  return {fma(x.a, y.a, x.b * y.c), fma(x.a, y.b, x.b * y.d), fma(x.c, y.a, x.d * y.c), fma(x.c, y.b, x.d * y.d)};
+}
+
+__device__ __forceinline__ M2 m2_norm(M2 x) {
+  const double mx = fmax(fmax(fabs(x.a), fabs(x.b)), fmax(fabs(x.c), fabs(x.d)));
+  if (mx == 0.0 || !isfinite(mx)) return x;
+  const int ex = ilogb(mx);
+  return {ldexp(x.a, -ex), ldexp(x.b, -ex), ldexp(x.c, -ex), ldexp(x.d, -ex)};
+}
+
+__device__ __forceinline__ M2 m2_shfl_down(const M2& x, int o) {
+  return {__shfl_down(x.a, o), __shfl_down(x.b, o), __shfl_down(x.c, o), __shfl_down(x.d, o)};
+}
+
+// F[k] = M_{s+TK} ... M_{s+1} for chunk k (s = k TK), k < nch - 1.  One wave per chunk; lane l owns
+// maps s + 1 + 4l .. s + 4 + 4l.
+__global__ __launch_bounds__(64) void tridiag_chunk_maps_kernel(const double* __restrict__ t, int m, int nch,
+                                                                double* __restrict__ F,
+                                                                const int32_t* __restrict__ info) {
+  const int k = blockIdx.x, l = threadIdx.x;
+  if (info[0] || k >= nch - 1) return;
+  const int i0 = k * TK + 1 + 4 * l;   // <= m - 1: chunk k + 1 exists
+  M2 P = {1.0, 0.0, 0.0, 1.0};
+#pragma unroll
+  for (int u = 0; u < 4; ++u) {
+    const double di = t[i0 + u], e = t[m + i0 + u - 1];
+    P = m2_norm(m2_mul({di, -e * e, 1.0, 0.0}, P));
+  }
+  // ordered product over the lanes: later lanes on the left
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const M2 Q = m2_shfl_down(P, o);
+    if ((l & (2 * o - 1)) == 0) P = m2_norm(m2_mul(Q, P));
+  }
+  if (l == 0) {
+    F[4 * k] = P.a;
+    F[4 * k + 1] = P.b;
+    F[4 * k + 2] = P.c;
+    F[4 * k + 3] = P.d;
+  }
+}
+
+// xy[k] = homogeneous start of chunk k: (F_{k-1} ... F_0)(d_0, 1).  One workgroup: each thread composes
+// a run of chunk maps, a scan over the threads in LDS gives every run its prefix, the runs are then
+// walked again.
+__global__ __launch_bounds__(SCAN_NT) void tridiag_chunk_starts_kernel(const double* __restrict__ t, int nch,
+                                                                      const double* __restrict__ F,
+                                                                      double* __restrict__ xy,
+                                                                      const int32_t* __restrict__ info) {
+  __shared__ M2 S[SCAN_NT];
+  if (info[0]) return;
+  const int tid = threadIdx.x;
+  const int per = (nch + SCAN_NT - 1) / SCAN_NT;
+  const int k0 = min(nch, tid * per), k1 = min(nch, k0 + per);
+  auto fmap = [&](int k) -> M2 {   // the map from chunk k's start to chunk k + 1's start
+    if (k >= nch - 1) return {1.0, 0.0, 0.0, 1.0};
+    return {F[4 * k], F[4 * k + 1], F[4 * k + 2], F[4 * k + 3]};
+  };
+  M2 G = {1.0, 0.0, 0.0, 1.0};
+  for (int k = k0; k < k1; ++k) G = m2_norm(m2_mul(fmap(k), G));
+  S[tid] = G;
+  __syncthreads();
+  for (int o = 1; o < SCAN_NT; o <<= 1) {
+    M2 v = S[tid];
+    if (tid >= o) v = m2_norm(m2_mul(v, S[tid - o]));
+    __syncthreads();
+    S[tid] = v;
+    __syncthreads();
+  }
+  double x = t[0], y = 1.0;
+  if (tid > 0) {
+    const M2 E = S[tid - 1];
+    const double nx = fma(E.a, x, E.b * y), ny = fma(E.c, x, E.d * y);
+    x = nx;
+    y = ny;
+  }
+  for (int k = k0; k < k1; ++k) {
+    xy[2 * k] = x;
+    xy[2 * k + 1] = y;
+    const M2 Fk = fmap(k);
+    double nx = fma(Fk.a, x, Fk.b * y), ny = fma(Fk.c, x, Fk.d * y);
+    const double mx = fmax(fabs(nx), fabs(ny));
+    if (mx != 0.0 && isfinite(mx)) {
+      const int ex = ilogb(mx);
+      nx = ldexp(nx, -ex);
+      ny = ldexp(ny, -ex);
     }
-    p[i] = pi;
-    if (i + 1 < m) {
-      double r = __builtin_amdgcn_rcp(pi);
-      r = __builtin_fma(r, __builtin_fma(-pi, r, 1.0), r);
-      r = __builtin_fma(r, __builtin_fma(-pi, r, 1.0), r);
-      const double e = t[m + i];
-      pi = t[i + 1] - e * e * r;
+    x = nx;
+    y = ny;
+  }
+}
+
+__global__ void tridiag_chunk_pivots_kernel(const double* __restrict__ t, int m, int nch,
+                                            const double* __restrict__ xy, double* __restrict__ p,
+                                            int32_t* __restrict__ fail, const int32_t* __restrict__ info) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (info[0] || k >= nch) return;
+  const int s0 = k * TK, s1 = min(m, s0 + TK);
+  double pi = xy[2 * k] / xy[2 * k + 1];
+  int32_t f = 0;
+  for (int i0 = s0; i0 < s1 && !f; i0 += 16) {
+    double dn[16], en[16];
+#pragma unroll
+    for (int u = 0; u < 16; ++u) {   // d_{i+1}, e_i (clamped into the array; used only when i + 1 < m)
+      const int i = (m >= 2) ? min(i0 + u, m - 2) : -1;
+      dn[u] = t[i + 1];
+      en[u] = t[(m >= 2) ? m + i : 0];
+    }
+#pragma unroll
+    for (int u = 0; u < 16; ++u) {
+      const int i = i0 + u;
+      if (i >= s1 || f) break;
+      if (!(pi > 0.0)) {
+        f = i + 1;
+        break;
+      }
+      p[i] = pi;
+      if (i + 1 < m) pi = dn[u] - en[u] * en[u] / pi;
     }
   }
+  fail[k] = f;
+}
+
+// info = the failed pivot of the first chunk that has one (chunks after a failure carry meaningless
+// starts, so only the first one counts).  One wave.
+__global__ __launch_bounds__(64) void tridiag_first_fail_kernel(const int32_t* __restrict__ fail, int nch,
+                                                                int32_t* __restrict__ info) {
+  if (info[0]) return;
+  int kmin = INT_MAX;
+  for (int k = threadIdx.x; k < nch; k += 64)
+    if (fail[k] && k < kmin) kmin = k;
+  for (int o = 32; o > 0; o >>= 1) kmin = min(kmin, __shfl_xor(kmin, o));
+  if (threadIdx.x == 0 && kmin != INT_MAX) info[0] = fail[kmin];
 }
 
 // c_i = sqrt(p_i), rc_i = 1 / c_i, f_i = e_i / c_i
@@ -702,27 +830,103 @@ __global__ void bidiag_apply_kernel(const double* __restrict__ c, const double* 
   W[j * ldw + i] = w;
 }
 
-// Q = C^{-1} Y in place (Q holds Y): q_{m-1} = y_{m-1} / c_{m-1}, q_i = (y_i - f_i q_{i+1}) / c_i,
-// one thread per column.
-__global__ void bidiag_back_kernel(const double* __restrict__ rc, const double* __restrict__ f, int m,
-                                   double* __restrict__ Q, int64_t ldq, int n, const int32_t* __restrict__ info) {
-  if (info[0]) return;
-  const int j = blockIdx.x * blockDim.x + threadIdx.x;
-  if (j >= n) return;
+// Q = C^{-1} Y in place (Q holds Y): q_i = a_i + b_i q_{i+1} with a_i = y_i / c_i, b_i = -f_i / c_i
+// (q_m = 0), in chunks of TK rows: (1) per chunk and column the chunk's own solution with q = 0 past
+// its end, and the coefficient B_i = b_i ... b_end of the value past the end (the same for every
+// column); (2) per column, the values at the chunk starts, last chunk first; (3) q_i += B_i q_next.
+__global__ void bidiag_back_local_kernel(const double* __restrict__ rc, const double* __restrict__ f, int m, int nch,
+                                         double* __restrict__ Q, int64_t ldq, int n, double* __restrict__ Bc,
+                                         const int32_t* __restrict__ info) {
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (info[0] || idx >= (int64_t)nch * n) return;
+  const int k = (int)(idx % nch), j = (int)(idx / nch);
+  const int s0 = k * TK, s1 = min(m, s0 + TK);
   double* q = Q + (int64_t)j * ldq;
-  double next = q[m - 1] * rc[m - 1];
-  q[m - 1] = next;
-  for (int i = m - 2; i >= 0; --i) {
-    next = __builtin_fma(-f[i], next, q[i]) * rc[i];
-    q[i] = next;
+  double a = 0.0, B = 1.0;
+  for (int i1 = s1; i1 > s0; i1 -= 16) {   // rows i1 - 1 down to max(s0, i1 - 16)
+    double rv[16], fv[16], qv[16];
+#pragma unroll
+    for (int u = 0; u < 16; ++u) {
+      const int i = max(i1 - 1 - u, s0);
+      rv[u] = rc[i];
+      fv[u] = f[min(i, m - 2 >= 0 ? m - 2 : 0)];
+      qv[u] = q[i];
+    }
+#pragma unroll
+    for (int u = 0; u < 16; ++u) {
+      const int i = i1 - 1 - u;
+      if (i < s0) break;
+      const double bi = (i + 1 < m) ? -fv[u] * rv[u] : 0.0;
+      a = fma(bi, a, qv[u] * rv[u]);
+      B *= bi;
+      q[i] = a;
+      if (j == 0) Bc[i] = B;
+    }
   }
+}
+
+// qn[j][k] = q_j at the start of chunk k + 1 (0 past the end): V_k = a_k + B_k V_{k+1} over the chunk
+// starts, as a scan of affine maps over one workgroup per column.
+__global__ __launch_bounds__(SCAN_NT) void bidiag_back_starts_kernel(const double* __restrict__ Bc, int m, int nch,
+                                                                    const double* __restrict__ Q, int64_t ldq, int n,
+                                                                    double* __restrict__ qn,
+                                                                    const int32_t* __restrict__ info) {
+  __shared__ double Sa[SCAN_NT], Sb[SCAN_NT];
+  const int j = blockIdx.x;
+  if (info[0] || j >= n) return;
+  const double* q = Q + (int64_t)j * ldq;
+  const int tid = threadIdx.x;
+  const int per = (nch + SCAN_NT - 1) / SCAN_NT;
+  // position kk walks the chunks from the last (kk = 0) to the first; g_kk(x) = a + b x
+  const int kk0 = min(nch, tid * per), kk1 = min(nch, kk0 + per);
+  double ga = 0.0, gb = 1.0;   // composite of this thread's maps, later ones outside
+  for (int kk = kk0; kk < kk1; ++kk) {
+    const int s0 = (nch - 1 - kk) * TK;
+    const double a = q[s0], b = Bc[s0];
+    ga = fma(b, ga, a);
+    gb = b * gb;
+  }
+  Sa[tid] = ga;
+  Sb[tid] = gb;
+  __syncthreads();
+  for (int o = 1; o < SCAN_NT; o <<= 1) {
+    double va = Sa[tid], vb = Sb[tid];
+    if (tid >= o) {
+      va = fma(vb, Sa[tid - o], va);
+      vb = vb * Sb[tid - o];
+    }
+    __syncthreads();
+    Sa[tid] = va;
+    Sb[tid] = vb;
+    __syncthreads();
+  }
+  double x = (tid > 0) ? Sa[tid - 1] : 0.0;   // V past this run (applied to V = 0 past the end)
+  for (int kk = kk0; kk < kk1; ++kk) {
+    const int k = nch - 1 - kk, s0 = k * TK;
+    qn[(int64_t)j * nch + k] = x;
+    x = fma(Bc[s0], x, q[s0]);
+  }
+}
+
+__global__ void bidiag_back_fix_kernel(const double* __restrict__ Bc, int m, int nch, double* __restrict__ Q,
+                                       int64_t ldq, int n, const double* __restrict__ qn,
+                                       const int32_t* __restrict__ info) {
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (info[0] || idx >= (int64_t)m * n) return;
+  const int64_t j = idx / m;
+  const int i = (int)(idx % m);
+  const double nx = qn[j * nch + i / TK];
+  if (nx != 0.0) Q[j * ldq + i] = fma(Bc[i], nx, Q[j * ldq + i]);
 }
 
 }  // namespace
 
 size_t chol_a_tridiag_workspace_bytes(int64_t m, int64_t n) {
+  const int64_t nch = (m + TK - 1) / TK;
   return align256((size_t)m * sizeof(double)) * 4 + align256((size_t)m * n * sizeof(double)) +
-         align256(euclid_qr_ws_bytes(m, n));
+         align256(euclid_qr_ws_bytes(m, n)) + align256((size_t)nch * 4 * sizeof(double)) +
+         align256((size_t)nch * 2 * sizeof(double)) + align256((size_t)nch * sizeof(int32_t)) +
+         align256((size_t)nch * n * sizeof(double));
 }
 
 int chol_a_tridiag_run(const oqr_op* A, const double* Z, int64_t ldz, int64_t m64, int64_t n64, double* Q,
@@ -741,7 +945,20 @@ int chol_a_tridiag_run(const oqr_op* A, const double* Z, int64_t ldz, int64_t m6
   double* f = take((size_t)m * sizeof(double));
   double* Wt = take((size_t)m * n * sizeof(double));
   double* qr_ws = take(euclid_qr_ws_bytes(m, n));
-  tridiag_pivots_kernel<<<1, 64, 0, s>>>(t, m, piv, info);
+  const int nch = ceil_div(m, TK);
+  double* F = take((size_t)nch * 4 * sizeof(double));
+  double* p0 = take((size_t)nch * 2 * sizeof(double));   // homogeneous chunk starts
+  int32_t* fail = (int32_t*)take((size_t)nch * sizeof(int32_t));
+  double* qn = take((size_t)nch * n * sizeof(double));
+  if (nch > 1) {
+    tridiag_chunk_maps_kernel<<<nch - 1, 64, 0, s>>>(t, m, nch, F, info);
+    OQR_TRY(hipGetLastError());
+  }
+  tridiag_chunk_starts_kernel<<<1, SCAN_NT, 0, s>>>(t, nch, F, p0, info);
+  OQR_TRY(hipGetLastError());
+  tridiag_chunk_pivots_kernel<<<ceil_div(nch, 64), 64, 0, s>>>(t, m, nch, p0, piv, fail, info);
+  OQR_TRY(hipGetLastError());
+  tridiag_first_fail_kernel<<<1, 64, 0, s>>>(fail, nch, info);
   OQR_TRY(hipGetLastError());
   tridiag_factor_kernel<<<ceil_div(m, 256), 256, 0, s>>>(t, piv, m, c, rc, f, info);
   OQR_TRY(hipGetLastError());
@@ -749,7 +966,12 @@ int chol_a_tridiag_run(const oqr_op* A, const double* Z, int64_t ldz, int64_t m6
   bidiag_apply_kernel<<<(unsigned)((mn + 255) / 256), 256, 0, s>>>(c, f, m, Z, ldz, Wt, m, n, info);
   OQR_TRY(hipGetLastError());
   OQR_TRY(launch_euclid_qr(Wt, m, m, n, qr_ws, R, ldr, Q, ldq, s));
-  bidiag_back_kernel<<<ceil_div(n, 64), 64, 0, s>>>(rc, f, m, Q, ldq, n, info);
+  double* Bc = piv;   // the pivots are no longer needed
+  bidiag_back_local_kernel<<<ceil_div((int64_t)nch * n, 64), 64, 0, s>>>(rc, f, m, nch, Q, ldq, n, Bc, info);
+  OQR_TRY(hipGetLastError());
+  bidiag_back_starts_kernel<<<n, SCAN_NT, 0, s>>>(Bc, m, nch, Q, ldq, n, qn, info);
+  OQR_TRY(hipGetLastError());
+  bidiag_back_fix_kernel<<<(unsigned)((mn + 255) / 256), 256, 0, s>>>(Bc, m, nch, Q, ldq, n, qn, info);
   OQR_TRY(hipGetLastError());
   return OQR_OK;
 }

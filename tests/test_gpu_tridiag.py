@@ -62,11 +62,23 @@ def test_tridiag_chol_eqr():
     assert np.abs(q - q0).max() <= 100 * 24 * U * np.linalg.cond(r0) * np.abs(q0).max() * 10
 
 
-def test_tridiag_chol_eqr_reports_the_failing_pivot():
-    d = np.full(300, 2.001)
-    d[150] = -1.0
-    t = W.Tridiag(d, np.full(299, -1.0))
-    z = np.zeros((300, 3), order="F")
+def test_tridiag_chol_eqr_large_m():
+    """m = 100000: the pivot recurrence and the bidiagonal back-substitution run in chunks of rows
+    (391 of them) joined by the chunk-to-chunk maps."""
+    t, z = case(100000, 16, seed=5)
+    q0, r0 = reference.tridiag_eqr(t, z)
+    banner("tridiag chol_a m=100000")
+    q, r = (to_host(x) for x in oqr.chol_a(op(t), to_dev_colmajor(z)))
+    stable_checks(t, z, q, r, r0)
+    assert np.abs(q - q0).max() <= 100 * 16 * U * np.linalg.cond(r0) * np.abs(q0).max() * 10
+
+
+@pytest.mark.parametrize("m,bad", [(300, 150), (3000, 1000), (3000, 2999)])
+def test_tridiag_chol_eqr_reports_the_failing_pivot(m, bad):
+    d = np.full(m, 2.001)
+    d[bad] = -1.0
+    t = W.Tridiag(d, np.full(m - 1, -1.0))
+    z = np.zeros((m, 3), order="F")
     z[0, 0] = z[1, 1] = z[2, 2] = 1.0
     plan = oqr.Plan("chol_a", op(t), 3)
     with pytest.raises(oqr.OQRError) as e:
@@ -103,3 +115,18 @@ def test_tridiag_single_row():
     z = np.array([[3.0]])
     q, r = (to_host(x) for x in oqr.cholqr2(op(t), to_dev_colmajor(z)))
     assert abs(r[0, 0] - 6.0) <= 4 * U * 6 and abs(q[0, 0] - 0.5) <= 4 * U
+
+
+@pytest.mark.parametrize("m", [1, 2, 257, 512, 513])
+def test_tridiag_chol_eqr_chunk_edges(m):
+    """CHOL-EQR at sizes around the 256-row chunks of its recurrences (one row, a last chunk of one row,
+    exact multiples)."""
+    t = W.laplacian1d(m, 1e-1)
+    n = min(m, 4)
+    z = W.tall_skinny(W.rng_for(96, m), m, n, 10.0 if n > 1 else 1.0)
+    q0, r0 = reference.tridiag_eqr(t, z)
+    banner(f"tridiag chol_a m={m}")
+    q, r = (to_host(x) for x in oqr.chol_a(op(t), to_dev_colmajor(z)))
+    assert metrics.residual_f(z, q, r) <= 1e-13
+    assert metrics.orth_loss(t, q) <= 1e-13
+    assert metrics.r_forward_error(r, r0) <= 100 * n * U * np.linalg.cond(r0) * 10
