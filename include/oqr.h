@@ -27,8 +27,11 @@
  *   - Q may alias Z (same pointer and ld): the triangular solve is done in
  *     place.  No other aliasing is allowed (A, R, ws, info distinct).
  *   - R is written in full: strictly lower triangle set to 0.
- *   - Only the upper triangle of dense A need be symmetric-consistent: the
- *     kernels read the whole of A and assume A = A^T.
+ *   - Dense A must be stored in full and symmetric (A = A^T).  The FP64
+ *     CholQR passes read only its upper block triangle (the blocks of 64 rows
+ *     on and above the diagonal) and form Z^T A Z = Z^T (U + D) Z + (U Z)^T Z
+ *     with U the strictly upper blocks and D the diagonal ones; the other
+ *     entry points read the whole of A.
  */
 #ifndef OQR_H
 #define OQR_H
@@ -234,7 +237,8 @@ int oqr_batched_tile_count(void);
 
 /* Timing aid: from oqr_trace_start(name) until oqr_trace_stop, every launch
  * of the named kernel ("gemm_f64", "gemm_split", "gram", "chol", "trsm",
- * "stencil", "split_z", "batch") made by this process is bracketed by a pair of HIP
+ * "stencil", "split_z", "batch", "symm_diag") made by this process is
+ * bracketed by a pair of HIP
  * events recorded on its stream (events are created on first use and reused).
  * oqr_trace_stop waits for the recorded events and returns the summed kernel
  * time in milliseconds and the number of launches.  Not thread-safe; do not

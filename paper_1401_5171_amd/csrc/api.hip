@@ -20,8 +20,9 @@ struct TraceState {
 };
 TraceState g_trace;
 
-const char* const kKernelNames[] = {"", "gemm_f64", "gemm_split", "gram", "chol", "trsm", "stencil", "split_z", "batch"};
-constexpr int kNumKernels = 9;
+const char* const kKernelNames[] = {"",        "gemm_f64", "gemm_split", "gram",  "chol",     "trsm",
+                                    "stencil", "split_z",  "batch",      "symm_diag"};
+constexpr int kNumKernels = 10;
 }  // namespace
 
 void trace_pre(int kid, hipStream_t s) {
@@ -151,7 +152,8 @@ struct Carve {
 };
 
 struct PassWs {
-  double* W;          // m x n
+  double* W;          // m x n (dense: the strictly upper block triangle of A times Z)
+  double* Ws;         // m x n (dense: W + the diagonal blocks of A times Z)
   double* partial;    // Gram partials
   double* G;          // n x n
   double* R1;         // n x n (first pass of CholQR2)
@@ -165,6 +167,7 @@ size_t pass_ws(const oqr_op* A, int64_t m, int64_t n, const oqr_opts& o, bool tw
   Carve c{(char*)base, 0};
   PassWs w;
   w.W = c.take<double>((size_t)m * n);
+  w.Ws = c.take<double>(A->kind == OQR_OP_DENSE ? (size_t)m * n : 0);
   w.partial = c.take<double>(gram_partial_bytes(m, n) / sizeof(double));
   w.G = c.take<double>((size_t)n * n);
   w.R1 = c.take<double>((size_t)n * n);
@@ -182,19 +185,34 @@ size_t pass_ws(const oqr_op* A, int64_t m, int64_t n, const oqr_opts& o, bool tw
   return c.off;
 }
 
+// G = Z^T A Z for symmetric A from Woff (strictly upper block triangle of A times Z) and Wsym (Woff plus
+// the diagonal blocks): G = Z^T Wsym + Woff^T Z, upper triangle.
+hipError_t gram_symm(const double* Z, int64_t ldz, int64_t m, int64_t n, const PassWs& w, hipStream_t s) {
+  hipError_t e = launch_gram_f64(Z, ldz, w.Ws, m, m, n, w.partial, w.G, s);
+  if (e != hipSuccess) return e;
+  return launch_gram_f64(w.W, m, Z, ldz, m, n, w.partial, w.G, s, true);
+}
+
 // One CHOLQR pass (Algorithm 1) on the device: W = A Z; G = Z^T W; R = chol(G [+ s I]); Q = Z R^{-1}.
+// Dense A is symmetric: the product reads only its upper block triangle and G is assembled from the
+// two halves (gram_symm).
 int cholqr_pass(const oqr_op* A, const double* Z, int64_t ldz, int64_t m, int64_t n, double* Q, int64_t ldq,
                 double* R, int64_t ldr, int prec, const oqr_opts& o, const PassWs& w, double* shift_slot,
                 int32_t* info, hipStream_t s) {
   if (A->kind == OQR_OP_DENSE) {
     const double* a = (const double*)A->a;
     if (prec == OQR_P_FP64) {
-      OQR_TRACED(K_GEMM_F64, s, launch_gemm_f64(a, A->lda, Z, ldz, w.W, m, m, n, w.kpart, s));
+      OQR_TRACED(K_GEMM_F64, s, launch_symm_upper(a, A->lda, Z, ldz, w.W, m, m, n, w.kpart, s));
+      OQR_TRACED(K_SYMM_DIAG, s,
+                 launch_symm_finish(a, A->lda, Z, ldz, w.W, w.Ws, m, m, n, w.kpart, symm_layers(m, n, w.kpart), s));
     } else {
       OQR_TRACED(K_SPLIT_Z, s, launch_split_z(Z, ldz, w.zs, m, n, slices_of(prec), s));
       OQR_TRACED(K_GEMM_SPLIT, s, launch_gemm_split(a, A->lda, w.zs, w.W, m, m, n, slices_of(prec), w.kpart, s));
     }
-    OQR_TRACED(K_GRAM, s, launch_gram_f64(Z, ldz, w.W, m, m, n, w.partial, w.G, s));
+    if (prec == OQR_P_FP64)
+      OQR_TRACED(K_GRAM, s, gram_symm(Z, ldz, m, n, w, s));
+    else
+      OQR_TRACED(K_GRAM, s, launch_gram_f64(Z, ldz, w.W, m, m, n, w.partial, w.G, s));
   } else {
     OQR_TRACED(K_STENCIL, s, launch_sparse_apply(A, Z, ldz, w.W, m, n, s));
     if (prec == OQR_P_FP64)

@@ -102,7 +102,7 @@ inline size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 // Kernel ids for oqr_trace_start (names in api.hip).
 enum KernelId { K_GEMM_F64 = 1, K_GEMM_SPLIT = 2, K_GRAM = 3, K_CHOL = 4, K_TRSM = 5, K_STENCIL = 6, K_SPLIT_Z = 7,
-               K_BATCH = 8 };
+               K_BATCH = 8, K_SYMM_DIAG = 9 };
 void trace_pre(int kid, hipStream_t s);
 void trace_post(int kid, hipStream_t s);
 
@@ -117,6 +117,16 @@ int device_cu_count();
 size_t gemm_kpart_bytes(int64_t m, int64_t n);
 hipError_t launch_gemm_f64(const double* A, int64_t lda, const double* Z, int64_t ldz, double* W, int64_t ldw,
                            int64_t m, int64_t n, double* kpart, hipStream_t s);
+// A symmetric, only its upper block triangle read (blocks of 64 rows): Woff = (strictly upper block
+// triangle of A) Z, then Wsym = Woff + blockdiag(A) Z, so that Z^T A Z = Z^T Wsym + Woff^T Z.  The
+// strictly upper part is balanced over workgroups: row tiles t and R - 1 - t are paired and a pair is
+// cut into symm_layers parts whose partial products go to the layers of kpart (summed by
+// launch_symm_finish; with one layer the product goes to Woff directly).
+int symm_layers(int64_t m, int64_t n, const double* kpart);
+hipError_t launch_symm_upper(const double* A, int64_t lda, const double* Z, int64_t ldz, double* Woff, int64_t ldw,
+                             int64_t m, int64_t n, double* kpart, hipStream_t s);
+hipError_t launch_symm_finish(const double* A, int64_t lda, const double* Z, int64_t ldz, double* Woff, double* Wsym,
+                              int64_t ldw, int64_t m, int64_t n, const double* kpart, int layers, hipStream_t s);
 // W = A * Z with A split on the fly into `slices` bfloat16 slices and Z pre-split (zs: slices x n
 // columns of split_ld(m) bf16 each); FP32 MFMA accumulation over K tiles of 256, FP64 across tiles.
 hipError_t launch_gemm_split(const double* A, int64_t lda, const unsigned short* zs, double* W, int64_t ldw,
@@ -131,8 +141,9 @@ hipError_t launch_sparse_apply(const oqr_op* op, const double* Z, int64_t ldz, d
 
 // Gram: partial[c] = (X^T Y) restricted to row chunk c, upper 64x64 tiles; then G = sum_c partial[c].
 size_t gram_partial_bytes(int64_t m, int64_t n);
+// accumulate: G += X^T Y instead of G = X^T Y.
 hipError_t launch_gram_f64(const double* X, int64_t ldx, const double* Y, int64_t ldy, int64_t m, int64_t n,
-                           double* partial, double* G, hipStream_t s);
+                           double* partial, double* G, hipStream_t s, bool accumulate = false);
 hipError_t launch_gram_split(const double* X, int64_t ldx, const double* Y, int64_t ldy, int64_t m, int64_t n,
                              int slices, double* partial, double* G, hipStream_t s);
 

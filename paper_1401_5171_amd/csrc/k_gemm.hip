@@ -21,89 +21,135 @@ constexpr int BK64 = 16;
 // columns of one row, touches 16 distinct bank pairs.
 constexpr int APAD = 1, BPAD = 1;
 
-template <int CB>
+// K ranges of the products.  GEMM_FULL: row tile blockIdx.x, K slice blockIdx.z of width kchunk.
+// GEMM_UPPER (A symmetric, strictly upper block triangle): row tile t needs K in [BM (t + 1), m);
+// tiles t and R - 1 - t form pair blockIdx.x (their lengths sum to m - BM), the pair's K steps are cut
+// into gridDim.z equal parts, and part blockIdx.z goes to layer blockIdx.z of the output (both tiles of
+// the pair are written in every layer, zeros where the part has no steps).  GEMM_DIAG: row tile
+// blockIdx.x, K in its own diagonal block [BM t, BM (t + 1)); the result is added to Wadd.
+enum GemmMode { GEMM_FULL = 0, GEMM_UPPER = 1, GEMM_DIAG = 2 };
+
+struct Seg {
+  int tile, k0, k1;
+};
+
+// The row-tile segments of workgroup (pair p, part h) in GEMM_UPPER, K steps of ks: a in tile p and,
+// unless the pair is one tile (returns false), b in tile R - 1 - p.
+__device__ __forceinline__ bool upper_segments(int m, int p, int h, int H, int ks, Seg& a, Seg& b) {
+  const int R = (m + BM - 1) / BM;
+  const int ta = p, tb = R - 1 - p;
+  const int sa = min(m, BM * (ta + 1)), sb = min(m, BM * (tb + 1));
+  const int na = (m - sa + ks - 1) / ks, nb = (tb != ta) ? (m - sb + ks - 1) / ks : 0;
+  const int T = na + nb;
+  const int s0 = (int)((int64_t)T * h / H), s1 = (int)((int64_t)T * (h + 1) / H);
+  a = {ta, min(m, sa + ks * min(s0, na)), min(m, sa + ks * min(s1, na))};
+  b = {tb, min(m, sb + ks * max(s0 - na, 0)), min(m, sb + ks * max(s1 - na, 0))};
+  return tb != ta;
+}
+
+template <int CB, int MODE>
 __global__ __launch_bounds__(NT, 2) void gemm_f64_kernel(const double* __restrict__ A, int64_t lda,
                                                           const double* __restrict__ Z, int64_t ldz,
                                                           double* __restrict__ W, int64_t ldw, int m, int n,
-                                                          int kchunk, int64_t wstride) {
+                                                          int kchunk, int64_t wstride,
+                                                          const double* __restrict__ Wadd, int64_t ldadd) {
   constexpr int BN = 64 * CB;                   // columns per workgroup
   __shared__ double As[BK64][BM + APAD];
   __shared__ double Bs[BK64][BN + BPAD];
   const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
-  const int i0 = blockIdx.x * BM, j0 = blockIdx.y * BN;
-  // K slice [kb, ke) of this workgroup (split K: partial products into W + z * wstride)
-  const int kb = blockIdx.z * kchunk, ke = min(m, kb + kchunk);
-  W += blockIdx.z * wstride;
+  const int j0 = blockIdx.y * BN;
   const int wc = wave * 16 * CB;
-
-  f64x4 acc[4][CB];
-#pragma unroll
-  for (int a = 0; a < 4; ++a)
-#pragma unroll
-    for (int b = 0; b < CB; ++b) acc[a][b] = f64x4{0, 0, 0, 0};
+  W += blockIdx.z * wstride;
 
   // global -> register staging
   constexpr int AR = BM * BK64 / NT;            // 4
   constexpr int BR = BK64 * BN / NT;            // 4*CB
-  double ra[AR], rb[BR];
   const int ai = t % BM, ak = t / BM;           // A: row ai, k = ak + 4r
   const int bk = t % BK64, bj = t / BK64;       // Z: k = bk, col = bj + 16r
-  // byte offsets inside the per-step buffers (rows beyond m / columns beyond n -> kOOB)
-  uint32_t aoff[AR], boff[BR];
-#pragma unroll
-  for (int r = 0; r < AR; ++r) aoff[r] = (i0 + ai < m) ? (uint32_t)(((int64_t)(ak + 4 * r) * lda + ai) * 8) : kOOB;
+  uint32_t boff[BR];
 #pragma unroll
   for (int r = 0; r < BR; ++r)
     boff[r] = (j0 + bj + 16 * r < n) ? (uint32_t)(((int64_t)(bj + 16 * r) * ldz + bk) * 8) : kOOB;
-  auto load = [&](int k0) {
-    // A rows i0.., columns k0..: the size bound cuts k >= ke; Z rows k0.., columns j0..
-    const bufrsrc abuf = make_buf(A + (int64_t)min(k0, ke) * lda + i0, (int64_t)(ke - min(k0, ke)) * lda * 8);
-    const bufrsrc zbuf = make_buf(Z + (int64_t)j0 * ldz + k0, (int64_t)(n - j0) * ldz * 8);
-    const bool kin = k0 + bk < ke;
-#pragma unroll
-    for (int r = 0; r < AR; ++r) ra[r] = buf_f64(abuf, aoff[r]);
-#pragma unroll
-    for (int r = 0; r < BR; ++r) rb[r] = buf_f64(zbuf, kin ? boff[r] : kOOB);
-  };
-  auto store = [&]() {
-#pragma unroll
-    for (int r = 0; r < AR; ++r) As[ak + 4 * r][ai] = ra[r];
-#pragma unroll
-    for (int r = 0; r < BR; ++r) Bs[bk][bj + 16 * r] = rb[r];
-  };
 
-  load(kb);
-  store();
-  __syncthreads();
-  for (int k0 = kb; k0 < ke; k0 += BK64) {
-    load(k0 + BK64);                   // past the end: guarded loads return zeros
+  // rows [i0, i0 + BM) of A times Z over K [kb, ke); result (+ Wadd) into W
+  auto segment = [&](int i0, int kb, int ke) {
+    f64x4 acc[4][CB];
 #pragma unroll
-    for (int kk = 0; kk < BK64; kk += 4) {
-      const int kr = kk + (lane >> 4);
-      double af[4], bf[CB];
+    for (int a = 0; a < 4; ++a)
 #pragma unroll
-      for (int a = 0; a < 4; ++a) af[a] = As[kr][a * 16 + (lane & 15)];
+      for (int b = 0; b < CB; ++b) acc[a][b] = f64x4{0, 0, 0, 0};
+    double ra[AR], rb[BR];
+    uint32_t aoff[AR];
 #pragma unroll
-      for (int b = 0; b < CB; ++b) bf[b] = Bs[kr][wc + b * 16 + (lane & 15)];
+    for (int r = 0; r < AR; ++r) aoff[r] = (i0 + ai < m) ? (uint32_t)(((int64_t)(ak + 4 * r) * lda + ai) * 8) : kOOB;
+    auto load = [&](int k0) {
+      // A rows i0.., columns k0..: the size bound cuts k >= ke; Z rows k0.., columns j0..
+      const bufrsrc abuf = make_buf(A + (int64_t)min(k0, ke) * lda + i0, (int64_t)(ke - min(k0, ke)) * lda * 8);
+      const bufrsrc zbuf = make_buf(Z + (int64_t)j0 * ldz + k0, (int64_t)(n - j0) * ldz * 8);
+      const bool kin = k0 + bk < ke;
 #pragma unroll
-      for (int a = 0; a < 4; ++a)
+      for (int r = 0; r < AR; ++r) ra[r] = buf_f64(abuf, aoff[r]);
 #pragma unroll
-        for (int b = 0; b < CB; ++b) acc[a][b] = mfma_f64(af[a], bf[b], acc[a][b]);
-    }
-    __syncthreads();
+      for (int r = 0; r < BR; ++r) rb[r] = buf_f64(zbuf, kin ? boff[r] : kOOB);
+    };
+    auto store = [&]() {
+#pragma unroll
+      for (int r = 0; r < AR; ++r) As[ak + 4 * r][ai] = ra[r];
+#pragma unroll
+      for (int r = 0; r < BR; ++r) Bs[bk][bj + 16 * r] = rb[r];
+    };
+
+    __syncthreads();                   // the previous segment's last reads of As / Bs
+    load(kb);
     store();
     __syncthreads();
-  }
+    for (int k0 = kb; k0 < ke; k0 += BK64) {
+      load(k0 + BK64);                 // past the end: guarded loads return zeros
 #pragma unroll
-  for (int a = 0; a < 4; ++a)
+      for (int kk = 0; kk < BK64; kk += 4) {
+        const int kr = kk + (lane >> 4);
+        double af[4], bf[CB];
 #pragma unroll
-    for (int b = 0; b < CB; ++b)
+        for (int a = 0; a < 4; ++a) af[a] = As[kr][a * 16 + (lane & 15)];
 #pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        int i = i0 + a * 16 + 4 * r + (lane >> 4);
-        int j = j0 + wc + b * 16 + (lane & 15);
-        if (i < m && j < n) W[(int64_t)j * ldw + i] = acc[a][b][r];
+        for (int b = 0; b < CB; ++b) bf[b] = Bs[kr][wc + b * 16 + (lane & 15)];
+#pragma unroll
+        for (int a = 0; a < 4; ++a)
+#pragma unroll
+          for (int b = 0; b < CB; ++b) acc[a][b] = mfma_f64(af[a], bf[b], acc[a][b]);
       }
+      __syncthreads();
+      store();
+      __syncthreads();
+    }
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+      for (int b = 0; b < CB; ++b)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int i = i0 + a * 16 + 4 * r + (lane >> 4);
+          const int j = j0 + wc + b * 16 + (lane & 15);
+          if (i < m && j < n) {
+            double v = acc[a][b][r];
+            if (MODE == GEMM_DIAG) v += Wadd[(int64_t)j * ldadd + i];
+            W[(int64_t)j * ldw + i] = v;
+          }
+        }
+  };
+
+  if (MODE == GEMM_UPPER) {
+    Seg sa, sb;
+    const bool two = upper_segments(m, blockIdx.x, blockIdx.z, gridDim.z, BK64, sa, sb);
+    segment(sa.tile * BM, sa.k0, sa.k1);
+    if (two) segment(sb.tile * BM, sb.k0, sb.k1);
+  } else if (MODE == GEMM_DIAG) {
+    const int i0 = blockIdx.x * BM;
+    segment(i0, i0, min(m, i0 + BM));
+  } else {
+    const int kb = blockIdx.z * kchunk;
+    segment(blockIdx.x * BM, kb, min(m, kb + kchunk));
+  }
 }
 
 // ---------------------------------------------------------------------------------------------
@@ -485,9 +531,22 @@ KSplit ksplit(int64_t m, int64_t n) {
 
 }  // namespace
 
+// Parts per pair of the GEMM_UPPER schedule: enough workgroups for two per CU, at most 8 layers.
+static int upper_parts(int64_t m, int64_t n) {
+  const int64_t R = ceil_div(m, BM), P = (R + 1) / 2, ycb = ceil_div(n, 64 * col_blocks(n));
+  const int64_t target = 2 * (int64_t)device_cu_count();
+  int64_t H = (target + P * ycb - 1) / (P * ycb);
+  if (H > 8) H = 8;
+  if (H < 1) H = 1;
+  return (int)H;
+}
+
 size_t gemm_kpart_bytes(int64_t m, int64_t n) {
   const KSplit k = ksplit(m, n);
-  return k.ks > 1 ? (size_t)k.ks * m * n * sizeof(double) : 0;
+  int layers = k.ks > 1 ? k.ks : 0;
+  const int h = upper_parts(m, n);
+  if (h > 1 && h > layers) layers = h;
+  return (size_t)layers * m * n * sizeof(double);
 }
 
 static hipError_t ksum(const double* P, int ks, int64_t m, int64_t n, double* W, int64_t ldw, hipStream_t s) {
@@ -495,6 +554,17 @@ static hipError_t ksum(const double* P, int ks, int64_t m, int64_t n, double* W,
   ksum_kernel<<<(unsigned)((total + 255) / 256), 256, 0, s>>>(P, ks, m, n, W, ldw);
   return hipGetLastError();
 }
+
+#define OQR_GEMM_F64(cb, MODE_, grid, out, ldo, kchunk, stride, wadd, ldadd)                                     \
+  do {                                                                                                          \
+    const int M_ = (int)m, N_ = (int)n;                                                                         \
+    if ((cb) == 1)                                                                                              \
+      gemm_f64_kernel<1, MODE_><<<(grid), NT, 0, s>>>(A, lda, Z, ldz, out, ldo, M_, N_, kchunk, stride, wadd, ldadd); \
+    else if ((cb) == 2)                                                                                         \
+      gemm_f64_kernel<2, MODE_><<<(grid), NT, 0, s>>>(A, lda, Z, ldz, out, ldo, M_, N_, kchunk, stride, wadd, ldadd); \
+    else                                                                                                        \
+      gemm_f64_kernel<4, MODE_><<<(grid), NT, 0, s>>>(A, lda, Z, ldz, out, ldo, M_, N_, kchunk, stride, wadd, ldadd); \
+  } while (0)
 
 hipError_t launch_gemm_f64(const double* A, int64_t lda, const double* Z, int64_t ldz, double* W, int64_t ldw,
                            int64_t m, int64_t n, double* kpart, hipStream_t s) {
@@ -504,14 +574,33 @@ hipError_t launch_gemm_f64(const double* A, int64_t lda, const double* Z, int64_
   dim3 grid(ceil_div(m, BM), ceil_div(n, 64 * cb), k.ks);
   double* out = k.ks > 1 ? kpart : W;
   const int64_t ldo = k.ks > 1 ? m : ldw, stride = k.ks > 1 ? m * n : 0;
-  switch (cb) {
-    case 1: gemm_f64_kernel<1><<<grid, NT, 0, s>>>(A, lda, Z, ldz, out, ldo, (int)m, (int)n, k.kchunk, stride); break;
-    case 2: gemm_f64_kernel<2><<<grid, NT, 0, s>>>(A, lda, Z, ldz, out, ldo, (int)m, (int)n, k.kchunk, stride); break;
-    default: gemm_f64_kernel<4><<<grid, NT, 0, s>>>(A, lda, Z, ldz, out, ldo, (int)m, (int)n, k.kchunk, stride); break;
-  }
+  OQR_GEMM_F64(cb, GEMM_FULL, grid, out, ldo, k.kchunk, stride, nullptr, 0);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess || k.ks == 1) return e;
   return ksum(kpart, k.ks, m, n, W, ldw, s);
+}
+
+int symm_layers(int64_t m, int64_t n, const double* kpart) { return kpart ? upper_parts(m, n) : 1; }
+
+hipError_t launch_symm_upper(const double* A, int64_t lda, const double* Z, int64_t ldz, double* Woff, int64_t ldw,
+                             int64_t m, int64_t n, double* kpart, hipStream_t s) {
+  const int cb = col_blocks(n);
+  const int R = ceil_div(m, BM), P = (R + 1) / 2, ycb = ceil_div(n, 64 * cb);
+  const int H = symm_layers(m, n, kpart);
+  double* out = H > 1 ? kpart : Woff;
+  const int64_t ldo = H > 1 ? m : ldw, stride = H > 1 ? m * n : 0;
+  OQR_GEMM_F64(cb, GEMM_UPPER, dim3(P, ycb, H), out, ldo, 0, stride, nullptr, 0);
+  return hipGetLastError();
+}
+
+hipError_t launch_symm_finish(const double* A, int64_t lda, const double* Z, int64_t ldz, double* Woff, double* Wsym,
+                              int64_t ldw, int64_t m, int64_t n, const double* kpart, int layers, hipStream_t s) {
+  hipError_t e;
+  if (layers > 1 && (e = ksum(kpart, layers, m, n, Woff, ldw, s)) != hipSuccess) return e;
+  const int cb = col_blocks(n);
+  const double* Wo = Woff;
+  OQR_GEMM_F64(cb, GEMM_DIAG, dim3(ceil_div(m, BM), ceil_div(n, 64 * cb), 1), Wsym, ldw, 0, 0, Wo, ldw);
+  return hipGetLastError();
 }
 
 hipError_t launch_gemm_split(const double* A, int64_t lda, const unsigned short* zs, double* W, int64_t ldw,

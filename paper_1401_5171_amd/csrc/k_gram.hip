@@ -426,7 +426,8 @@ __global__ __launch_bounds__(NT, 2) void gram_full_split_kernel(const double* __
 // G(i, j) = G(j, i) = sum_c partial[c](i, j) for i <= j.  Eight interleaved partial sums (chunk c goes
 // to sum c mod 8) keep eight loads in flight; they are combined in a fixed order, so the result does
 // not depend on timing.
-__global__ void gram_reduce_kernel(const double* __restrict__ partial, int n, int chunks, double* __restrict__ G) {
+__global__ void gram_reduce_kernel(const double* __restrict__ partial, int n, int chunks, double* __restrict__ G,
+                                   int accumulate) {
   const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (idx >= (int64_t)n * n) return;
   const int j = (int)(idx / n), i = (int)(idx % n);
@@ -439,7 +440,8 @@ __global__ void gram_reduce_kernel(const double* __restrict__ partial, int n, in
     for (int u = 0; u < 8; ++u) s[u] += partial[(int64_t)(c + u) * nn + idx];
   }
   for (int u = 0; c < chunks; ++c, ++u) s[u] += partial[(int64_t)c * nn + idx];
-  const double t = ((s[0] + s[1]) + (s[2] + s[3])) + ((s[4] + s[5]) + (s[6] + s[7]));
+  double t = ((s[0] + s[1]) + (s[2] + s[3])) + ((s[4] + s[5]) + (s[6] + s[7]));
+  if (accumulate) t += G[(int64_t)j * n + i];
   G[(int64_t)j * n + i] = t;
   G[(int64_t)i * n + j] = t;
 }
@@ -457,14 +459,15 @@ size_t gram_partial_bytes(int64_t m, int64_t n) {
   return b;
 }
 
-static hipError_t reduce(const double* partial, int64_t n, int chunks, double* G, hipStream_t s) {
+static hipError_t reduce(const double* partial, int64_t n, int chunks, double* G, hipStream_t s,
+                         bool accumulate = false) {
   const int64_t total = n * n;
-  gram_reduce_kernel<<<(unsigned)((total + 255) / 256), 256, 0, s>>>(partial, (int)n, chunks, G);
+  gram_reduce_kernel<<<(unsigned)((total + 255) / 256), 256, 0, s>>>(partial, (int)n, chunks, G, accumulate);
   return hipGetLastError();
 }
 
 hipError_t launch_gram_f64(const double* X, int64_t ldx, const double* Y, int64_t ldy, int64_t m, int64_t n,
-                           double* partial, double* G, hipStream_t s) {
+                           double* partial, double* G, hipStream_t s, bool accumulate) {
   if (n <= 2 * TB) {
     const FullPlan f = full_plan(m, BK);
     if (n <= TB)
@@ -473,13 +476,13 @@ hipError_t launch_gram_f64(const double* X, int64_t ldx, const double* Y, int64_
       gram_full_f64_kernel<2><<<f.chunks, NT, 0, s>>>(X, ldx, Y, ldy, (int)m, (int)n, f.kc, partial);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    return reduce(partial, n, f.chunks, G, s);
+    return reduce(partial, n, f.chunks, G, s, accumulate);
   }
   GramPlan p = plan(m, n);
   gram_f64_kernel<<<dim3(p.tiles, p.chunks), NT, 0, s>>>(X, ldx, Y, ldy, (int)m, (int)n, p.nb, p.kc, partial);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  return reduce(partial, n, p.chunks, G, s);
+  return reduce(partial, n, p.chunks, G, s, accumulate);
 }
 
 hipError_t launch_gram_split(const double* X, int64_t ldx, const double* Y, int64_t ldy, int64_t m, int64_t n,

@@ -8,8 +8,11 @@ dominates) plus a 1e-14 floor, or for the unstable variants within 10 n u times 
 expression (kappa(R)^2 for CHOLQR-A and CGS-A, kappa(R) for MGS-A); its residual obeys the same bar
 as the oracle's.  Where the oracle's Cholesky breaks down, the GPU must either report the failed
 pivot in `info` or return a result whose loss is also large; it may report a breakdown only at the
-edge (u max(kappa(R)^2, kappa(A)) > 1e-3, or an oracle loss above 1e-6): the breakdown point moves
-with rounding.
+edge, where Theorem 2.1's bound on the loss of CHOLQR-A (without its constant c m n),
+u ||R^-1|| ||Z|| (||R^-1|| ||A Z|| + ||Q|| ||A||), or u kappa(A) exceeds 1e-3, or the oracle's loss
+exceeds 1e-6: there the rounding of the Gram is within three orders of its smallest eigenvalue and the
+breakdown point moves with the order of summation (in Case 1, Z in the span of A's smallest
+eigenvectors, the bound is about u kappa(R)^2 kappa(A)).
 The scaling laws themselves are pinned on the CPU (test_oracle_claims.py); this suite shows that the
 GPU variants follow the same laws.
 """
@@ -54,6 +57,14 @@ BOUND = {
     "mgs_row": lambda kr: kr,
     "mgs_col": lambda kr: kr,
 }
+
+
+def theorem_bound(a, z, q0, r0):
+    """Theorem 2.1 (Section 2), without the constant c m n:
+    u ||R^-1|| ||Z|| (||R^-1|| ||A Z|| + ||Q|| ||A||)."""
+    ri = np.linalg.norm(np.linalg.inv(r0), 2)
+    return U * ri * np.linalg.norm(z, 2) * (ri * np.linalg.norm(a @ z, 2)
+                                           + np.linalg.norm(q0, 2) * np.linalg.norm(a, 2))
 
 
 def gpu_run(name, A, Zd):
@@ -101,8 +112,9 @@ def test_gpu_variants_follow_the_oracle(case):
                 continue                      # both are lost; the level is not meaningful
             kr = np.linalg.cond(r0)
             if info != 0:
-                # a breakdown only at the edge: the Gram (kappa(R)^2) or A itself near singular in FP64
-                assert U * max(kr * kr, ka) > 1e-3 or l0 > 1e-6, what
+                # a breakdown only at the edge: the Gram's rounding near its smallest eigenvalue, or A
+                # itself near singular in FP64
+                assert theorem_bound(a, z, q0, r0) > 1e-3 or U * ka > 1e-3 or l0 > 1e-6, what
                 continue
             factor = 10 if l0 <= 1e-6 else 100   # rounding-dominated regime: wider band
             bar = factor * l0 + 1e-14
