@@ -207,12 +207,12 @@ int cholqr_pass(const oqr_op* A, const double* Z, int64_t ldz, int64_t m, int64_
                  launch_symm_finish(a, A->lda, Z, ldz, w.W, w.Ws, m, m, n, w.kpart, symm_layers(m, n, w.kpart), s));
     } else {
       OQR_TRACED(K_SPLIT_Z, s, launch_split_z(Z, ldz, w.zs, m, n, slices_of(prec), s));
-      OQR_TRACED(K_GEMM_SPLIT, s, launch_gemm_split(a, A->lda, w.zs, w.W, m, m, n, slices_of(prec), w.kpart, s));
+      OQR_TRACED(K_GEMM_SPLIT, s,
+                 launch_symm_split_upper(a, A->lda, w.zs, w.W, m, m, n, slices_of(prec), w.kpart, s));
+      OQR_TRACED(K_SYMM_DIAG, s,
+                 launch_symm_finish(a, A->lda, Z, ldz, w.W, w.Ws, m, m, n, w.kpart, symm_layers(m, n, w.kpart), s));
     }
-    if (prec == OQR_P_FP64)
-      OQR_TRACED(K_GRAM, s, gram_symm(Z, ldz, m, n, w, s));
-    else
-      OQR_TRACED(K_GRAM, s, launch_gram_f64(Z, ldz, w.W, m, m, n, w.partial, w.G, s));
+    OQR_TRACED(K_GRAM, s, gram_symm(Z, ldz, m, n, w, s));
   } else {
     OQR_TRACED(K_STENCIL, s, launch_sparse_apply(A, Z, ldz, w.W, m, n, s));
     if (prec == OQR_P_FP64)

@@ -125,6 +125,10 @@ hipError_t launch_gemm_f64(const double* A, int64_t lda, const double* Z, int64_
 int symm_layers(int64_t m, int64_t n, const double* kpart);
 hipError_t launch_symm_upper(const double* A, int64_t lda, const double* Z, int64_t ldz, double* Woff, int64_t ldw,
                              int64_t m, int64_t n, double* kpart, hipStream_t s);
+// Woff of launch_symm_upper with A split on the fly into bfloat16 slices (Z pre-split, as for
+// launch_gemm_split); the diagonal blocks are then added in FP64 by launch_symm_finish.
+hipError_t launch_symm_split_upper(const double* A, int64_t lda, const unsigned short* zs, double* Woff, int64_t ldw,
+                                   int64_t m, int64_t n, int slices, double* kpart, hipStream_t s);
 hipError_t launch_symm_finish(const double* A, int64_t lda, const double* Z, int64_t ldz, double* Woff, double* Wsym,
                               int64_t ldw, int64_t m, int64_t n, const double* kpart, int layers, hipStream_t s);
 // W = A * Z with A split on the fly into `slices` bfloat16 slices and Z pre-split (zs: slices x n

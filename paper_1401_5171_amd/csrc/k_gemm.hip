@@ -162,7 +162,7 @@ __global__ __launch_bounds__(NT, 2) void gemm_f64_kernel(const double* __restric
 constexpr int BKS = 32;
 constexpr int SROW = BKS + 8;   // LDS row stride of an A slice (bf16 elements)
 
-template <int S, int CB>
+template <int S, int CB, int MODE>
 __global__ __launch_bounds__(NT, 1) void gemm_split_kernel(const double* __restrict__ A, int64_t lda,
                                                             const unsigned short* __restrict__ zs,
                                                             double* __restrict__ W, int64_t ldw, int m, int n,
@@ -171,30 +171,19 @@ __global__ __launch_bounds__(NT, 1) void gemm_split_kernel(const double* __restr
   __shared__ __attribute__((aligned(16))) unsigned short As[2][S][BM][SROW];
   __shared__ double Dacc[NT / 64][4 * CB * 4][64];     // FP64 accumulators: [wave][slot][lane]
   const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
-  const int i0 = blockIdx.x * BM, j0 = blockIdx.y * BN;
+  const int j0 = blockIdx.y * BN;
   const int wc = j0 + wave * 16 * CB;
   const int64_t mp = split_ld(m);             // ld of the slices of Z (rows padded with zeros)
   const int64_t slice_stride = mp * n;
-  // K slice [kb, ke) (kchunk is a multiple of BKS; the last slice ends at m)
-  const int kb = blockIdx.z * kchunk, ke = min(m, kb + kchunk);
+  // the current segment: rows [i0, i0 + BM), K [kb, ke) (kb a multiple of BKS)
+  int i0 = 0, kb = 0, ke = 0;
   W += blockIdx.z * wstride;
 
   f32x4 acc[4][CB];
-#pragma unroll
-  for (int a = 0; a < 4; ++a)
-#pragma unroll
-    for (int b = 0; b < CB; ++b) {
-      acc[a][b] = f32x4{0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-      for (int r = 0; r < 4; ++r) Dacc[wave][(a * CB + b) * 4 + r][lane] = 0.0;
-    }
-
   // A tile 64 x 32: thread t loads row ai = t % 64, k = 8 ak .. 8 ak + 7 (ak = t / 64).
   // Three register stages keep A two K steps ahead of the MFMAs (HBM latency).
   const int ai = t % BM, ak = t / BM;
   uint32_t aoff[8];
-#pragma unroll
-  for (int e = 0; e < 8; ++e) aoff[e] = (i0 + ai < m) ? (uint32_t)(((int64_t)(ak * 8 + e) * lda + ai) * 8) : kOOB;
   double ra0[8], ra1[8], ra2[8];
   auto load_a = [&](double (&ra)[8], int k0) {
     k0 += kb;
@@ -242,9 +231,8 @@ __global__ __launch_bounds__(NT, 1) void gemm_split_kernel(const double* __restr
         dst[s][b] = buf_b128(zbuf, zoff[b] == kOOB ? kOOB : zoff[b] + (uint32_t)(s * slice_stride * 2));
   };
 
-  // K steps, padded to a multiple of 6 (3 A register stages x 2 B fragment buffers); steps past the
+  // K steps are padded to a multiple of 6 (3 A register stages x 2 B fragment buffers); steps past the
   // end of K read empty buffers and contribute zeros, so no load sits under a branch.
-  const int nsteps = ((ke - kb + BKS - 1) / BKS + 5) / 6 * 6;
   // One K step, a single basic block: request B(st+2) and A(st+3); read the A fragments of buffer
   // st & 1; convert A(st+1) into the other buffer while the MFMAs run; one barrier.  B is requested
   // before A: memory counters retire in order, so the wait for B(st+1) at the next step must not
@@ -254,13 +242,13 @@ __global__ __launch_bounds__(NT, 1) void gemm_split_kernel(const double* __restr
     const int cur = st & 1;
     load_b((st + 2) * BKS, bfill);
     load_a(ra_fill, (st + 3) * BKS);
-    const int kb = 8 * (lane >> 4);
+    const int kq = 8 * (lane >> 4);
     bf16x8 af[S][4];
 #pragma unroll
     for (int p = 0; p < S; ++p)
 #pragma unroll
       for (int a = 0; a < 4; ++a)
-        af[p][a] = __builtin_bit_cast(bf16x8, *reinterpret_cast<const u16x8*>(&As[cur][p][a * 16 + (lane & 15)][kb]));
+        af[p][a] = __builtin_bit_cast(bf16x8, *reinterpret_cast<const u16x8*>(&As[cur][p][a * 16 + (lane & 15)][kq]));
     store_a(ra_store, cur ^ 1);
 #pragma unroll
     for (int p = 0; p < S; ++p)
@@ -292,6 +280,18 @@ __global__ __launch_bounds__(NT, 1) void gemm_split_kernel(const double* __restr
       }
   };
 
+  auto segment = [&]() {
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = 0; b < CB; ++b) {
+      acc[a][b] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+      for (int r = 0; r < 4; ++r) Dacc[wave][(a * CB + b) * 4 + r][lane] = 0.0;
+    }
+#pragma unroll
+  for (int e = 0; e < 8; ++e) aoff[e] = (i0 + ai < m) ? (uint32_t)(((int64_t)(ak * 8 + e) * lda + ai) * 8) : kOOB;
+  const int nsteps = ((ke - kb + BKS - 1) / BKS + 5) / 6 * 6;
   load_b(0, bf0);
   load_b(BKS, bf1);
   load_a(ra0, 0);
@@ -324,6 +324,22 @@ __global__ __launch_bounds__(NT, 1) void gemm_split_kernel(const double* __restr
         const int j = wc + b * 16 + (lane & 15);
         if (i < m && j < n) W[(int64_t)j * ldw + i] = Dacc[wave][(a * CB + b) * 4 + r][lane];
       }
+  };
+
+  if (MODE == GEMM_UPPER) {
+    Seg sa, sb;
+    const bool two = upper_segments(m, blockIdx.x, blockIdx.z, gridDim.z, BKS, sa, sb);
+    i0 = sa.tile * BM, kb = sa.k0, ke = sa.k1;
+    segment();
+    if (two) {
+      __syncthreads();                  // the last reads of As
+      i0 = sb.tile * BM, kb = sb.k0, ke = sb.k1;
+      segment();
+    }
+  } else {
+    i0 = blockIdx.x * BM, kb = blockIdx.z * kchunk, ke = min(m, kb + kchunk);
+    segment();
+  }
 }
 
 // Split bfloat16 product for n in (128, 256]: 512 threads (two waves per SIMD), a 64-row block of W
@@ -338,7 +354,7 @@ constexpr int BN2 = 256;
 
 __device__ __forceinline__ int bsw(int col, int ch) { return col * BKS + 8 * (ch ^ ((col >> 1) & 3)); }
 
-template <int S>
+template <int S, int MODE>
 __global__ __launch_bounds__(NT2, 1) void gemm_split2_kernel(const double* __restrict__ A, int64_t lda,
                                                              const unsigned short* __restrict__ zs,
                                                              double* __restrict__ W, int64_t ldw, int m, int n,
@@ -347,27 +363,17 @@ __global__ __launch_bounds__(NT2, 1) void gemm_split2_kernel(const double* __res
   __shared__ __attribute__((aligned(16))) unsigned short Bs[2][S][BN2 * BKS];
   const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
   const int rh = wave >> 2, cq = wave & 3;
-  const int i0 = blockIdx.x * BM;
   const int64_t mp = split_ld(m);
   constexpr int64_t TILE = (int64_t)S * BN2 * BKS;   // bf16 elements of one K step of the tiled slices
-  const int kb = blockIdx.z * kchunk, ke = min(m, kb + kchunk);
+  // the current segment: rows [i0, i0 + BM), K [kb, ke) (kb a multiple of BKS)
+  int i0 = 0, kb = 0, ke = 0;
   W += blockIdx.z * wstride;
 
   f32x4 acc[2][4];
   double dacc[2][4][4];
-#pragma unroll
-  for (int a = 0; a < 2; ++a)
-#pragma unroll
-    for (int b = 0; b < 4; ++b) {
-      acc[a][b] = f32x4{0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-      for (int r = 0; r < 4; ++r) dacc[a][b][r] = 0.0;
-    }
   // A tile 64 x 32: thread t loads row ai = t % 64, k = 4 aq .. 4 aq + 3 (aq = t / 64)
   const int ai = t % BM, aq = t / BM;
   uint32_t aoff[4];
-#pragma unroll
-  for (int e = 0; e < 4; ++e) aoff[e] = (i0 + ai < m) ? (uint32_t)(((int64_t)(aq * 4 + e) * lda + ai) * 8) : kOOB;
   // B tile: S slices x 256 columns x 32 rows = S * 1024 chunks of 16 bytes; chunk c = t + 512 u:
   // slice c / 1024, column (c / 4) % 256, rows 8 (c % 4) .. + 7 (offsets inside the contiguous tile)
   constexpr int BU = S * 1024 / NT2;
@@ -448,6 +454,17 @@ __global__ __launch_bounds__(NT2, 1) void gemm_split2_kernel(const double* __res
     if (st % 30 == 29) fold();                // FP32 accumulation over at most 960 rows of K
   };
 
+  auto segment = [&]() {
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+      acc[a][b] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+      for (int r = 0; r < 4; ++r) dacc[a][b][r] = 0.0;
+    }
+#pragma unroll
+  for (int e = 0; e < 4; ++e) aoff[e] = (i0 + ai < m) ? (uint32_t)(((int64_t)(aq * 4 + e) * lda + ai) * 8) : kOOB;
   // K steps padded to an even count (steps past the end load empty buffers and add zeros)
   const int nsteps = ((ke - kb + BKS - 1) / BKS + 1) / 2 * 2;
   load(kb, ra0, rb0);
@@ -476,6 +493,22 @@ __global__ __launch_bounds__(NT2, 1) void gemm_split2_kernel(const double* __res
         const int j = 64 * cq + 16 * b + (lane & 15);
         if (i < m && j < n) W[(int64_t)j * ldw + i] = dacc[a][b][r];
       }
+  };
+
+  if (MODE == GEMM_UPPER) {
+    Seg sa, sb;
+    const bool two = upper_segments(m, blockIdx.x, blockIdx.z, gridDim.z, BKS, sa, sb);
+    i0 = sa.tile * BM, kb = sa.k0, ke = sa.k1;
+    segment();
+    if (two) {
+      __syncthreads();                  // the last reads of As / Bs
+      i0 = sb.tile * BM, kb = sb.k0, ke = sb.k1;
+      segment();
+    }
+  } else {
+    i0 = blockIdx.x * BM, kb = blockIdx.z * kchunk, ke = min(m, kb + kchunk);
+    segment();
+  }
 }
 
 // Slices of Z, rows m..split_ld(m)-1 zero.  Column layout (n <= 128): zs[s][j][i] (ld split_ld(m)).
@@ -603,6 +636,25 @@ hipError_t launch_symm_finish(const double* A, int64_t lda, const double* Z, int
   return hipGetLastError();
 }
 
+template <int MODE>
+static hipError_t split_launch(const double* A, int64_t lda, const unsigned short* zs, double* out, int64_t ldo,
+                               int64_t m, int64_t n, int slices, dim3 grid, int kchunk, int64_t stride, hipStream_t s) {
+  const int cb = col_blocks(n), M = (int)m, N = (int)n;
+  if (cb == 4) {
+    if (slices == 2)
+      gemm_split2_kernel<2, MODE><<<grid, NT2, 0, s>>>(A, lda, zs, out, ldo, M, N, kchunk, stride);
+    else
+      gemm_split2_kernel<3, MODE><<<grid, NT2, 0, s>>>(A, lda, zs, out, ldo, M, N, kchunk, stride);
+  } else if (slices == 2) {
+    if (cb == 1) gemm_split_kernel<2, 1, MODE><<<grid, NT, 0, s>>>(A, lda, zs, out, ldo, M, N, kchunk, stride);
+    else gemm_split_kernel<2, 2, MODE><<<grid, NT, 0, s>>>(A, lda, zs, out, ldo, M, N, kchunk, stride);
+  } else {
+    if (cb == 1) gemm_split_kernel<3, 1, MODE><<<grid, NT, 0, s>>>(A, lda, zs, out, ldo, M, N, kchunk, stride);
+    else gemm_split_kernel<3, 2, MODE><<<grid, NT, 0, s>>>(A, lda, zs, out, ldo, M, N, kchunk, stride);
+  }
+  return hipGetLastError();
+}
+
 hipError_t launch_gemm_split(const double* A, int64_t lda, const unsigned short* zs, double* W, int64_t ldw,
                              int64_t m, int64_t n, int slices, double* kpart, hipStream_t s) {
   const int cb = col_blocks(n);
@@ -611,26 +663,19 @@ hipError_t launch_gemm_split(const double* A, int64_t lda, const unsigned short*
   dim3 grid(ceil_div(m, BM), ceil_div(n, 64 * cb), k.ks);
   double* out = k.ks > 1 ? kpart : W;
   const int64_t ldo = k.ks > 1 ? m : ldw, stride = k.ks > 1 ? m * n : 0;
-  if (cb == 4) {
-    if (slices == 2)
-      gemm_split2_kernel<2><<<grid, NT2, 0, s>>>(A, lda, zs, out, ldo, (int)m, (int)n, k.kchunk, stride);
-    else
-      gemm_split2_kernel<3><<<grid, NT2, 0, s>>>(A, lda, zs, out, ldo, (int)m, (int)n, k.kchunk, stride);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess || k.ks == 1) return e;
-    return ksum(kpart, k.ks, m, n, W, ldw, s);
-  }
-#define OQR_SPLIT_CASE(S_, CB_) \
-  gemm_split_kernel<S_, CB_><<<grid, NT, 0, s>>>(A, lda, zs, out, ldo, (int)m, (int)n, k.kchunk, stride)
-  if (slices == 2) {
-    if (cb == 1) OQR_SPLIT_CASE(2, 1); else OQR_SPLIT_CASE(2, 2);
-  } else {
-    if (cb == 1) OQR_SPLIT_CASE(3, 1); else OQR_SPLIT_CASE(3, 2);
-  }
-#undef OQR_SPLIT_CASE
-  hipError_t e = hipGetLastError();
+  hipError_t e = split_launch<GEMM_FULL>(A, lda, zs, out, ldo, m, n, slices, grid, k.kchunk, stride, s);
   if (e != hipSuccess || k.ks == 1) return e;
   return ksum(kpart, k.ks, m, n, W, ldw, s);
+}
+
+hipError_t launch_symm_split_upper(const double* A, int64_t lda, const unsigned short* zs, double* Woff, int64_t ldw,
+                                   int64_t m, int64_t n, int slices, double* kpart, hipStream_t s) {
+  const int cb = col_blocks(n);
+  const int R = ceil_div(m, BM), P = (R + 1) / 2, ycb = ceil_div(n, 64 * cb);
+  const int H = symm_layers(m, n, kpart);
+  double* out = H > 1 ? kpart : Woff;
+  const int64_t ldo = H > 1 ? m : ldw, stride = H > 1 ? m * n : 0;
+  return split_launch<GEMM_UPPER>(A, lda, zs, out, ldo, m, n, slices, dim3(P, ycb, H), 0, stride, s);
 }
 
 size_t split_z_elems(int64_t m, int64_t n, int slices) {
