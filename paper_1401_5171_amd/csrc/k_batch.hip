@@ -79,9 +79,11 @@ struct Smem {
   double dmax;
 };
 
-// G = X^T A X for one instance, streaming A once by row blocks of BR rows:
-//   W_b = A_b X (MFMA, W_b in registers), then G += X_b^T W_b with W_b's accumulators used directly as
-//   the B operand (the FP64 MFMA's D layout is its B layout, one K step per accumulator element).
+// G = X^T A X for one instance, A symmetric: row block b (BR rows) streams only its diagonal block and
+// the blocks right of it, W_b = A_b,diag X_b + A_b,right X (MFMA, W_b in registers), and
+// G = D + H + H^T with D += X_b^T (A_b,diag X_b) and H += X_b^T (A_b,right X), so A is read about half;
+// W_b's accumulators serve directly as the B operand of X_b^T W_b (the FP64 MFMA's D layout is its
+// B layout, one K step per accumulator element).
 // Wave w owns the 16 columns cb = w % CLS of W and G and the row group rg = w / CLS of each row block
 // (RG = 4 / CLS groups of 16 * RBW rows).  On return, waves of row group 0 hold G(:, 16 cb ..) in g.
 template <class T, int CLS>
@@ -97,8 +99,9 @@ __device__ __noinline__ void gram_phase(const T* A_, int64_t lda_, const T* X_, 
   const int cb = wave % CLS, rg = wave / CLS;
   const int nbk = (n + 15) / 16;
   const bool active = cb < nbk;               // wave-uniform
+  f64x4 h[4];                                  // H (the blocks right of the diagonal)
 #pragma unroll
-  for (int b = 0; b < 4; ++b) g[b] = f64x4{0, 0, 0, 0};
+  for (int b = 0; b < 4; ++b) g[b] = h[b] = f64x4{0, 0, 0, 0};
   // tile loads: A 16 values per thread (row t % BR, k = t / BR + 2q), X 8 values (k = t % BK, col t / BK + 8q),
   // unconditional buffer loads (elements outside the matrix read as 0), consumed only at the next LDS store
   const int ai = t % BR, ak = t / BR;
@@ -124,8 +127,29 @@ __device__ __noinline__ void gram_phase(const T* A_, int64_t lda_, const T* X_, 
     f64x4 w[RBW];
 #pragma unroll
     for (int b = 0; b < RBW; ++b) w[b] = f64x4{0, 0, 0, 0};
-    load(0);
-    for (int k0 = 0; k0 < m; k0 += BK) {
+    // dst += X_b^T W_b over this wave's rows
+    auto accum = [&](f64x4 (&dst)[4]) {
+      if (!active) return;
+#pragma unroll
+      for (int rb = 0; rb < RBW; ++rb) {
+        const int rbase = r0 + 16 * RBW * rg + 16 * rb;
+        double xa[4][4];
+#pragma unroll
+        for (int s4 = 0; s4 < 4; ++s4)
+#pragma unroll
+          for (int gi = 0; gi < 4; ++gi) {
+            const int row = rbase + 4 * s4 + li, col = 16 * gi + lj;
+            xa[s4][gi] = ldv(X, (int64_t)col * ldx + row, row < m && col < n);
+          }
+#pragma unroll
+        for (int s4 = 0; s4 < 4; ++s4)
+#pragma unroll
+          for (int gi = 0; gi < 4; ++gi)
+            if (gi < nbk) dst[gi] = mfma_f64(xa[s4][gi], w[rb][s4], dst[gi]);
+      }
+    };
+    const int dend = min(m, r0 + BR);          // end of the diagonal block
+    auto kstep = [&](int k0) {
 #pragma unroll
       for (int q = 0; q < BR * BK / NT; ++q) S.tl.As[ak + 2 * q][ai] = (double)ra[q];
 #pragma unroll
@@ -143,47 +167,59 @@ __device__ __noinline__ void gram_phase(const T* A_, int64_t lda_, const T* X_, 
         }
       }
       __syncthreads();
-    }
-    // G(:, cb) += X_b^T W_b over this wave's rows
-    if (active) {
+    };
+    load(r0);
+    for (int k0 = r0; k0 < dend; k0 += BK) kstep(k0);
+    accum(g);                                  // D += X_b^T (A_b,diag X_b)
+    if (dend < m) {
 #pragma unroll
-      for (int rb = 0; rb < RBW; ++rb) {
-        const int rbase = r0 + 16 * RBW * rg + 16 * rb;
-        double xa[4][4];
-#pragma unroll
-        for (int s4 = 0; s4 < 4; ++s4)
-#pragma unroll
-          for (int gi = 0; gi < 4; ++gi) {
-            const int row = rbase + 4 * s4 + li, col = 16 * gi + lj;
-            xa[s4][gi] = ldv(X, (int64_t)col * ldx + row, row < m && col < n);
-          }
-#pragma unroll
-        for (int s4 = 0; s4 < 4; ++s4)
-#pragma unroll
-          for (int gi = 0; gi < 4; ++gi)
-            if (gi < nbk) g[gi] = mfma_f64(xa[s4][gi], w[rb][s4], g[gi]);
-      }
+      for (int b = 0; b < RBW; ++b) w[b] = f64x4{0, 0, 0, 0};
+      for (int k0 = dend; k0 < m; k0 += BK) kstep(k0);
+      accum(h);                                // H += X_b^T (A_b,right X)
     }
   }
   // sum the row groups into the waves of group 0
   if (RG > 1) {
-    if (rg > 0 && active) {
-#pragma unroll
-      for (int gi = 0; gi < 4; ++gi)
-#pragma unroll
-        for (int r = 0; r < 4; ++r) S.red[wave - CLS][gi][r][lane] = g[gi][r];
-    }
-    __syncthreads();
-    if (rg == 0 && active) {
-#pragma unroll
-      for (int q = 1; q < RG; ++q)
+    auto reduce_groups = [&](f64x4 (&v)[4]) {
+      if (rg > 0 && active) {
 #pragma unroll
         for (int gi = 0; gi < 4; ++gi)
 #pragma unroll
-          for (int r = 0; r < 4; ++r) g[gi][r] += S.red[q * CLS + wave - CLS][gi][r][lane];
-    }
-    __syncthreads();
+          for (int r = 0; r < 4; ++r) S.red[wave - CLS][gi][r][lane] = v[gi][r];
+      }
+      __syncthreads();
+      if (rg == 0 && active) {
+#pragma unroll
+        for (int q = 1; q < RG; ++q)
+#pragma unroll
+          for (int gi = 0; gi < 4; ++gi)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) v[gi][r] += S.red[q * CLS + wave - CLS][gi][r][lane];
+      }
+      __syncthreads();
+    };
+    reduce_groups(g);
+    reduce_groups(h);
   }
+  // G = D + H + H^T: H through LDS (Ws is free until the end of the pass)
+  const bool own = rg == 0 && active;
+  if (own) {
+#pragma unroll
+    for (int gi = 0; gi < 4; ++gi)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) S.f.Ws[gi * 16 + 4 * r + li][cb * 16 + lj] = h[gi][r];
+  }
+  __syncthreads();
+  if (own) {
+#pragma unroll
+    for (int gi = 0; gi < 4; ++gi)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int i = gi * 16 + 4 * r + li, j = cb * 16 + lj;
+        g[gi][r] += h[gi][r] + ((i < nbk * 16) ? S.f.Ws[j][i] : 0.0);
+      }
+  }
+  __syncthreads();
 }
 
 // One CHOLQR pass on instance (A, X) in place: X <- X R^{-1}, R into smem Gs (upper, zero lower).
