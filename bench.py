@@ -38,7 +38,9 @@ PEAK = {"fp64": 78.6e12, "bf16": 2.5e15, "hbm": 8.0e12}
 # then WRITE_SIZE, KiB per dispatch) scaled by what the same counters read for a 1 GiB copy
 # (--workload copycal: FETCH_SIZE x 2.0, WRITE_SIZE x 1.0).  Only for the kernel build they were taken
 # on; workloads without an entry report null.
-TRAFFIC = {}
+TRAFFIC = {
+    ("dense32768", "gemm_f64"): (9499978.4 * 2.0 + 131200.0 * 1.0) * 1024,
+}
 
 
 def upper_product_flops(m, n, bm=64):
