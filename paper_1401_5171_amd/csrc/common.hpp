@@ -95,6 +95,15 @@ __device__ __forceinline__ uint4 buf_b128(bufrsrc r, uint32_t off) {
   return make_uint4(v.x, v.y, v.z, v.w);
 }
 
+// 1 / sqrt(x) for finite x > 0: the hardware estimate refined by two Newton steps (a dependent chain
+// of seven operations instead of a correctly rounded square root and a division; the result is within
+// about one unit in the last place).
+__device__ __forceinline__ double rsqrt_nr(double x) {
+  double r = __builtin_amdgcn_rsq(x);
+  r = fma(0.5 * r, fma(-x * r, r, 1.0), r);
+  return fma(0.5 * r, fma(-x * r, r, 1.0), r);
+}
+
 inline int ceil_div(int64_t a, int64_t b) { return (int)((a + b - 1) / b); }
 // Leading dimension of the bfloat16 slices of Z: m rounded up to a multiple of 32.
 __host__ __device__ inline int64_t split_ld(int64_t m) { return (m + 31) & ~(int64_t)31; }

@@ -139,7 +139,7 @@ __global__ __launch_bounds__(NTC) void chol_kernel(const double* __restrict__ G,
           if (t == 0) s_fail = k0 + k + 1;
           break;
         }
-        const double rkk = sqrt(piv), ri = 1.0 / rkk;   // one reciprocal per pivot
+        const double ri = rsqrt_nr(piv), rkk = piv * ri;   // one refined reciprocal square root per pivot
         if (t == 0) rdiag[k] = ri;
 #pragma unroll
         for (int e = 0; e < DPT; ++e) {
