@@ -343,16 +343,14 @@ __global__ __launch_bounds__(NT, 1) void gemm_split_kernel(const double* __restr
 }
 
 // Split bfloat16 product for n in (128, 256]: 512 threads (two waves per SIMD), a 64-row block of W
-// over 256 columns.  Wave (rh, cq) owns rows 32 rh .. + 31 and columns 64 cq .. + 63 (2 x 4 tiles).
-// Per K step of 32 the workgroup stages the A tile (converted to S slices) and the B tile (the K step's
-// slices of Z, one contiguous block of the tiled layout) in double-buffered LDS, one barrier per step;
-// the tiles of the next two steps are in flight in registers (two alternating sets).  B rows in LDS
-// are 64 bytes with the 16-byte chunk index XOR-ed by (column / 2) mod 4.  FP32 accumulation over at
-// most 960 rows of K, folded into FP64 accumulators held in registers.
+// over 256 columns.  Wave w owns all 64 rows and columns 32 w .. 32 w + 31 (4 x 2 tiles).  Per K step
+// of 32 the workgroup converts the A tile into S slices in double-buffered LDS (one barrier per step,
+// the next two A tiles in flight in registers); every wave reads its B fragments (8 consecutive K of a
+// column of a slice: 16 contiguous bytes of the tiled layout) straight from memory into registers,
+// three K steps ahead, so that B never passes through LDS and no two waves load the same fragment.
+// FP32 accumulation over at most 960 rows of K, folded into FP64 accumulators held in registers.
 constexpr int NT2 = 512;
 constexpr int BN2 = 256;
-
-__device__ __forceinline__ int bsw(int col, int ch) { return col * BKS + 8 * (ch ^ ((col >> 1) & 3)); }
 
 template <int S, int MODE>
 __global__ __launch_bounds__(NT2, 1) void gemm_split2_kernel(const double* __restrict__ A, int64_t lda,
@@ -360,43 +358,46 @@ __global__ __launch_bounds__(NT2, 1) void gemm_split2_kernel(const double* __res
                                                              double* __restrict__ W, int64_t ldw, int m, int n,
                                                              int kchunk, int64_t wstride) {
   __shared__ __attribute__((aligned(16))) unsigned short As[2][S][BM][SROW];
-  __shared__ __attribute__((aligned(16))) unsigned short Bs[2][S][BN2 * BKS];
   const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
-  const int rh = wave >> 2, cq = wave & 3;
   const int64_t mp = split_ld(m);
   constexpr int64_t TILE = (int64_t)S * BN2 * BKS;   // bf16 elements of one K step of the tiled slices
   // the current segment: rows [i0, i0 + BM), K [kb, ke) (kb a multiple of BKS)
   int i0 = 0, kb = 0, ke = 0;
   W += blockIdx.z * wstride;
 
-  f32x4 acc[2][4];
-  double dacc[2][4][4];
+  f32x4 acc[4][2];
+  double dacc[4][2][4];
   // A tile 64 x 32: thread t loads row ai = t % 64, k = 4 aq .. 4 aq + 3 (aq = t / 64)
   const int ai = t % BM, aq = t / BM;
   uint32_t aoff[4];
-  // B tile: S slices x 256 columns x 32 rows = S * 1024 chunks of 16 bytes; chunk c = t + 512 u:
-  // slice c / 1024, column (c / 4) % 256, rows 8 (c % 4) .. + 7 (offsets inside the contiguous tile)
-  constexpr int BU = S * 1024 / NT2;
-  uint32_t boff[BU];
+  // B fragment (slice q, tile b): lane holds K kq .. kq + 7 of column 32 wave + 16 b + lane % 16
+  const int kq = 8 * (lane >> 4);
+  uint32_t fb[S][2];
 #pragma unroll
-  for (int u = 0; u < BU; ++u) {
-    const int c = t + NT2 * u, sl = c / 1024, col = (c / 4) % BN2, q = c % 4;
-    boff[u] = (col < n) ? (uint32_t)((((int64_t)sl * BN2 + col) * BKS + 8 * q) * 2) : kOOB;
-  }
+  for (int q = 0; q < S; ++q)
+#pragma unroll
+    for (int b = 0; b < 2; ++b) {
+      const int col = 32 * wave + 16 * b + (lane & 15);
+      fb[q][b] = (col < n) ? (uint32_t)((((int64_t)q * BN2 + col) * BKS + kq) * 2) : kOOB;
+    }
   double ra0[4], ra1[4];
-  uint4 rb0[BU], rb1[BU];
-  auto load = [&](int k0, double (&ra)[4], uint4 (&rb)[BU]) {
+  uint4 bq0[S][2], bq1[S][2], bq2[S][2];
+  auto load_a = [&](int k0, double (&ra)[4]) {
     const bufrsrc abuf = make_buf(A + (int64_t)min(k0, ke) * lda + i0, (int64_t)(ke - min(k0, ke)) * lda * 8);
 #pragma unroll
     for (int e = 0; e < 4; ++e) ra[e] = buf_f64(abuf, aoff[e]);
+  };
+  auto load_b = [&](int k0, uint4 (&bq)[S][2]) {
     // the K step's tile of slices; past the slice (or the padded end) the buffer is empty
     const bool live = k0 < ke || (ke == m && k0 < mp);
     const bufrsrc zbuf = make_buf(zs + (live ? (int64_t)(k0 / BKS) * TILE : 0), live ? TILE * 2 : 0);
 #pragma unroll
-    for (int u = 0; u < BU; ++u) rb[u] = buf_b128(zbuf, boff[u]);
+    for (int q = 0; q < S; ++q)
+#pragma unroll
+      for (int b = 0; b < 2; ++b) bq[q][b] = buf_b128(zbuf, fb[q][b]);
   };
-  auto store = [&](int buf, const double (&ra)[4], const uint4 (&rb)[BU]) {
-    // A: FP64 -> FP32 -> S bf16 slices (RNE, two per v_cvt_pk_bf16_f32); remainders exact in FP32
+  auto store_a = [&](int buf, const double (&ra)[4]) {
+    // FP64 -> FP32 -> S bf16 slices (RNE, two per v_cvt_pk_bf16_f32); remainders exact in FP32
     f32x2 r[2] = {f32x2{(float)ra[0], (float)ra[1]}, f32x2{(float)ra[2], (float)ra[3]}};
 #pragma unroll
     for (int sl = 0; sl < S; ++sl) {
@@ -411,88 +412,87 @@ __global__ __launch_bounds__(NT2, 1) void gemm_split2_kernel(const double* __res
       }
       *reinterpret_cast<uint2*>(&As[buf][sl][ai][aq * 4]) = make_uint2(w[0], w[1]);
     }
-#pragma unroll
-    for (int u = 0; u < BU; ++u) {
-      const int c = t + NT2 * u, sl = c / 1024, col = (c / 4) % BN2, q = c % 4;
-      *reinterpret_cast<uint4*>(&Bs[buf][sl][bsw(col, q)]) = rb[u];
-    }
   };
   auto fold = [&]() {
 #pragma unroll
-    for (int a = 0; a < 2; ++a)
+    for (int a = 0; a < 4; ++a)
 #pragma unroll
-      for (int b = 0; b < 4; ++b) {
+      for (int b = 0; b < 2; ++b) {
 #pragma unroll
         for (int r = 0; r < 4; ++r) dacc[a][b][r] += (double)acc[a][b][r];
         acc[a][b] = f32x4{0.f, 0.f, 0.f, 0.f};
       }
   };
-  const int kq = 8 * (lane >> 4);
-  auto compute = [&](int st) {
+  auto compute = [&](int st, const uint4 (&bq)[S][2]) {
     const int cur = st & 1;
-    bf16x8 af[S][2];
 #pragma unroll
-    for (int p = 0; p < S; ++p)
+    for (int a = 0; a < 4; ++a) {
+      bf16x8 af[S];
 #pragma unroll
-      for (int a = 0; a < 2; ++a)
-        af[p][a] = __builtin_bit_cast(bf16x8, *reinterpret_cast<const u16x8*>(&As[cur][p][32 * rh + 16 * a + (lane & 15)][kq]));
-#pragma unroll
-    for (int b = 0; b < 4; ++b) {
-      bf16x8 bf[S];
-#pragma unroll
-      for (int q = 0; q < S; ++q)
-        bf[q] = __builtin_bit_cast(bf16x8,
-                                   *reinterpret_cast<const u16x8*>(&Bs[cur][q][bsw(64 * cq + 16 * b + (lane & 15), kq / 8)]));
+      for (int p = 0; p < S; ++p)
+        af[p] = __builtin_bit_cast(bf16x8, *reinterpret_cast<const u16x8*>(&As[cur][p][16 * a + (lane & 15)][kq]));
 #pragma unroll
       for (int p = 0; p < S; ++p)
 #pragma unroll
         for (int q = 0; q < S - p; ++q)
 #pragma unroll
-          for (int a = 0; a < 2; ++a)
-            acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[p][a], bf[q], acc[a][b], 0, 0, 0);
+          for (int b = 0; b < 2; ++b)
+            acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[p], __builtin_bit_cast(bf16x8, bq[q][b]),
+                                                                acc[a][b], 0, 0, 0);
     }
     if (st % 30 == 29) fold();                // FP32 accumulation over at most 960 rows of K
   };
 
   auto segment = [&]() {
 #pragma unroll
-  for (int a = 0; a < 2; ++a)
+    for (int a = 0; a < 4; ++a)
 #pragma unroll
-    for (int b = 0; b < 4; ++b) {
-      acc[a][b] = f32x4{0.f, 0.f, 0.f, 0.f};
+      for (int b = 0; b < 2; ++b) {
+        acc[a][b] = f32x4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-      for (int r = 0; r < 4; ++r) dacc[a][b][r] = 0.0;
-    }
-#pragma unroll
-  for (int e = 0; e < 4; ++e) aoff[e] = (i0 + ai < m) ? (uint32_t)(((int64_t)(aq * 4 + e) * lda + ai) * 8) : kOOB;
-  // K steps padded to an even count (steps past the end load empty buffers and add zeros)
-  const int nsteps = ((ke - kb + BKS - 1) / BKS + 1) / 2 * 2;
-  load(kb, ra0, rb0);
-  store(0, ra0, rb0);
-  __syncthreads();
-  load(kb + BKS, ra0, rb0);
-  load(kb + 2 * BKS, ra1, rb1);
-  for (int st = 0; st < nsteps; st += 2) {
-    compute(st);
-    store(1, ra0, rb0);                       // tiles of step st + 1
-    load(kb + (st + 3) * BKS, ra0, rb0);
-    __syncthreads();
-    compute(st + 1);
-    store(0, ra1, rb1);                       // tiles of step st + 2
-    load(kb + (st + 4) * BKS, ra1, rb1);
-    __syncthreads();
-  }
-  fold();
-#pragma unroll
-  for (int a = 0; a < 2; ++a)
-#pragma unroll
-    for (int b = 0; b < 4; ++b)
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int i = i0 + 32 * rh + 16 * a + 4 * (lane >> 4) + r;
-        const int j = 64 * cq + 16 * b + (lane & 15);
-        if (i < m && j < n) W[(int64_t)j * ldw + i] = dacc[a][b][r];
+        for (int r = 0; r < 4; ++r) dacc[a][b][r] = 0.0;
       }
+#pragma unroll
+    for (int e = 0; e < 4; ++e) aoff[e] = (i0 + ai < m) ? (uint32_t)(((int64_t)(aq * 4 + e) * lda + ai) * 8) : kOOB;
+    // K steps padded to a multiple of 6 (2 A buffers x 3 B stages); steps past the end read empty
+    // buffers and add zeros
+    const int nsteps = ((ke - kb + BKS - 1) / BKS + 5) / 6 * 6;
+    load_a(kb, ra0);
+    load_b(kb, bq0);
+    load_b(kb + BKS, bq1);
+    load_b(kb + 2 * BKS, bq2);
+    store_a(0, ra0);
+    __syncthreads();
+    load_a(kb + BKS, ra0);
+    load_a(kb + 2 * BKS, ra1);
+    // step st: MFMAs on A buffer st & 1 and B stage st % 3; A(st + 1) into the other buffer; A and B of
+    // step st + 3 requested
+#define OQR_SPLIT2_STEP(st, RA, BQ)       \
+  compute(st, BQ);                        \
+  store_a(((st) + 1) & 1, RA);            \
+  load_a(kb + ((st) + 3) * BKS, RA);      \
+  load_b(kb + ((st) + 3) * BKS, BQ);      \
+  __syncthreads();
+    for (int st = 0; st < nsteps; st += 6) {
+      OQR_SPLIT2_STEP(st + 0, ra0, bq0)
+      OQR_SPLIT2_STEP(st + 1, ra1, bq1)
+      OQR_SPLIT2_STEP(st + 2, ra0, bq2)
+      OQR_SPLIT2_STEP(st + 3, ra1, bq0)
+      OQR_SPLIT2_STEP(st + 4, ra0, bq1)
+      OQR_SPLIT2_STEP(st + 5, ra1, bq2)
+    }
+#undef OQR_SPLIT2_STEP
+    fold();
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+      for (int b = 0; b < 2; ++b)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int i = i0 + 16 * a + 4 * (lane >> 4) + r;
+          const int j = 32 * wave + 16 * b + (lane & 15);
+          if (i < m && j < n) W[(int64_t)j * ldw + i] = dacc[a][b][r];
+        }
   };
 
   if (MODE == GEMM_UPPER) {
@@ -501,7 +501,7 @@ __global__ __launch_bounds__(NT2, 1) void gemm_split2_kernel(const double* __res
     i0 = sa.tile * BM, kb = sa.k0, ke = sa.k1;
     segment();
     if (two) {
-      __syncthreads();                  // the last reads of As / Bs
+      __syncthreads();                  // the last reads of As
       i0 = sb.tile * BM, kb = sb.k0, ke = sb.k1;
       segment();
     }
