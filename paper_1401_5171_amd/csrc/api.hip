@@ -188,9 +188,7 @@ size_t pass_ws(const oqr_op* A, int64_t m, int64_t n, const oqr_opts& o, bool tw
 // G = Z^T A Z for symmetric A from Woff (strictly upper block triangle of A times Z) and Wsym (Woff plus
 // the diagonal blocks): G = Z^T Wsym + Woff^T Z, upper triangle.
 hipError_t gram_symm(const double* Z, int64_t ldz, int64_t m, int64_t n, const PassWs& w, hipStream_t s) {
-  hipError_t e = launch_gram_f64(Z, ldz, w.Ws, m, m, n, w.partial, w.G, s);
-  if (e != hipSuccess) return e;
-  return launch_gram_f64(w.W, m, Z, ldz, m, n, w.partial, w.G, s, true);
+  return launch_gram_symm(Z, ldz, w.Ws, w.W, m, m, n, w.partial, w.G, s);
 }
 
 // One CHOLQR pass (Algorithm 1) on the device: W = A Z; G = Z^T W; R = chol(G [+ s I]); Q = Z R^{-1}.

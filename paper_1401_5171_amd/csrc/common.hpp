@@ -154,6 +154,9 @@ hipError_t launch_sparse_apply(const oqr_op* op, const double* Z, int64_t ldz, d
 
 // Gram: partial[c] = (X^T Y) restricted to row chunk c, upper 64x64 tiles; then G = sum_c partial[c].
 size_t gram_partial_bytes(int64_t m, int64_t n);
+// G = Z^T Wsym + Woff^T Z (upper triangle; both products accumulated in the same tiles, one pass).
+hipError_t launch_gram_symm(const double* Z, int64_t ldz, const double* Wsym, const double* Woff, int64_t ldw,
+                            int64_t m, int64_t n, double* partial, double* G, hipStream_t s);
 // accumulate: G += X^T Y instead of G = X^T Y.
 hipError_t launch_gram_f64(const double* X, int64_t ldx, const double* Y, int64_t ldy, int64_t m, int64_t n,
                            double* partial, double* G, hipStream_t s, bool accumulate = false);

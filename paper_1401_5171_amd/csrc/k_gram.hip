@@ -44,11 +44,16 @@ __device__ __forceinline__ void tile_of(int t, int nb, int& I, int& J) {
 constexpr int BK = 16;
 constexpr int PAD = 8;
 
+// SYM: G = X^T Y + X2^T X (the symmetric assembly Z^T Wsym + Woff^T Z with X = Z, Y = Wsym, X2 = Woff).
+template <bool SYM>
 __global__ __launch_bounds__(NT) void gram_f64_kernel(const double* __restrict__ X, int64_t ldx,
-                                                       const double* __restrict__ Y, int64_t ldy, int m, int n,
+                                                       const double* __restrict__ Y, int64_t ldy,
+                                                       const double* __restrict__ X2, int64_t ldx2, int m, int n,
                                                        int nb, int kc, double* __restrict__ partial) {
   __shared__ double Xs[BK][TB + PAD];
   __shared__ double Ys[BK][TB + PAD];
+  __shared__ double X2s[SYM ? BK : 1][TB + PAD];    // X2 columns of block I
+  __shared__ double XJs[SYM ? BK : 1][TB + PAD];    // X columns of block J
   int I, J;
   tile_of(blockIdx.x, nb, I, J);
   const int c = blockIdx.y;
@@ -59,7 +64,7 @@ __global__ __launch_bounds__(NT) void gram_f64_kernel(const double* __restrict__
 #pragma unroll
   for (int b = 0; b < 4; ++b) acc[b] = f64x4{0, 0, 0, 0};
   const int lk = t % BK, lc = t / BK;   // k = lk, column = lc + 16 r
-  double rx[4], ry[4];
+  double rx[4], ry[4], rx2[SYM ? 4 : 1], rxj[SYM ? 4 : 1];
   auto load = [&](int k0) {
     const int k = k0 + lk;
 #pragma unroll
@@ -67,6 +72,10 @@ __global__ __launch_bounds__(NT) void gram_f64_kernel(const double* __restrict__
       const int cx = I0 + lc + 16 * r, cy = J0 + lc + 16 * r;
       rx[r] = sel_load(X, (int64_t)cx * ldx + k, k < r1 && cx < n);
       ry[r] = sel_load(Y, (int64_t)cy * ldy + k, k < r1 && cy < n);
+      if (SYM) {
+        rx2[r] = sel_load(X2, (int64_t)cx * ldx2 + k, k < r1 && cx < n);
+        rxj[r] = sel_load(X, (int64_t)cy * ldx + k, k < r1 && cy < n);
+      }
     }
   };
   auto store = [&]() {
@@ -74,6 +83,10 @@ __global__ __launch_bounds__(NT) void gram_f64_kernel(const double* __restrict__
     for (int r = 0; r < 4; ++r) {
       Xs[lk][lc + 16 * r] = rx[r];
       Ys[lk][lc + 16 * r] = ry[r];
+      if (SYM) {
+        X2s[lk][lc + 16 * r] = rx2[r];
+        XJs[lk][lc + 16 * r] = rxj[r];
+      }
     }
   };
   load(r0);
@@ -88,6 +101,11 @@ __global__ __launch_bounds__(NT) void gram_f64_kernel(const double* __restrict__
       const double a = Xs[kr][wave * 16 + (lane & 15)];
 #pragma unroll
       for (int b = 0; b < 4; ++b) acc[b] = mfma_f64(a, Ys[kr][b * 16 + (lane & 15)], acc[b]);
+      if (SYM) {
+        const double a2 = X2s[kr][wave * 16 + (lane & 15)];
+#pragma unroll
+        for (int b = 0; b < 4; ++b) acc[b] = mfma_f64(a2, XJs[kr][b * 16 + (lane & 15)], acc[b]);
+      }
     }
     __syncthreads();
     if (more) {
@@ -230,25 +248,28 @@ __device__ __forceinline__ bufrsrc block_buf(const double* base, int64_t ld, int
   return make_buf(base + (int64_t)c0 * ld + r0, ((int64_t)(cols - 1) * ld + (m - r0)) * 8);
 }
 
-template <int NBT>
+template <int NBT, bool SYM>
 __global__ __launch_bounds__(NT, 2) void gram_full_f64_kernel(const double* __restrict__ X, int64_t ldx,
-                                                             const double* __restrict__ Y, int64_t ldy, int m, int n,
-                                                             int kc, double* __restrict__ partial) {
+                                                             const double* __restrict__ Y, int64_t ldy,
+                                                             const double* __restrict__ X2, int64_t ldx2, int m,
+                                                             int n, int kc, double* __restrict__ partial) {
   __shared__ double Xs[NBT][BK][TB + 1];
   __shared__ double Ys[NBT][BK][TB + 1];
+  __shared__ double X2s[SYM ? NBT : 1][BK][TB + 1];
   const int c = blockIdx.x;
   const int r0 = c * kc, r1 = min(m, r0 + kc);
   const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
   const int li = lane >> 4, lj = lane & 15;
-  bufrsrc xb[NBT], yb[NBT];
+  bufrsrc xb[NBT], yb[NBT], x2b[NBT];
 #pragma unroll
   for (int b = 0; b < NBT; ++b) {
     xb[b] = block_buf(X, ldx, m, n, r0, b * TB);
     yb[b] = block_buf(Y, ldy, m, n, r0, b * TB);
+    if (SYM) x2b[b] = block_buf(X2, ldx2, m, n, r0, b * TB);
   }
   // thread: k = t % BK, columns lc + 16 q (q = 0..3) of each block
   const int lk = t % BK, lc = t / BK;
-  double rx[NBT][4], ry[NBT][4];
+  double rx[NBT][4], ry[NBT][4], rx2[SYM ? NBT : 1][4];
   auto load = [&](int k0) {
     const int k = k0 + lk;                    // absolute row
 #pragma unroll
@@ -260,6 +281,10 @@ __global__ __launch_bounds__(NT, 2) void gram_full_f64_kernel(const double* __re
         const uint32_t oy = (k < r1) ? (uint32_t)((int64_t)col * ldy + (k - r0)) * 8u : kOOB;
         rx[b][q] = buf_f64(xb[b], ox);
         ry[b][q] = buf_f64(yb[b], oy);
+        if (SYM) {
+          const uint32_t o2 = (k < r1) ? (uint32_t)((int64_t)col * ldx2 + (k - r0)) * 8u : kOOB;
+          rx2[b][q] = buf_f64(x2b[b], o2);
+        }
       }
   };
   constexpr int NTILE = NBT * (NBT + 1) / 2;
@@ -276,6 +301,7 @@ __global__ __launch_bounds__(NT, 2) void gram_full_f64_kernel(const double* __re
       for (int q = 0; q < 4; ++q) {
         Xs[b][lk][lc + 16 * q] = rx[b][q];
         Ys[b][lk][lc + 16 * q] = ry[b][q];
+        if (SYM) X2s[b][lk][lc + 16 * q] = rx2[b][q];
       }
     __syncthreads();
     load(k0 + BK);                            // past r1: kOOB, zeros
@@ -286,10 +312,14 @@ __global__ __launch_bounds__(NT, 2) void gram_full_f64_kernel(const double* __re
 #pragma unroll
       for (int I = 0; I < NBT; ++I) {
         const double a = Xs[I][kr][wave * 16 + lj];
+        const double a2 = SYM ? X2s[I][kr][wave * 16 + lj] : 0.0;
 #pragma unroll
         for (int J = I; J < NBT; ++J, ++u)
 #pragma unroll
-          for (int q = 0; q < 4; ++q) acc[u][q] = mfma_f64(a, Ys[J][kr][q * 16 + lj], acc[u][q]);
+          for (int q = 0; q < 4; ++q) {
+            acc[u][q] = mfma_f64(a, Ys[J][kr][q * 16 + lj], acc[u][q]);
+            if (SYM) acc[u][q] = mfma_f64(a2, Xs[J][kr][q * 16 + lj], acc[u][q]);
+          }
       }
     }
     __syncthreads();
@@ -466,23 +496,35 @@ static hipError_t reduce(const double* partial, int64_t n, int chunks, double* G
   return hipGetLastError();
 }
 
-hipError_t launch_gram_f64(const double* X, int64_t ldx, const double* Y, int64_t ldy, int64_t m, int64_t n,
-                           double* partial, double* G, hipStream_t s, bool accumulate) {
+template <bool SYM>
+static hipError_t gram_f64(const double* X, int64_t ldx, const double* Y, int64_t ldy, const double* X2, int64_t ldx2,
+                           int64_t m, int64_t n, double* partial, double* G, hipStream_t s, bool accumulate) {
   if (n <= 2 * TB) {
     const FullPlan f = full_plan(m, BK);
     if (n <= TB)
-      gram_full_f64_kernel<1><<<f.chunks, NT, 0, s>>>(X, ldx, Y, ldy, (int)m, (int)n, f.kc, partial);
+      gram_full_f64_kernel<1, SYM><<<f.chunks, NT, 0, s>>>(X, ldx, Y, ldy, X2, ldx2, (int)m, (int)n, f.kc, partial);
     else
-      gram_full_f64_kernel<2><<<f.chunks, NT, 0, s>>>(X, ldx, Y, ldy, (int)m, (int)n, f.kc, partial);
+      gram_full_f64_kernel<2, SYM><<<f.chunks, NT, 0, s>>>(X, ldx, Y, ldy, X2, ldx2, (int)m, (int)n, f.kc, partial);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     return reduce(partial, n, f.chunks, G, s, accumulate);
   }
   GramPlan p = plan(m, n);
-  gram_f64_kernel<<<dim3(p.tiles, p.chunks), NT, 0, s>>>(X, ldx, Y, ldy, (int)m, (int)n, p.nb, p.kc, partial);
+  gram_f64_kernel<SYM><<<dim3(p.tiles, p.chunks), NT, 0, s>>>(X, ldx, Y, ldy, X2, ldx2, (int)m, (int)n, p.nb, p.kc,
+                                                              partial);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   return reduce(partial, n, p.chunks, G, s, accumulate);
+}
+
+hipError_t launch_gram_f64(const double* X, int64_t ldx, const double* Y, int64_t ldy, int64_t m, int64_t n,
+                           double* partial, double* G, hipStream_t s, bool accumulate) {
+  return gram_f64<false>(X, ldx, Y, ldy, nullptr, 0, m, n, partial, G, s, accumulate);
+}
+
+hipError_t launch_gram_symm(const double* Z, int64_t ldz, const double* Wsym, const double* Woff, int64_t ldw,
+                            int64_t m, int64_t n, double* partial, double* G, hipStream_t s) {
+  return gram_f64<true>(Z, ldz, Wsym, ldw, Woff, ldw, m, n, partial, G, s, false);
 }
 
 hipError_t launch_gram_split(const double* X, int64_t ldx, const double* Y, int64_t ldy, int64_t m, int64_t n,
