@@ -152,7 +152,9 @@ struct Carve {
 };
 
 struct PassWs {
-  double* W;          // m x n (dense: the strictly upper block triangle of A times Z)
+  double* W;          // m x n, leading dimension ldw (dense: the strictly upper block triangle of A times Z;
+                      // stencil: A Z, or the first-pass Q of CholQR2 when the Gram is fused)
+  int64_t ldw;
   double* Ws;         // m x n (dense: W + the diagonal blocks of A times Z)
   double* partial;    // Gram partials
   double* G;          // n x n
@@ -163,12 +165,21 @@ struct PassWs {
   double* shifts;     // [2] shift used per pass
 };
 
+// Leading dimension of the m x n workspace W.  For the stencil it is padded past a multiple of 128 bytes,
+// so that the rows of different columns fall in different cache sets (with ld = m = 2^k the same row of
+// every column maps to one set, and the neighbour rows that the fused Gram re-reads are evicted).
+int64_t w_ld(const oqr_op* A, int64_t m) { return A->kind == OQR_OP_STENCIL7 ? (m + 15) / 16 * 16 + 16 : m; }
+
 size_t pass_ws(const oqr_op* A, int64_t m, int64_t n, const oqr_opts& o, bool two, PassWs* out, void* base) {
   Carve c{(char*)base, 0};
   PassWs w;
-  w.W = c.take<double>((size_t)m * n);
+  w.ldw = w_ld(A, m);
+  w.W = c.take<double>((size_t)w.ldw * n);
   w.Ws = c.take<double>(A->kind == OQR_OP_DENSE ? (size_t)m * n : 0);
-  w.partial = c.take<double>(gram_partial_bytes(m, n) / sizeof(double));
+  size_t pb = gram_partial_bytes(m, n);
+  const size_t spb = stencil_gram_partial_bytes(A, n);
+  if (spb > pb) pb = spb;
+  w.partial = c.take<double>(pb / sizeof(double));
   w.G = c.take<double>((size_t)n * n);
   w.R1 = c.take<double>((size_t)n * n);
   w.R2 = c.take<double>((size_t)n * n);
@@ -192,6 +203,7 @@ hipError_t gram_symm(const double* Z, int64_t ldz, int64_t m, int64_t n, const P
 }
 
 // One CHOLQR pass (Algorithm 1) on the device: W = A Z; G = Z^T W; R = chol(G [+ s I]); Q = Z R^{-1}.
+// For the 7-point operator in FP64 the first two steps run as one kernel that never stores W.
 // Dense A is symmetric: the product reads only its upper block triangle and G is assembled from the
 // two halves (gram_symm).
 int cholqr_pass(const oqr_op* A, const double* Z, int64_t ldz, int64_t m, int64_t n, double* Q, int64_t ldq,
@@ -211,12 +223,14 @@ int cholqr_pass(const oqr_op* A, const double* Z, int64_t ldz, int64_t m, int64_
                  launch_symm_finish(a, A->lda, Z, ldz, w.W, w.Ws, m, m, n, w.kpart, symm_layers(m, n, w.kpart), s));
     }
     OQR_TRACED(K_GRAM, s, gram_symm(Z, ldz, m, n, w, s));
+  } else if (prec == OQR_P_FP64 && stencil_gram_fits(A, ldz, n)) {
+    OQR_TRACED(K_GRAM, s, launch_stencil_gram(A, Z, ldz, n, w.partial, w.G, s));
   } else {
-    OQR_TRACED(K_STENCIL, s, launch_sparse_apply(A, Z, ldz, w.W, m, n, s));
+    OQR_TRACED(K_STENCIL, s, launch_sparse_apply(A, Z, ldz, w.W, w.ldw, n, s));
     if (prec == OQR_P_FP64)
-      OQR_TRACED(K_GRAM, s, launch_gram_f64(Z, ldz, w.W, m, m, n, w.partial, w.G, s));
+      OQR_TRACED(K_GRAM, s, launch_gram_f64(Z, ldz, w.W, w.ldw, m, n, w.partial, w.G, s));
     else
-      OQR_TRACED(K_GRAM, s, launch_gram_split(Z, ldz, w.W, m, m, n, slices_of(prec), w.partial, w.G, s));
+      OQR_TRACED(K_GRAM, s, launch_gram_split(Z, ldz, w.W, w.ldw, m, n, slices_of(prec), w.partial, w.G, s));
   }
   const bool red = prec != OQR_P_FP64;
   OQR_TRACED(K_CHOL, s, launch_chol_small(w.G, n, R, ldr, red ? U32 : U64, red ? o.shift_c : 0.0,
@@ -379,9 +393,13 @@ int oqr_cholqr2(const oqr_op* A, const double* Z, int64_t ldz, int64_t m, int64_
   const size_t need = pass_ws(A, m, n, o, true, nullptr, nullptr);
   if ((rc = ws_check(ws, ws_bytes, need))) return rc;
   pass_ws(A, m, n, o, true, &w, ws);
-  // pass 1: Z -> (Q1 in Q, R1);  pass 2: Q1 -> (Q in place, R2);  R = R2 R1
-  if ((rc = cholqr_pass(A, Z, ldz, m, n, Q, ldq, w.R1, n, o.pass1, o, w, w.shifts, info_dev, s))) return rc;
-  if ((rc = cholqr_pass(A, Q, ldq, m, n, Q, ldq, w.R2, n, o.pass2, o, w, w.shifts + 1, info_dev, s))) return rc;
+  // pass 1: Z -> (Q1, R1);  pass 2: Q1 -> (Q, R2);  R = R2 R1.  Q1 is kept in Q (pass 2 in place), or, for
+  // the stencil with the fused Gram, in the padded workspace W, whose A Q1 the second pass never stores.
+  const bool q1_in_w = A->kind == OQR_OP_STENCIL7 && o.pass2 == OQR_P_FP64 && stencil_gram_fits(A, w.ldw, n);
+  double* q1 = q1_in_w ? w.W : Q;
+  const int64_t ldq1 = q1_in_w ? w.ldw : ldq;
+  if ((rc = cholqr_pass(A, Z, ldz, m, n, q1, ldq1, w.R1, n, o.pass1, o, w, w.shifts, info_dev, s))) return rc;
+  if ((rc = cholqr_pass(A, q1, ldq1, m, n, Q, ldq, w.R2, n, o.pass2, o, w, w.shifts + 1, info_dev, s))) return rc;
   if (launch_trmm_upper(w.R2, n, w.R1, n, R, ldr, n, info_dev, s) != hipSuccess) return OQR_E_HIP;
   return OQR_OK;
 }

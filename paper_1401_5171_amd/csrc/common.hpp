@@ -157,6 +157,12 @@ size_t gram_partial_bytes(int64_t m, int64_t n);
 // G = Z^T Wsym + Woff^T Z (upper triangle; both products accumulated in the same tiles, one pass).
 hipError_t launch_gram_symm(const double* Z, int64_t ldz, const double* Wsym, const double* Woff, int64_t ldw,
                             int64_t m, int64_t n, double* partial, double* G, hipStream_t s);
+// G = Z^T (A Z) for the 7-point operator (OQR_OP_STENCIL7) in one pass, A Z formed in registers and never
+// stored; fits: n <= 128 and 32-bit offsets inside a 64-column block of Z.
+bool stencil_gram_fits(const oqr_op* op, int64_t ldz, int64_t n);
+size_t stencil_gram_partial_bytes(const oqr_op* op, int64_t n);
+hipError_t launch_stencil_gram(const oqr_op* op, const double* Z, int64_t ldz, int64_t n, double* partial, double* G,
+                               hipStream_t s);
 // accumulate: G += X^T Y instead of G = X^T Y.
 hipError_t launch_gram_f64(const double* X, int64_t ldx, const double* Y, int64_t ldy, int64_t m, int64_t n,
                            double* partial, double* G, hipStream_t s, bool accumulate = false);

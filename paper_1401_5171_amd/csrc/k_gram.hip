@@ -476,6 +476,164 @@ __global__ void gram_reduce_kernel(const double* __restrict__ partial, int n, in
   G[(int64_t)i * n + j] = t;
 }
 
+
+// ---- G = Z^T (A Z) for the 7-point operator, A Z never stored -----------------------------------
+// Steps 1 and 2 of CHOLQR (Algorithm 1) in one pass when A is the matrix-free stencil: the operand Y
+// of the Gram product is A Z, formed in registers from Z, so A Z costs no HBM traffic.  A workgroup
+// owns SP = 16 consecutive points p of the grid plane and a range of planes z, and marches through z:
+// each K step is the 16 rows k = z nx ny + p of all n columns.  A 16-lane row of a wave holds the 16
+// points of one column, so
+//   x-neighbours: the lane to the left or right (DPP row shift); the two points beyond the region's
+//                 ends are loaded by lanes 0 and 15 only;
+//   z-neighbours: planes z - 1 and z + 1 of the same lane, kept in registers as the march goes on;
+//   y-neighbours: two loads (rows +-nx, L2 hits: regions adjacent in y run on the same XCD).
+// Out-of-grid neighbours read as zero (buffer loads past the resource, or masked).
+constexpr int SP = 16;     // plane points per region = rows per K step
+
+// v = old where the DPP source lane lies outside the 16-lane row
+template <int CTRL>
+__device__ __forceinline__ double row_shift(double old, double v) {
+  const long long o = __double_as_longlong(old), x = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_update_dpp((int)o, (int)x, CTRL, 0xf, 0xf, false);
+  const int hi = __builtin_amdgcn_update_dpp((int)(o >> 32), (int)(x >> 32), CTRL, 0xf, 0xf, false);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+constexpr int DPP_ROW_SHL1 = 0x101;   // lane i reads lane i + 1
+constexpr int DPP_ROW_SHR1 = 0x111;   // lane i reads lane i - 1
+
+template <int NBT>
+__global__ __launch_bounds__(NT, 2) void stencil_gram_kernel(const double* __restrict__ Z, int64_t ldz, int n,
+                                                            int nx, int ny, int nz, double center, double off,
+                                                            int zparts, int zlen, double* __restrict__ partial) {
+  constexpr int NQ = 4 * NBT;                 // columns per thread: cg + 16 q
+  __shared__ double Xs[NBT][SP][TB + 1];
+  __shared__ double Ys[NBT][SP][TB + 1];
+  const int G = gridDim.x;
+  const int L = (G & 7) ? (int)blockIdx.x : (int)(blockIdx.x & 7) * (G >> 3) + (int)(blockIdx.x >> 3);
+  const int reg = L / zparts, zpart = L % zparts;
+  const int z0 = zpart * zlen, z1 = min(nz, z0 + zlen);
+  const int sxy = nx * ny;
+  const int m = sxy * nz;
+  const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+  const int li = lane >> 4, lj = lane & 15;
+  const int lk = lane & 15, cg = t >> 4;      // point p0 + lk, columns cg + 16 q
+  // one buffer resource per 16-column group (scalar registers): column cg of group g is column
+  // 16 g + cg of Z, and a thread's offsets are the same in every group
+  bufrsrc zb[NQ];
+#pragma unroll
+  for (int g = 0; g < NQ; ++g) {
+    const int c0 = 16 * g, cols = min(16, n - c0);
+    zb[g] = make_buf(Z + (int64_t)c0 * ldz, cols > 0 ? ((int64_t)(cols - 1) * ldz + m) * 8 : 0);
+  }
+  const int p = reg * SP + lk;
+  const bool in = p < sxy;
+  const int x = p % nx, y = p / nx;
+  const bool xl = in && x > 0, xr = in && x < nx - 1, yl = in && y > 0, yr = in && y < ny - 1;
+  // the neighbour beyond the region: lane 0 loads p - 1, lane 15 loads p + 1
+  const int de = (lk == 0 && xl) ? -1 : (lk == SP - 1 && xr) ? 1 : 0;
+  // Invalid loads get bit 31 of the offset set (past every resource: zero).  Masks are ORed after the
+  // plane offset is added, rather than selected, so that the compiler keeps one unconditional load.
+  const uint32_t o_c = (uint32_t)(((int64_t)cg * ldz + p) * 8);
+  const uint32_t m_c = in ? 0u : kOOB, m_e = de ? 0u : kOOB, m_ym = yl ? 0u : kOOB, m_yp = yr ? 0u : kOOB;
+  const uint32_t o_e = o_c + (uint32_t)(de * 8), o_ym = o_c - (uint32_t)nx * 8u, o_yp = o_c + (uint32_t)nx * 8u;
+  auto plane = [&](int zz) -> uint32_t { return (uint32_t)zz * (uint32_t)sxy * 8u; };
+  // the centres of planes z - 1, z, z + 1 rotate through three arrays (static roles after unrolling)
+  double ca[NQ], cbv[NQ], cc[NQ], e[NQ], ym[NQ], yp[NQ];
+  // centre of plane zz (zero outside the grid)
+  auto load_c = [&](double (&v)[NQ], int zz) {
+    const uint32_t mz = (zz >= 0 && zz < nz) ? 0u : kOOB;
+    const uint32_t oc = (o_c + plane(zz)) | (m_c | mz);
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) v[q] = buf_f64(zb[q], oc);
+  };
+  // edge and y-neighbours of plane zz
+  auto load_n = [&](int zz) {
+    const uint32_t mz = zz < z1 ? 0u : kOOB, pz = plane(zz);
+    const uint32_t oe = (o_e + pz) | (m_e | mz), om = (o_ym + pz) | (m_ym | mz), op = (o_yp + pz) | (m_yp | mz);
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
+      e[q] = buf_f64(zb[q], oe);
+      ym[q] = buf_f64(zb[q], om);
+      yp[q] = buf_f64(zb[q], op);
+    }
+  };
+  constexpr int NTILE = NBT * (NBT + 1) / 2;
+  f64x4 acc[NTILE][4];
+#pragma unroll
+  for (int u = 0; u < NTILE; ++u)
+#pragma unroll
+    for (int q = 0; q < 4; ++q) acc[u][q] = f64x4{0, 0, 0, 0};
+  // plane z: cm, c0, cp hold the centres of z - 1, z, z + 1; cm is refilled with plane z + 2
+  auto step = [&](int z, double (&cm)[NQ], double (&c0)[NQ], double (&cp)[NQ]) {
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
+      double xm = row_shift<DPP_ROW_SHR1>(e[q], c0[q]);
+      double xp = row_shift<DPP_ROW_SHL1>(e[q], c0[q]);
+      xm = xl ? xm : 0.0;
+      xp = xr ? xp : 0.0;
+      const double w = center * c0[q] + off * (((xm + xp) + (ym[q] + yp[q])) + (cm[q] + cp[q]));
+      Xs[q >> 2][lk][cg + 16 * (q & 3)] = c0[q];
+      Ys[q >> 2][lk][cg + 16 * (q & 3)] = in ? w : 0.0;
+    }
+    __syncthreads();
+    load_c(cm, z + 2);
+    load_n(z + 1);
+#pragma unroll
+    for (int kk = 0; kk < SP; kk += 4) {
+      const int kr = kk + li;
+      int u = 0;
+#pragma unroll
+      for (int I = 0; I < NBT; ++I) {
+        const double a = Xs[I][kr][wave * 16 + lj];
+#pragma unroll
+        for (int J = I; J < NBT; ++J, ++u)
+#pragma unroll
+          for (int q = 0; q < 4; ++q) acc[u][q] = mfma_f64(a, Ys[J][kr][q * 16 + lj], acc[u][q]);
+      }
+    }
+    __syncthreads();
+  };
+  load_c(ca, z0 - 1);
+  load_c(cbv, z0);
+  load_c(cc, z0 + 1);
+  load_n(z0);
+  for (int z = z0; z < z1; z += 3) {
+    step(z, ca, cbv, cc);
+    if (z + 1 < z1) step(z + 1, cbv, cc, ca);
+    if (z + 2 < z1) step(z + 2, cc, ca, cbv);
+  }
+  double* P = partial + (int64_t)blockIdx.x * n * n;
+  int u = 0;
+#pragma unroll
+  for (int I = 0; I < NBT; ++I)
+#pragma unroll
+    for (int J = I; J < NBT; ++J, ++u)
+#pragma unroll
+      for (int q = 0; q < 4; ++q)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int i = I * TB + wave * 16 + 4 * r + li;
+          const int j = J * TB + q * 16 + lj;
+          if (i < n && j < n) P[(int64_t)j * n + i] = acc[u][q][r];
+        }
+}
+
+struct StencilPlan {
+  int zparts, zlen, chunks;
+};
+// Regions of SP plane points; the planes are cut into parts when there are fewer than 512 regions.
+StencilPlan stencil_plan(int64_t sxy, int64_t nz) {
+  StencilPlan p;
+  const int64_t nreg = (sxy + SP - 1) / SP;
+  int64_t zp = (512 + nreg - 1) / nreg;
+  if (zp > nz) zp = nz;
+  if (zp < 1) zp = 1;
+  p.zlen = (int)((nz + zp - 1) / zp);
+  p.zparts = (int)((nz + p.zlen - 1) / p.zlen);
+  p.chunks = (int)(nreg * p.zparts);
+  return p;
+}
+
 }  // namespace
 
 size_t gram_partial_bytes(int64_t m, int64_t n) {
@@ -548,6 +706,36 @@ hipError_t launch_gram_split(const double* X, int64_t ldx, const double* Y, int6
     gram_split_kernel<2><<<dim3(p.tiles, p.chunks), NT, 0, s>>>(X, ldx, Y, ldy, (int)m, (int)n, p.nb, p.kc, partial);
   else
     gram_split_kernel<3><<<dim3(p.tiles, p.chunks), NT, 0, s>>>(X, ldx, Y, ldy, (int)m, (int)n, p.nb, p.kc, partial);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  return reduce(partial, n, p.chunks, G, s);
+}
+
+bool stencil_gram_fits(const oqr_op* op, int64_t ldz, int64_t n) {
+  if (op->kind != OQR_OP_STENCIL7 || n < 1 || n > 2 * TB) return false;
+  const int64_t sxy = (int64_t)op->nx * op->ny, m = sxy * op->nz;
+  if (m < 1) return false;
+  // 32-bit byte offsets within one 64-column block, 32-bit row indices
+  return ((int64_t)(TB - 1) * ldz + m) * 8 < 0x7fffffffll && m < 0x7fffffffll;
+}
+
+size_t stencil_gram_partial_bytes(const oqr_op* op, int64_t n) {
+  if (op->kind != OQR_OP_STENCIL7 || n < 1 || n > 2 * TB) return 0;
+  const int64_t sxy = (int64_t)op->nx * op->ny;
+  if (sxy < 1 || op->nz < 1) return 0;
+  return (size_t)stencil_plan(sxy, op->nz).chunks * n * n * sizeof(double);
+}
+
+hipError_t launch_stencil_gram(const oqr_op* op, const double* Z, int64_t ldz, int64_t n, double* partial, double* G,
+                               hipStream_t s) {
+  if (!stencil_gram_fits(op, ldz, n)) return hipErrorInvalidValue;
+  const StencilPlan p = stencil_plan((int64_t)op->nx * op->ny, op->nz);
+  if (n <= TB)
+    stencil_gram_kernel<1><<<p.chunks, NT, 0, s>>>(Z, ldz, (int)n, op->nx, op->ny, op->nz, op->center, op->off,
+                                                   p.zparts, p.zlen, partial);
+  else
+    stencil_gram_kernel<2><<<p.chunks, NT, 0, s>>>(Z, ldz, (int)n, op->nx, op->ny, op->nz, op->center, op->off,
+                                                   p.zparts, p.zlen, partial);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   return reduce(partial, n, p.chunks, G, s);
