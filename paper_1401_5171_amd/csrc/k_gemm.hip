@@ -17,9 +17,10 @@ constexpr int NT = 256;      // threads per workgroup (4 waves)
 // FP64: v_mfma_f64_16x16x4_f64.  Wave w owns all 64 rows and columns [w*16*CB, (w+1)*16*CB).
 // ---------------------------------------------------------------------------------------------
 constexpr int BK64 = 16;
-// Odd row strides (in doubles): a 16-lane group reading or writing 16 rows of one column, or 16
-// columns of one row, touches 16 distinct bank pairs.
-constexpr int APAD = 1, BPAD = 1;
+// LDS row strides (doubles) against bank conflicts.  As (80 = 16 mod 32): the A-fragment reads (2 K rows x
+// 16 rows per half-wave) cover disjoint bank halves; its stores are contiguous.  Bs (270 = 2 x odd): the
+// stores (16 K rows x 2 columns per half-wave) hit distinct banks and the B-fragment reads overlap in 2 lanes.
+constexpr int APAD = 16, BPAD = 14;
 
 // K ranges of the products.  GEMM_FULL: row tile blockIdx.x, K slice blockIdx.z of width kchunk.
 // GEMM_UPPER (A symmetric, strictly upper block triangle): row tile t needs K in [BM (t + 1), m);
