@@ -203,7 +203,7 @@ hipError_t gram_symm(const double* Z, int64_t ldz, int64_t m, int64_t n, const P
 }
 
 // One CHOLQR pass (Algorithm 1) on the device: W = A Z; G = Z^T W; R = chol(G [+ s I]); Q = Z R^{-1}.
-// For the 7-point operator in FP64 the first two steps run as one kernel that never stores W.
+// For the 7-point operator with n <= 128 the first two steps run as one kernel that never stores W.
 // Dense A is symmetric: the product reads only its upper block triangle and G is assembled from the
 // two halves (gram_symm).
 int cholqr_pass(const oqr_op* A, const double* Z, int64_t ldz, int64_t m, int64_t n, double* Q, int64_t ldq,
@@ -223,8 +223,11 @@ int cholqr_pass(const oqr_op* A, const double* Z, int64_t ldz, int64_t m, int64_
                  launch_symm_finish(a, A->lda, Z, ldz, w.W, w.Ws, m, m, n, w.kpart, symm_layers(m, n, w.kpart), s));
     }
     OQR_TRACED(K_GRAM, s, gram_symm(Z, ldz, m, n, w, s));
-  } else if (prec == OQR_P_FP64 && stencil_gram_fits(A, ldz, n)) {
-    OQR_TRACED(K_GRAM, s, launch_stencil_gram(A, Z, ldz, n, w.partial, w.G, s));
+  } else if (stencil_gram_fits(A, ldz, n)) {
+    if (prec == OQR_P_FP64)
+      OQR_TRACED(K_GRAM, s, launch_stencil_gram(A, Z, ldz, n, w.partial, w.G, s));
+    else
+      OQR_TRACED(K_GRAM, s, launch_stencil_gram_split(A, Z, ldz, n, slices_of(prec), w.partial, w.G, s));
   } else {
     OQR_TRACED(K_STENCIL, s, launch_sparse_apply(A, Z, ldz, w.W, w.ldw, n, s));
     if (prec == OQR_P_FP64)
@@ -395,7 +398,7 @@ int oqr_cholqr2(const oqr_op* A, const double* Z, int64_t ldz, int64_t m, int64_
   pass_ws(A, m, n, o, true, &w, ws);
   // pass 1: Z -> (Q1, R1);  pass 2: Q1 -> (Q, R2);  R = R2 R1.  Q1 is kept in Q (pass 2 in place), or, for
   // the stencil with the fused Gram, in the padded workspace W, whose A Q1 the second pass never stores.
-  const bool q1_in_w = A->kind == OQR_OP_STENCIL7 && o.pass2 == OQR_P_FP64 && stencil_gram_fits(A, w.ldw, n);
+  const bool q1_in_w = A->kind == OQR_OP_STENCIL7 && stencil_gram_fits(A, w.ldw, n);
   double* q1 = q1_in_w ? w.W : Q;
   const int64_t ldq1 = q1_in_w ? w.ldw : ldq;
   if ((rc = cholqr_pass(A, Z, ldz, m, n, q1, ldq1, w.R1, n, o.pass1, o, w, w.shifts, info_dev, s))) return rc;

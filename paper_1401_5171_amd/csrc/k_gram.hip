@@ -5,6 +5,8 @@
 // FP64, and a second kernel sums the partials in chunk order, so the result is
 // deterministic (no atomics).  Only tiles with I <= J are computed; the
 // reduction writes both triangles of G from the upper one.
+#include <type_traits>
+
 #include "common.hpp"
 
 namespace oqr {
@@ -618,6 +620,186 @@ __global__ __launch_bounds__(NT, 2) void stencil_gram_kernel(const double* __res
         }
 }
 
+// ---- split-bfloat16 variant of the fused stencil Gram --------------------------------------------
+// Same march, DPP neighbours and register rotation as stencil_gram_kernel.  The thread that forms an
+// element of X = Z and Y = A Z (in FP64) rounds both to FP32 and splits them into S bfloat16 slices in
+// LDS (as the split operator product does), so every element is split once; the products with slice indices p + q < S run on
+// v_mfma_f32_16x16x16_bf16 (K = 16 = one plane), accumulated in FP32 over KT rows and then folded into
+// FP64, as in the unfused split Gram.  512 threads (two waves per SIMD): a thread holds columns
+// cg + 32 j of its point; wave w owns the 16-row block w & 3 of every output tile and half w >> 2 of
+// the (tile, column block) pairs.
+constexpr int NT2 = 512;
+constexpr int SKP = 4;     // LDS padding (bf16 elements) after a column's 16 k values
+
+typedef short s16x4 __attribute__((ext_vector_type(4)));
+
+// upper 64 x 64 tiles in order (0,0) (0,1) (1,1) for two column blocks, (0,0) for one
+__host__ __device__ constexpr int tile_row(int u, int nbt) { return nbt == 1 ? 0 : (u == 2 ? 1 : 0); }
+__host__ __device__ constexpr int tile_col(int u, int nbt) { return nbt == 1 ? 0 : (u == 0 ? 0 : 1); }
+
+template <int S, int NBT>
+__global__ __launch_bounds__(NT2, 1) void stencil_gram_split_kernel(const double* __restrict__ Z, int64_t ldz, int n,
+                                                                   int nx, int ny, int nz, double center,
+                                                                   double off, int zparts, int zlen,
+                                                                   double* __restrict__ partial) {
+  constexpr int NQ = 2 * NBT;                 // columns per thread: cg + 32 j
+  constexpr int NTILE = NBT * (NBT + 1) / 2;
+  constexpr int NP = 2 * NTILE;               // (tile, column block) pairs per wave
+  __shared__ __attribute__((aligned(16))) unsigned short Xs[NBT][S][TB][SP + SKP];
+  __shared__ __attribute__((aligned(16))) unsigned short Ys[NBT][S][TB][SP + SKP];
+  const int G = gridDim.x;
+  const int L = (G & 7) ? (int)blockIdx.x : (int)(blockIdx.x & 7) * (G >> 3) + (int)(blockIdx.x >> 3);
+  const int reg = L / zparts, zpart = L % zparts;
+  const int z0 = zpart * zlen, z1 = min(nz, z0 + zlen);
+  const int sxy = nx * ny;
+  const int m = sxy * nz;
+  const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+  const int lk = lane & 15, cg = t >> 4;      // point p0 + lk; columns cg + 32 j
+  const int kq = lane >> 4, lj = lane & 15;   // MFMA fragment: k = 4 kq .. 4 kq + 3, row / column lj
+  const int rb = wave & 3, hf = wave >> 2;
+  // one buffer resource per 32-column group; column cg of group g is column 32 g + cg of Z
+  bufrsrc zb[NQ];
+#pragma unroll
+  for (int g = 0; g < NQ; ++g) {
+    const int c0 = 32 * g, cols = min(32, n - c0);
+    zb[g] = make_buf(Z + (int64_t)c0 * ldz, cols > 0 ? ((int64_t)(cols - 1) * ldz + m) * 8 : 0);
+  }
+  const int p = reg * SP + lk;
+  const bool in = p < sxy;
+  const int x = p % nx, y = p / nx;
+  const bool xl = in && x > 0, xr = in && x < nx - 1, yl = in && y > 0, yr = in && y < ny - 1;
+  const int de = (lk == 0 && xl) ? -1 : (lk == SP - 1 && xr) ? 1 : 0;
+  const uint32_t o_c = (uint32_t)(((int64_t)cg * ldz + p) * 8);
+  const uint32_t m_c = in ? 0u : kOOB, m_e = de ? 0u : kOOB, m_ym = yl ? 0u : kOOB, m_yp = yr ? 0u : kOOB;
+  const uint32_t o_e = o_c + (uint32_t)(de * 8), o_ym = o_c - (uint32_t)nx * 8u, o_yp = o_c + (uint32_t)nx * 8u;
+  auto plane = [&](int zz) -> uint32_t { return (uint32_t)zz * (uint32_t)sxy * 8u; };
+  double ca[NQ], cbv[NQ], cc[NQ], e[NQ], ym[NQ], yp[NQ];
+  auto load_c = [&](double (&v)[NQ], int zz) {
+    const uint32_t mz = (zz >= 0 && zz < nz) ? 0u : kOOB;
+    const uint32_t oc = (o_c + plane(zz)) | (m_c | mz);
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) v[q] = buf_f64(zb[q], oc);
+  };
+  auto load_n = [&](int zz) {
+    const uint32_t mz = zz < z1 ? 0u : kOOB, pz = plane(zz);
+    const uint32_t oe = (o_e + pz) | (m_e | mz), om = (o_ym + pz) | (m_ym | mz), op = (o_yp + pz) | (m_yp | mz);
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
+      e[q] = buf_f64(zb[q], oe);
+      ym[q] = buf_f64(zb[q], om);
+      yp[q] = buf_f64(zb[q], op);
+    }
+  };
+  f32x4 acc[NP];
+  double dacc[NP][4];
+#pragma unroll
+  for (int v = 0; v < NP; ++v) {
+    acc[v] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int r = 0; r < 4; ++r) dacc[v][r] = 0.0;
+  }
+  // the MFMAs of half H of the pairs: pair g = H NP + v is tile g / 4, column block g % 4
+  auto mfma_half = [&](auto hc) {
+    constexpr int H = decltype(hc)::value;
+    s16x4 a[NBT][S];
+#pragma unroll
+    for (int I = 0; I < NBT; ++I)
+#pragma unroll
+      for (int s2 = 0; s2 < S; ++s2) a[I][s2] = *reinterpret_cast<const s16x4*>(&Xs[I][s2][rb * 16 + lj][4 * kq]);
+#pragma unroll
+    for (int v = 0; v < NP; ++v) {
+      const int g = H * NP + v, u = g >> 2, qb = g & 3;
+      const int I = tile_row(u, NBT), J = tile_col(u, NBT);
+      s16x4 b[S];
+#pragma unroll
+      for (int s2 = 0; s2 < S; ++s2) b[s2] = *reinterpret_cast<const s16x4*>(&Ys[J][s2][qb * 16 + lj][4 * kq]);
+#pragma unroll
+      for (int p1 = S - 1; p1 >= 0; --p1)
+#pragma unroll
+        for (int q2 = S - 1 - p1; q2 >= 0; --q2)
+          acc[v] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a[I][p1], b[q2], acc[v], 0, 0, 0);
+    }
+  };
+  int since = 0;
+  // FP64 -> FP32 -> S bfloat16 slices, two elements (columns cg and cg + 32 of block b) per
+  // v_cvt_pk_bf16_f32 (nearest even); the FP32 remainders are exact
+  auto store_split = [&](unsigned short (&T)[NBT][S][TB][SP + SKP], int b, double v0, double v1) {
+    f32x2 r = f32x2{(float)v0, (float)v1};
+#pragma unroll
+    for (int s2 = 0; s2 < S; ++s2) {
+      const unsigned w = __builtin_bit_cast(unsigned, __builtin_convertvector(r, bf16x2));
+      T[b][s2][cg][lk] = (unsigned short)(w & 0xffffu);
+      T[b][s2][cg + 32][lk] = (unsigned short)(w >> 16);
+      if (s2 + 1 < S) {
+        r.x -= __uint_as_float(w << 16);
+        r.y -= __uint_as_float(w & 0xffff0000u);
+      }
+    }
+  };
+  auto step = [&](int z, double (&cm)[NQ], double (&c0)[NQ], double (&cp)[NQ]) {
+    double w[NQ];
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
+      double xm = row_shift<DPP_ROW_SHR1>(e[q], c0[q]);
+      double xp = row_shift<DPP_ROW_SHL1>(e[q], c0[q]);
+      xm = xl ? xm : 0.0;
+      xp = xr ? xp : 0.0;
+      w[q] = in ? center * c0[q] + off * (((xm + xp) + (ym[q] + yp[q])) + (cm[q] + cp[q])) : 0.0;
+    }
+#pragma unroll
+    for (int b = 0; b < NBT; ++b) {
+      store_split(Xs, b, c0[2 * b], c0[2 * b + 1]);
+      store_split(Ys, b, w[2 * b], w[2 * b + 1]);
+    }
+    __syncthreads();
+    load_c(cm, z + 2);
+    load_n(z + 1);
+    if (hf == 0)
+      mfma_half(std::integral_constant<int, 0>{});
+    else
+      mfma_half(std::integral_constant<int, 1>{});
+    since += SP;
+    if (since == KT || z == z1 - 1) {
+#pragma unroll
+      for (int v = 0; v < NP; ++v) {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) dacc[v][r] += (double)acc[v][r];
+        acc[v] = f32x4{0.f, 0.f, 0.f, 0.f};
+      }
+      since = 0;
+    }
+    __syncthreads();
+  };
+  load_c(ca, z0 - 1);
+  load_c(cbv, z0);
+  load_c(cc, z0 + 1);
+  load_n(z0);
+  for (int z = z0; z < z1; z += 3) {
+    step(z, ca, cbv, cc);
+    if (z + 1 < z1) step(z + 1, cbv, cc, ca);
+    if (z + 2 < z1) step(z + 2, cc, ca, cbv);
+  }
+  double* P = partial + (int64_t)blockIdx.x * n * n;
+  auto write_half = [&](auto hc) {
+    constexpr int H = decltype(hc)::value;
+#pragma unroll
+    for (int v = 0; v < NP; ++v) {
+      const int g = H * NP + v, u = g >> 2, qb = g & 3;
+      const int I = tile_row(u, NBT), J = tile_col(u, NBT);
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int i = I * TB + rb * 16 + 4 * kq + r;
+        const int j = J * TB + qb * 16 + lj;
+        if (i < n && j < n) P[(int64_t)j * n + i] = dacc[v][r];
+      }
+    }
+  };
+  if (hf == 0)
+    write_half(std::integral_constant<int, 0>{});
+  else
+    write_half(std::integral_constant<int, 1>{});
+}
+
 struct StencilPlan {
   int zparts, zlen, chunks;
 };
@@ -724,6 +906,24 @@ size_t stencil_gram_partial_bytes(const oqr_op* op, int64_t n) {
   const int64_t sxy = (int64_t)op->nx * op->ny;
   if (sxy < 1 || op->nz < 1) return 0;
   return (size_t)stencil_plan(sxy, op->nz).chunks * n * n * sizeof(double);
+}
+
+hipError_t launch_stencil_gram_split(const oqr_op* op, const double* Z, int64_t ldz, int64_t n, int slices,
+                                     double* partial, double* G, hipStream_t s) {
+  if (!stencil_gram_fits(op, ldz, n) || (slices != 2 && slices != 3)) return hipErrorInvalidValue;
+  const StencilPlan p = stencil_plan((int64_t)op->nx * op->ny, op->nz);
+#define OQR_SGS(S_, NBT_)                                                                                    \
+  stencil_gram_split_kernel<S_, NBT_><<<p.chunks, NT2, 0, s>>>(Z, ldz, (int)n, op->nx, op->ny, op->nz, op->center, \
+                                                              op->off, p.zparts, p.zlen, partial)
+  if (slices == 3) {
+    if (n <= TB) OQR_SGS(3, 1); else OQR_SGS(3, 2);
+  } else {
+    if (n <= TB) OQR_SGS(2, 1); else OQR_SGS(2, 2);
+  }
+#undef OQR_SGS
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  return reduce(partial, n, p.chunks, G, s);
 }
 
 hipError_t launch_stencil_gram(const oqr_op* op, const double* Z, int64_t ldz, int64_t n, double* partial, double* G,

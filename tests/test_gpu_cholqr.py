@@ -295,3 +295,22 @@ def test_stencil_mixed_gram_then_fp64(pass1):
     assert metrics.residual_f(z, q, r) <= 1e-12
     assert metrics.orth_loss(st, q) <= 1e-12
     assert metrics.r_forward_error(r, r0) <= 10 * n * U * np.linalg.cond(r0)
+
+
+@pytest.mark.parametrize("pass1,n,grid", [("bf16x3", 64, (33, 17, 20)), ("bf16x2", 100, (20, 24, 9))])
+def test_stencil_fused_split_pass_matches_emulated_error_level(pass1, n, grid):
+    """One split-bfloat16 CholQR pass on the stencil (A Z formed inside the split Gram kernel): the GPU's
+    loss of orthogonality sits within 10x of the CPU emulation of the same arithmetic (exact FP64 stencil,
+    split operands, FP32 sums over 256-row tiles). Level, not bits: the GPU's K tiles are plane regions,
+    the emulation's consecutive rows. Ragged regions (nx not a multiple of 16), n = 64 and 100."""
+    from oracle import mixed
+    st = W.laplacian7(*grid)
+    z = W.tall_skinny(W.rng_for(3, 4, *grid), st.m, n, 1e3)
+    qe, re, info, s = mixed.cholqr_pass(st, z, pass1, shift_c=1.0)
+    assert info == 0
+    banner(f"stencil fused split pass {pass1} grid={grid} n={n}")
+    q, r = (to_host(x) for x in oqr.cholqr(oqr.Stencil7(*grid, st.center, st.off), to_dev_colmajor(z),
+                                            prec=pass1, shift_c=1.0))
+    le, lg = metrics.orth_loss(st, qe), metrics.orth_loss(st, q)
+    assert le / 10 <= lg <= 10 * le, (le, lg)
+    assert metrics.residual_f(z, q, r) <= 1e-12
