@@ -238,7 +238,7 @@ struct FullPlan {
 FullPlan full_plan(int64_t m, int kstep) {
   FullPlan p;
   int64_t kc = (m + NCH_FULL - 1) / NCH_FULL;
-  if (kc < 256) kc = 256;
+  if (kc < 64) kc = 64;
   kc = (kc + kstep - 1) / kstep * kstep;
   p.kc = (int)kc;
   p.chunks = ceil_div(m, kc);
