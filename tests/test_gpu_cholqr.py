@@ -314,3 +314,26 @@ def test_stencil_fused_split_pass_matches_emulated_error_level(pass1, n, grid):
     le, lg = metrics.orth_loss(st, qe), metrics.orth_loss(st, q)
     assert le / 10 <= lg <= 10 * le, (le, lg)
     assert metrics.residual_f(z, q, r) <= 1e-12
+
+
+@pytest.mark.parametrize("grid,n,pass1,pad", [
+    ((1, 1, 1), 1, "fp64", 0),        # a single grid point
+    ((5, 3, 1), 3, "fp64", 0),        # one plane; 16-point regions straddle lines of 5
+    ((1, 7, 6), 5, "bf16x3", 0),      # lines of one point: no x-neighbours
+    ((9, 1, 17), 65, "fp64", 5),      # ny = 1; one column in the second 64-column block; ld = m + 5
+    ((6, 5, 40), 128, "bf16x2", 3),   # n = 128, ld = m + 3
+])
+def test_stencil_fused_gram_edge_shapes(grid, n, pass1, pad):
+    """The fused stencil Gram (FP64 and split) on degenerate grids and a padded leading dimension of Z:
+    CholQR2 against the oracle's whitened Householder QR."""
+    import torch
+    st = W.laplacian7(*grid)
+    z = W.tall_skinny(W.rng_for(3, 5, *grid), st.m, n, 1e2)
+    q0, r0 = reference.stencil_eqr(st, z)
+    banner(f"stencil fused edge grid={grid} n={n} pass1={pass1} pad={pad}")
+    zd = torch.empty(n, st.m + pad, dtype=torch.float64, device="cuda").t()[: st.m]
+    zd.copy_(torch.from_numpy(np.asarray(z, dtype=np.float64)))
+    q, r = (to_host(x) for x in oqr.cholqr2(oqr.Stencil7(*grid, st.center, st.off), zd, pass1=pass1, pass2="fp64"))
+    assert metrics.residual_f(z, q, r) <= 1e-12
+    assert metrics.orth_loss(st, q) <= 1e-12
+    assert metrics.r_forward_error(r, r0) <= 10 * max(n, 2) * U * np.linalg.cond(r0)
