@@ -115,6 +115,29 @@ def make_inputs(wl, torch):
     return A, Z, z, m, n, desc, 2.0 * m * n * n, "gram", 1.0 * m * n * n
 
 
+def schedule_roofline(kind, m, n, pass_precs, ms):
+    """Roofline of a whole CholQR2 schedule: T_roof = sum over passes of max(B / HBM peak, sum over steps
+    of F_step / peak of the step's precision), frac = T_roof / measured.  Per pass, algorithmic counts
+    independent of how the library schedules them: a1 2 m^2 n (dense) / 13 m n (stencil) / 5 m n
+    (tridiagonal), a2 m n^2 (upper triangle), a3 n^3 / 3, a4 m n^2; a1 and a2 at bf16 peak in a split
+    pass, FP64 otherwise, a3 and a4 always FP64; B = unique A bytes 8 m (m + 1) / 2 (dense) or 16 m
+    (tridiagonal) + 3 x 8 m n (Z read, Z read again by the substitution, Q written).  The dense a1 counts
+    the full product: the library evaluates only the upper block triangle (half those flops), so a
+    schedule can run faster than this roofline."""
+    a1 = {"dense": 2.0 * m * m * n, "stencil": 13.0 * m * n, "tridiag": 5.0 * m * n}[kind]
+    a_bytes = {"dense": 8.0 * m * (m + 1) / 2, "stencil": 0.0, "tridiag": 16.0 * m}[kind]
+    t = 0.0
+    for prec in pass_precs:
+        peak12 = PEAK["bf16"] if prec != "fp64" else PEAK["fp64"]
+        if kind != "dense":
+            t_mx = a1 / PEAK["fp64"] + m * n * n / peak12         # the matrix-free apply is FP64 vector work
+        else:
+            t_mx = (a1 + m * n * n) / peak12
+        t_mx += (n ** 3 / 3 + m * n * n) / PEAK["fp64"]
+        t += max((a_bytes + 3 * 8.0 * m * n) / PEAK["hbm"], t_mx)
+    return {"t_roof_ms": round(t * 1e3, 4), "measured_ms": round(ms, 4), "frac": round(t * 1e3 / ms, 4)}
+
+
 def time_steps(plan, Z, Q, R, steps, torch, kernel):
     import paper_1401_5171_amd as oqr
     torch.cuda.synchronize()
@@ -441,6 +464,13 @@ def main():
         "speedup_vs_fp64_cholqr2": round(res["fp64"]["ms_per_step"] / mx["ms_per_step"], 3),
         "breakdown_ms": {"mixed": mx["breakdown_ms"], "fp64": res["fp64"]["breakdown_ms"]},
         "roofline": roof,
+    }
+    kind = "dense" if dense else ("tridiag" if args.workload == "tridiag" else "stencil")
+    line["schedule_roofline"] = {
+        "mixed": schedule_roofline(kind, m, n, (pass1, "fp64"), mx["ms_per_step"]),
+        "fp64": schedule_roofline(kind, m, n, ("fp64", "fp64"), res["fp64"]["ms_per_step"]),
+        "definition": "sum over passes of max(unique algorithmic bytes / 8 TB/s, sum of step flops / peak of "
+                      "the step's precision); a1 counted as the full 2m^2n product for dense A",
     }
     if args.workload == "tridiag":
         line["variants"] = time_variants(A, Z, m, n, flops, torch)
