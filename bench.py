@@ -68,7 +68,8 @@ def parse():
     p.add_argument("--batch-count", type=int, default=4096)
     p.add_argument("--batch-dtype", default="f64", choices=["f64", "f32"], help="storage type of the batch")
     p.add_argument("--tile", type=int, default=-1, help="batched tile id (-1: time every id, keep the best)")
-    p.add_argument("--pass1", default=None, help="precision of pass 1 of the mixed schedule")
+    p.add_argument("--pass1", default=None, choices=["fp64", "bf16x2", "bf16x3"],
+                   help="precision of pass 1 of the mixed schedule (default bf16x2: hi/lo split)")
     p.add_argument("--cpu-sample", type=int, default=8192, help="m' of the CPU oracle sample (0 = skip)")
     return p.parse_args()
 
@@ -402,7 +403,9 @@ def main():
         return run_copycal(torch)
     A, Z, z_host, m, n, desc, flops, dom_kernel, dom_flops = make_inputs(args.workload, torch)
     dense = not hasattr(A, "nx") and not hasattr(A, "host")
-    pass1 = args.pass1 or ("bf16x3")
+    # pass 1 of the mixed schedule: hi/lo bfloat16 operands (two slices, products hi*hi + hi*lo + lo*hi),
+    # FP32 accumulation, as the workloads specify; pass 2 FP64
+    pass1 = args.pass1 or "bf16x2"
     Q = torch.empty(n, m, dtype=torch.float64, device="cuda").t()
     R = torch.empty(n, n, dtype=torch.float64, device="cuda").t()
     mixed = oqr.Plan("cholqr2", A, n, pass1=pass1, pass2="fp64")
