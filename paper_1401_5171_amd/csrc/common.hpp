@@ -166,9 +166,8 @@ hipError_t launch_stencil_gram(const oqr_op* op, const double* Z, int64_t ldz, i
 // The same in split bfloat16 (slices 2 or 3): products p + q < slices on MFMA, FP32 over 256 rows, FP64 beyond.
 hipError_t launch_stencil_gram_split(const oqr_op* op, const double* Z, int64_t ldz, int64_t n, int slices,
                                      double* partial, double* G, hipStream_t s);
-// accumulate: G += X^T Y instead of G = X^T Y.
 hipError_t launch_gram_f64(const double* X, int64_t ldx, const double* Y, int64_t ldy, int64_t m, int64_t n,
-                           double* partial, double* G, hipStream_t s, bool accumulate = false);
+                           double* partial, double* G, hipStream_t s);
 hipError_t launch_gram_split(const double* X, int64_t ldx, const double* Y, int64_t ldy, int64_t m, int64_t n,
                              int slices, double* partial, double* G, hipStream_t s);
 

@@ -458,8 +458,7 @@ __global__ __launch_bounds__(NT, 2) void gram_full_split_kernel(const double* __
 // G(i, j) = G(j, i) = sum_c partial[c](i, j) for i <= j.  Eight interleaved partial sums (chunk c goes
 // to sum c mod 8) keep eight loads in flight; they are combined in a fixed order, so the result does
 // not depend on timing.
-__global__ void gram_reduce_kernel(const double* __restrict__ partial, int n, int chunks, double* __restrict__ G,
-                                   int accumulate) {
+__global__ void gram_reduce_kernel(const double* __restrict__ partial, int n, int chunks, double* __restrict__ G) {
   const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (idx >= (int64_t)n * n) return;
   const int j = (int)(idx / n), i = (int)(idx % n);
@@ -473,7 +472,6 @@ __global__ void gram_reduce_kernel(const double* __restrict__ partial, int n, in
   }
   for (int u = 0; c < chunks; ++c, ++u) s[u] += partial[(int64_t)c * nn + idx];
   double t = ((s[0] + s[1]) + (s[2] + s[3])) + ((s[4] + s[5]) + (s[6] + s[7]));
-  if (accumulate) t += G[(int64_t)j * n + i];
   G[(int64_t)j * n + i] = t;
   G[(int64_t)i * n + j] = t;
 }
@@ -829,16 +827,15 @@ size_t gram_partial_bytes(int64_t m, int64_t n) {
   return b;
 }
 
-static hipError_t reduce(const double* partial, int64_t n, int chunks, double* G, hipStream_t s,
-                         bool accumulate = false) {
+static hipError_t reduce(const double* partial, int64_t n, int chunks, double* G, hipStream_t s) {
   const int64_t total = n * n;
-  gram_reduce_kernel<<<(unsigned)((total + 255) / 256), 256, 0, s>>>(partial, (int)n, chunks, G, accumulate);
+  gram_reduce_kernel<<<(unsigned)((total + 255) / 256), 256, 0, s>>>(partial, (int)n, chunks, G);
   return hipGetLastError();
 }
 
 template <bool SYM>
 static hipError_t gram_f64(const double* X, int64_t ldx, const double* Y, int64_t ldy, const double* X2, int64_t ldx2,
-                           int64_t m, int64_t n, double* partial, double* G, hipStream_t s, bool accumulate) {
+                           int64_t m, int64_t n, double* partial, double* G, hipStream_t s) {
   if (n <= 2 * TB) {
     const FullPlan f = full_plan(m, BK);
     if (n <= TB)
@@ -847,24 +844,24 @@ static hipError_t gram_f64(const double* X, int64_t ldx, const double* Y, int64_
       gram_full_f64_kernel<2, SYM><<<f.chunks, NT, 0, s>>>(X, ldx, Y, ldy, X2, ldx2, (int)m, (int)n, f.kc, partial);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    return reduce(partial, n, f.chunks, G, s, accumulate);
+    return reduce(partial, n, f.chunks, G, s);
   }
   GramPlan p = plan(m, n);
   gram_f64_kernel<SYM><<<dim3(p.tiles, p.chunks), NT, 0, s>>>(X, ldx, Y, ldy, X2, ldx2, (int)m, (int)n, p.nb, p.kc,
                                                               partial);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  return reduce(partial, n, p.chunks, G, s, accumulate);
+  return reduce(partial, n, p.chunks, G, s);
 }
 
 hipError_t launch_gram_f64(const double* X, int64_t ldx, const double* Y, int64_t ldy, int64_t m, int64_t n,
-                           double* partial, double* G, hipStream_t s, bool accumulate) {
-  return gram_f64<false>(X, ldx, Y, ldy, nullptr, 0, m, n, partial, G, s, accumulate);
+                           double* partial, double* G, hipStream_t s) {
+  return gram_f64<false>(X, ldx, Y, ldy, nullptr, 0, m, n, partial, G, s);
 }
 
 hipError_t launch_gram_symm(const double* Z, int64_t ldz, const double* Wsym, const double* Woff, int64_t ldw,
                             int64_t m, int64_t n, double* partial, double* G, hipStream_t s) {
-  return gram_f64<true>(Z, ldz, Wsym, ldw, Woff, ldw, m, n, partial, G, s, false);
+  return gram_f64<true>(Z, ldz, Wsym, ldw, Woff, ldw, m, n, partial, G, s);
 }
 
 hipError_t launch_gram_split(const double* X, int64_t ldx, const double* Y, int64_t ldy, int64_t m, int64_t n,
