@@ -264,19 +264,14 @@ def run_batch(args, torch, oqr):
         alg_bytes += 2 * 3 * esize * m_ * n_
     log(f"batch: {len(sizes)} instances, sum A = {np.sum(ms * ms) * esize / 1e9:.1f} GB, {flops:.3e} flops")
     bp = oqr.BatchPlan(As, Zs)
-    tiles = list(range(1, oqr.batch_tile_count() + 1)) if args.tile < 0 else [args.tile]
-    tile_ms = {}
-    for tl in tiles:
-        bp.run(tile=tl)
-        torch.cuda.synchronize()
-        with oqr.KernelTimer("batch") as kt:
-            for _ in range(3):
-                bp.run(tile=tl)
-            torch.cuda.synchronize()
-        tile_ms[tl] = kt.avg_ms
-        log(f"tile {tl}: {kt.avg_ms:.3f} ms per batched launch")
-    best = min(tile_ms, key=tile_ms.get)
-    bp.tile = best
+    if args.tile < 0:
+        tile_ms = bp.autotune(reps=3)           # the library's tile configurations, fastest kept
+    else:
+        bp.tile = args.tile
+        tile_ms = {}
+    for tl, ms_ in tile_ms.items():
+        log(f"tile {tl}: {ms_:.3f} ms per batched launch")
+    best = bp.tile
     for _ in range(args.warmup):
         bp.run()
     torch.cuda.synchronize()

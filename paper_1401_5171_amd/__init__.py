@@ -316,6 +316,23 @@ class BatchPlan:
         self.ws = torch.empty(max(int(nbytes), 256), dtype=torch.uint8, device=self.device)
         self.info = torch.zeros(self.batch, dtype=torch.int32, device=self.device)
 
+    def autotune(self, reps: int = 3) -> dict:
+        """Time every tile configuration of the library on this batch (`reps` launches each, HIP
+        events around the batched kernel), keep the fastest in `self.tile` and return
+        {tile id: average ms}.  Inputs are read only; outputs are overwritten."""
+        torch = _torch()
+        times = {}
+        for tl in range(1, batch_tile_count() + 1):
+            self.run(tile=tl)
+            torch.cuda.synchronize()
+            with KernelTimer("batch") as kt:
+                for _ in range(reps):
+                    self.run(tile=tl)
+                torch.cuda.synchronize()
+            times[tl] = kt.avg_ms
+        self.tile = min(times, key=times.get)
+        return times
+
     def run(self, stream=None, tile=None):
         torch = _torch()
         s = stream if stream is not None else torch.cuda.current_stream(self.device).cuda_stream

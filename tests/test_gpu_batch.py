@@ -161,3 +161,22 @@ def test_graph_capture_replays_match_eager():
         assert int(plan.info.sum().item()) == 0
         for k in range(len(insts)):
             assert torch.equal(plan.Qs[k], eager_q[k]) and torch.equal(plan.Rs[k], eager_r[k]), (rep, k)
+
+
+def test_autotune_picks_a_tile_and_keeps_the_bits():
+    """BatchPlan.autotune times every tile configuration on the caller's batch and keeps the fastest;
+    the outputs after tuning equal those of the default configuration bit for bit."""
+    insts = make_batch(24, seed=9)
+    As, Zs = upload(insts, np.float64)
+    ref = oqr.BatchPlan(As, Zs, tile=0)
+    ref.run()
+    plan = oqr.BatchPlan(As, Zs)
+    banner("batch autotune")
+    times = plan.autotune(reps=2)
+    assert sorted(times) == list(range(1, oqr.batch_tile_count() + 1))
+    assert all(t > 0 for t in times.values())
+    assert plan.tile == min(times, key=times.get)
+    plan.run()
+    torch.cuda.synchronize()
+    for k in range(len(insts)):
+        assert torch.equal(plan.Qs[k], ref.Qs[k]) and torch.equal(plan.Rs[k], ref.Rs[k])
