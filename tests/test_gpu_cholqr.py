@@ -337,3 +337,25 @@ def test_stencil_fused_gram_edge_shapes(grid, n, pass1, pad):
     assert metrics.residual_f(z, q, r) <= 1e-12
     assert metrics.orth_loss(st, q) <= 1e-12
     assert metrics.r_forward_error(r, r0) <= 10 * max(n, 2) * U * np.linalg.cond(r0)
+
+
+@pytest.mark.parametrize("n,ld,pass1", [(150, None, "fp64"), (150, None, "bf16x3"), (2, 4_400_000, "fp64"),
+                                        (2, 4_400_000, "bf16x2")])
+def test_stencil_unfused_fallbacks(n, ld, pass1):
+    """The stencil paths that do not fuse A Z into the Gram: n > 128 (apply + tile Gram), and a leading
+    dimension of Z too large for 32-bit offsets inside a 64-column block (apply + all-tiles Gram)."""
+    import torch
+    grid = (16, 12, 10)
+    st = W.laplacian7(*grid)
+    z = W.tall_skinny(W.rng_for(3, 6, n), st.m, n, 1e2)
+    q0, r0 = reference.stencil_eqr(st, z)
+    banner(f"stencil unfused n={n} ld={ld} pass1={pass1}")
+    if ld is None:
+        zd = to_dev_colmajor(z)
+    else:
+        zd = torch.empty(n, ld, dtype=torch.float64, device="cuda").t()[: st.m]
+        zd.copy_(torch.from_numpy(np.asarray(z, dtype=np.float64)))
+    q, r = (to_host(x) for x in oqr.cholqr2(oqr.Stencil7(*grid, st.center, st.off), zd, pass1=pass1, pass2="fp64"))
+    assert metrics.residual_f(z, q, r) <= 1e-12
+    assert metrics.orth_loss(st, q) <= 1e-12
+    assert metrics.r_forward_error(r, r0) <= 10 * n * U * np.linalg.cond(r0)
