@@ -504,13 +504,14 @@ constexpr int DPP_ROW_SHR1 = 0x111;   // lane i reads lane i - 1
 template <int NBT>
 __global__ __launch_bounds__(NT, 2) void stencil_gram_kernel(const double* __restrict__ Z, int64_t ldz, int n,
                                                             int nx, int ny, int nz, double center, double off,
-                                                            int zparts, int zlen, double* __restrict__ partial) {
+                                                            int nreg, int zparts, int zlen,
+                                                            double* __restrict__ partial) {
   constexpr int NQ = 4 * NBT;                 // columns per thread: cg + 16 q
   __shared__ double Xs[NBT][SP][TB + 1];
   __shared__ double Ys[NBT][SP][TB + 1];
   const int G = gridDim.x;
   const int L = (G & 7) ? (int)blockIdx.x : (int)(blockIdx.x & 7) * (G >> 3) + (int)(blockIdx.x >> 3);
-  const int reg = L / zparts, zpart = L % zparts;
+  const int reg0 = L / zparts, zpart = L % zparts, nrb = G / zparts;   // regions reg0, reg0 + nrb, ...
   const int z0 = zpart * zlen, z1 = min(nz, z0 + zlen);
   const int sxy = nx * ny;
   const int m = sxy * nz;
@@ -525,17 +526,29 @@ __global__ __launch_bounds__(NT, 2) void stencil_gram_kernel(const double* __res
     const int c0 = 16 * g, cols = min(16, n - c0);
     zb[g] = make_buf(Z + (int64_t)c0 * ldz, cols > 0 ? ((int64_t)(cols - 1) * ldz + m) * 8 : 0);
   }
-  const int p = reg * SP + lk;
-  const bool in = p < sxy;
-  const int x = p % nx, y = p / nx;
-  const bool xl = in && x > 0, xr = in && x < nx - 1, yl = in && y > 0, yr = in && y < ny - 1;
-  // the neighbour beyond the region: lane 0 loads p - 1, lane 15 loads p + 1
-  const int de = (lk == 0 && xl) ? -1 : (lk == SP - 1 && xr) ? 1 : 0;
-  // Invalid loads get bit 31 of the offset set (past every resource: zero).  Masks are ORed after the
-  // plane offset is added, rather than selected, so that the compiler keeps one unconditional load.
-  const uint32_t o_c = (uint32_t)(((int64_t)cg * ldz + p) * 8);
-  const uint32_t m_c = in ? 0u : kOOB, m_e = de ? 0u : kOOB, m_ym = yl ? 0u : kOOB, m_yp = yr ? 0u : kOOB;
-  const uint32_t o_e = o_c + (uint32_t)(de * 8), o_ym = o_c - (uint32_t)nx * 8u, o_yp = o_c + (uint32_t)nx * 8u;
+  // per region: the thread's point, its neighbour masks and offsets.  Invalid loads get bit 31 of the
+  // offset set (past every resource: zero); masks are ORed after the plane offset is added, rather
+  // than selected, so that the compiler keeps one unconditional load.  Lane 0 loads the point before
+  // the region, lane 15 the point after it (the x-neighbours beyond the DPP row).
+  bool in = false, xl = false, xr = false;
+  uint32_t o_c = 0, m_c = 0, m_e = 0, m_ym = 0, m_yp = 0, o_e = 0, o_ym = 0, o_yp = 0;
+  auto set_region = [&](int reg) {
+    const int p = reg * SP + lk;
+    in = p < sxy;
+    const int x = p % nx, y = p / nx;
+    xl = in && x > 0;
+    xr = in && x < nx - 1;
+    const bool yl = in && y > 0, yr = in && y < ny - 1;
+    const int de = (lk == 0 && xl) ? -1 : (lk == SP - 1 && xr) ? 1 : 0;
+    o_c = (uint32_t)(((int64_t)cg * ldz + p) * 8);
+    m_c = in ? 0u : kOOB;
+    m_e = de ? 0u : kOOB;
+    m_ym = yl ? 0u : kOOB;
+    m_yp = yr ? 0u : kOOB;
+    o_e = o_c + (uint32_t)(de * 8);
+    o_ym = o_c - (uint32_t)nx * 8u;
+    o_yp = o_c + (uint32_t)nx * 8u;
+  };
   auto plane = [&](int zz) -> uint32_t { return (uint32_t)zz * (uint32_t)sxy * 8u; };
   // the centres of planes z - 1, z, z + 1 rotate through three arrays (static roles after unrolling)
   double ca[NQ], cbv[NQ], cc[NQ], e[NQ], ym[NQ], yp[NQ];
@@ -593,14 +606,17 @@ __global__ __launch_bounds__(NT, 2) void stencil_gram_kernel(const double* __res
     }
     __syncthreads();
   };
-  load_c(ca, z0 - 1);
-  load_c(cbv, z0);
-  load_c(cc, z0 + 1);
-  load_n(z0);
-  for (int z = z0; z < z1; z += 3) {
-    step(z, ca, cbv, cc);
-    if (z + 1 < z1) step(z + 1, cbv, cc, ca);
-    if (z + 2 < z1) step(z + 2, cc, ca, cbv);
+  for (int reg = reg0; reg < nreg; reg += nrb) {
+    set_region(reg);
+    load_c(ca, z0 - 1);
+    load_c(cbv, z0);
+    load_c(cc, z0 + 1);
+    load_n(z0);
+    for (int z = z0; z < z1; z += 3) {
+      step(z, ca, cbv, cc);
+      if (z + 1 < z1) step(z + 1, cbv, cc, ca);
+      if (z + 2 < z1) step(z + 2, cc, ca, cbv);
+    }
   }
   double* P = partial + (int64_t)blockIdx.x * n * n;
   int u = 0;
@@ -638,7 +654,7 @@ __host__ __device__ constexpr int tile_col(int u, int nbt) { return nbt == 1 ? 0
 template <int S, int NBT>
 __global__ __launch_bounds__(NT2, 1) void stencil_gram_split_kernel(const double* __restrict__ Z, int64_t ldz, int n,
                                                                    int nx, int ny, int nz, double center,
-                                                                   double off, int zparts, int zlen,
+                                                                   double off, int nreg, int zparts, int zlen,
                                                                    double* __restrict__ partial) {
   constexpr int NQ = 2 * NBT;                 // columns per thread: cg + 32 j
   constexpr int NTILE = NBT * (NBT + 1) / 2;
@@ -647,7 +663,7 @@ __global__ __launch_bounds__(NT2, 1) void stencil_gram_split_kernel(const double
   __shared__ __attribute__((aligned(16))) unsigned short Ys[NBT][S][TB][SP + SKP];
   const int G = gridDim.x;
   const int L = (G & 7) ? (int)blockIdx.x : (int)(blockIdx.x & 7) * (G >> 3) + (int)(blockIdx.x >> 3);
-  const int reg = L / zparts, zpart = L % zparts;
+  const int reg0 = L / zparts, zpart = L % zparts, nrb = G / zparts;   // regions reg0, reg0 + nrb, ...
   const int z0 = zpart * zlen, z1 = min(nz, z0 + zlen);
   const int sxy = nx * ny;
   const int m = sxy * nz;
@@ -662,14 +678,25 @@ __global__ __launch_bounds__(NT2, 1) void stencil_gram_split_kernel(const double
     const int c0 = 32 * g, cols = min(32, n - c0);
     zb[g] = make_buf(Z + (int64_t)c0 * ldz, cols > 0 ? ((int64_t)(cols - 1) * ldz + m) * 8 : 0);
   }
-  const int p = reg * SP + lk;
-  const bool in = p < sxy;
-  const int x = p % nx, y = p / nx;
-  const bool xl = in && x > 0, xr = in && x < nx - 1, yl = in && y > 0, yr = in && y < ny - 1;
-  const int de = (lk == 0 && xl) ? -1 : (lk == SP - 1 && xr) ? 1 : 0;
-  const uint32_t o_c = (uint32_t)(((int64_t)cg * ldz + p) * 8);
-  const uint32_t m_c = in ? 0u : kOOB, m_e = de ? 0u : kOOB, m_ym = yl ? 0u : kOOB, m_yp = yr ? 0u : kOOB;
-  const uint32_t o_e = o_c + (uint32_t)(de * 8), o_ym = o_c - (uint32_t)nx * 8u, o_yp = o_c + (uint32_t)nx * 8u;
+  bool in = false, xl = false, xr = false;
+  uint32_t o_c = 0, m_c = 0, m_e = 0, m_ym = 0, m_yp = 0, o_e = 0, o_ym = 0, o_yp = 0;
+  auto set_region = [&](int reg) {       // as in stencil_gram_kernel
+    const int p = reg * SP + lk;
+    in = p < sxy;
+    const int x = p % nx, y = p / nx;
+    xl = in && x > 0;
+    xr = in && x < nx - 1;
+    const bool yl = in && y > 0, yr = in && y < ny - 1;
+    const int de = (lk == 0 && xl) ? -1 : (lk == SP - 1 && xr) ? 1 : 0;
+    o_c = (uint32_t)(((int64_t)cg * ldz + p) * 8);
+    m_c = in ? 0u : kOOB;
+    m_e = de ? 0u : kOOB;
+    m_ym = yl ? 0u : kOOB;
+    m_yp = yr ? 0u : kOOB;
+    o_e = o_c + (uint32_t)(de * 8);
+    o_ym = o_c - (uint32_t)nx * 8u;
+    o_yp = o_c + (uint32_t)nx * 8u;
+  };
   auto plane = [&](int zz) -> uint32_t { return (uint32_t)zz * (uint32_t)sxy * 8u; };
   double ca[NQ], cbv[NQ], cc[NQ], e[NQ], ym[NQ], yp[NQ];
   auto load_c = [&](double (&v)[NQ], int zz) {
@@ -768,14 +795,17 @@ __global__ __launch_bounds__(NT2, 1) void stencil_gram_split_kernel(const double
     }
     __syncthreads();
   };
-  load_c(ca, z0 - 1);
-  load_c(cbv, z0);
-  load_c(cc, z0 + 1);
-  load_n(z0);
-  for (int z = z0; z < z1; z += 3) {
-    step(z, ca, cbv, cc);
-    if (z + 1 < z1) step(z + 1, cbv, cc, ca);
-    if (z + 2 < z1) step(z + 2, cc, ca, cbv);
+  for (int reg = reg0; reg < nreg; reg += nrb) {
+    set_region(reg);
+    load_c(ca, z0 - 1);
+    load_c(cbv, z0);
+    load_c(cc, z0 + 1);
+    load_n(z0);
+    for (int z = z0; z < z1; z += 3) {
+      step(z, ca, cbv, cc);
+      if (z + 1 < z1) step(z + 1, cbv, cc, ca);
+      if (z + 2 < z1) step(z + 2, cc, ca, cbv);
+    }
   }
   double* P = partial + (int64_t)blockIdx.x * n * n;
   auto write_half = [&](auto hc) {
@@ -799,18 +829,21 @@ __global__ __launch_bounds__(NT2, 1) void stencil_gram_split_kernel(const double
 }
 
 struct StencilPlan {
-  int zparts, zlen, chunks;
+  int nreg, zparts, zlen, chunks;
 };
-// Regions of SP plane points; the planes are cut into parts when there are fewer than 512 regions.
+// Regions of SP plane points; the planes are cut into parts when there are fewer than 512 regions, and
+// beyond 2048 regions a workgroup marches several (so that the partial Gram tiles stay within 2048 x n^2).
+constexpr int64_t MAX_REGION_BASES = 2048;
 StencilPlan stencil_plan(int64_t sxy, int64_t nz) {
   StencilPlan p;
   const int64_t nreg = (sxy + SP - 1) / SP;
   int64_t zp = (512 + nreg - 1) / nreg;
   if (zp > nz) zp = nz;
   if (zp < 1) zp = 1;
+  p.nreg = (int)nreg;
   p.zlen = (int)((nz + zp - 1) / zp);
   p.zparts = (int)((nz + p.zlen - 1) / p.zlen);
-  p.chunks = (int)(nreg * p.zparts);
+  p.chunks = (int)((nreg < MAX_REGION_BASES ? nreg : MAX_REGION_BASES) * p.zparts);
   return p;
 }
 
@@ -911,7 +944,7 @@ hipError_t launch_stencil_gram_split(const oqr_op* op, const double* Z, int64_t 
   const StencilPlan p = stencil_plan((int64_t)op->nx * op->ny, op->nz);
 #define OQR_SGS(S_, NBT_)                                                                                    \
   stencil_gram_split_kernel<S_, NBT_><<<p.chunks, NT2, 0, s>>>(Z, ldz, (int)n, op->nx, op->ny, op->nz, op->center, \
-                                                              op->off, p.zparts, p.zlen, partial)
+                                                              op->off, p.nreg, p.zparts, p.zlen, partial)
   if (slices == 3) {
     if (n <= TB) OQR_SGS(3, 1); else OQR_SGS(3, 2);
   } else {
@@ -929,10 +962,10 @@ hipError_t launch_stencil_gram(const oqr_op* op, const double* Z, int64_t ldz, i
   const StencilPlan p = stencil_plan((int64_t)op->nx * op->ny, op->nz);
   if (n <= TB)
     stencil_gram_kernel<1><<<p.chunks, NT, 0, s>>>(Z, ldz, (int)n, op->nx, op->ny, op->nz, op->center, op->off,
-                                                   p.zparts, p.zlen, partial);
+                                                   p.nreg, p.zparts, p.zlen, partial);
   else
     stencil_gram_kernel<2><<<p.chunks, NT, 0, s>>>(Z, ldz, (int)n, op->nx, op->ny, op->nz, op->center, op->off,
-                                                   p.zparts, p.zlen, partial);
+                                                   p.nreg, p.zparts, p.zlen, partial);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   return reduce(partial, n, p.chunks, G, s);

@@ -322,6 +322,8 @@ def test_stencil_fused_split_pass_matches_emulated_error_level(pass1, n, grid):
     ((1, 7, 6), 5, "bf16x3", 0),      # lines of one point: no x-neighbours
     ((9, 1, 17), 65, "fp64", 5),      # ny = 1; one column in the second 64-column block; ld = m + 5
     ((6, 5, 40), 128, "bf16x2", 3),   # n = 128, ld = m + 3
+    ((256, 192, 2), 8, "fp64", 0),    # 3072 plane regions: workgroups march several regions
+    ((256, 192, 2), 70, "bf16x3", 0),
 ])
 def test_stencil_fused_gram_edge_shapes(grid, n, pass1, pad):
     """The fused stencil Gram (FP64 and split) on degenerate grids and a padded leading dimension of Z:
