@@ -291,6 +291,159 @@ __global__ __launch_bounds__(NT, 1) void trsm_persist_kernel(const double* Z, in
   }
 }
 
+// Persistent variant for 64 < n <= 128 with 128-row tiles: one workgroup (four waves, one per SIMD)
+// per CU; every thread carries two rows (t / 4 and t / 4 + 64) through the substitution, so two
+// independent chains share each pivot's R row, and every wave updates four 16-row blocks of one
+// 16-column half on MFMA (four accumulator chains, half the R fragments of a wave in registers).  The diagonal blocks of R are kept packed (strictly upper rows only) so that the
+// 128-row tile fits in LDS; the R fragments take the registers a next-tile prefetch would need, so a
+// tile's Z is loaded at its start.  Same operations in the same order per row as
+// trsm_persist_kernel<128>, so the results are identical.
+constexpr int NM2 = 128, BM2 = 128, LDQ2 = BM2 + 1, NBLK2 = NM2 / JB;
+constexpr int RZP = JB * (JB - 1) / 2;          // packed strictly upper entries of one diagonal block
+constexpr int RZO = 1;                            // entry 0 is padding: lane reads of columns <= c (unused)
+                                                  // then stay in the array with no clamp
+
+__host__ __device__ constexpr int rz_row(int c) { return c * (JB - 1) - c * (c - 1) / 2; }   // row c start
+
+__global__ __launch_bounds__(NT, 1) void trsm_persist2_kernel(const double* Z, int64_t ldz,
+                                                              const double* __restrict__ R, int64_t ldr,
+                                                              double* Q, int64_t ldq, int m, int n, int ntiles,
+                                                              const int32_t* __restrict__ info) {
+  constexpr int NF = 8 * NBLK2 * (NBLK2 - 1) / 2;
+  __shared__ double Qs[NM2 * LDQ2];               // Qs[j * LDQ2 + i]: row i of the tile, column j
+  __shared__ double RZ[NBLK2][RZO + RZP];         // R(j0 + c, j0 + col), col > c, packed by rows
+  __shared__ double rinv[NBLK2][JB];
+  if (info[0] != 0) return;
+  const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+  const int li = lane >> 4, lj = lane & 15;
+  const int nblk = (n + JB - 1) / JB;
+  for (int idx = t; idx < NBLK2 * RZP; idx += NT) {
+    const int J = idx / RZP, k = idx % RZP;
+    int c = 0;
+    while (k >= rz_row(c + 1)) ++c;
+    const int col = c + 1 + (k - rz_row(c)), gr = J * JB + c, gc = J * JB + col;
+    RZ[J][RZO + k] = (gc < n) ? R[(int64_t)gc * ldr + gr] : 0.0;
+  }
+  if (t < NBLK2) RZ[t][0] = 0.0;
+  for (int idx = t; idx < NBLK2 * JB; idx += NT)
+    rinv[idx / JB][idx % JB] = (idx < n) ? 1.0 / R[(int64_t)idx * ldr + idx] : 1.0;
+  // MFMA update: wave w owns column half hw = w & 1 of every block and the four 16-row blocks
+  // 4 (w >> 1) .. 4 (w >> 1) + 3, so it keeps the R fragments of its half only:
+  // rf[off(J) + s] = R(4 s + li, j0 + 16 hw + lj), s < 8 J
+  const int hw = wave & 1, rb0 = 4 * (wave >> 1);
+  double rf[NF];
+#pragma unroll
+  for (int J = 1; J < NBLK2; ++J) {
+    const int off = 8 * J * (J - 1) / 2;
+    const int jc = J * JB + 16 * hw + lj;
+#pragma unroll
+    for (int s2 = 0; s2 < 8 * J; ++s2) {
+      const int kk = 4 * s2 + li;
+      rf[off + s2] = (jc < n && kk < n) ? R[(int64_t)jc * ldr + kk] : 0.0;
+    }
+  }
+  // Z tile: thread (row pi = t % 128, columns pj + 2u), in groups of 16 loads (no registers held
+  // across the tile: the R fragments fill them)
+  constexpr int PU = NM2 / 2;
+  const int pi = t % BM2, pj = t / BM2;
+  const int row = t >> 2, sub = t & 3;      // substitution rows row and row + 64, 4 lanes per row
+  for (int tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+    const int i0 = tile * BM2;
+    {
+      const int zrow = min(i0 + pi, m - 1);
+#pragma unroll
+      for (int u0 = 0; u0 < PU; u0 += 16) {
+        double zr[16];
+#pragma unroll
+        for (int u = 0; u < 16; ++u) zr[u] = Z[(int64_t)min(pj + 2 * (u0 + u), n - 1) * ldz + zrow];
+#pragma unroll
+        for (int u = 0; u < 16; ++u) Qs[(pj + 2 * (u0 + u)) * LDQ2 + pi] = (pj + 2 * (u0 + u) < n) ? zr[u] : 0.0;
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int J = 0; J < NBLK2; ++J) {
+      if (J >= nblk) break;
+      const int j0 = J * JB;
+      if (J > 0) {
+        const int off = 8 * J * (J - 1) / 2;
+        f64x4 acc[4];                             // row block rb0 + b, column half hw
+#pragma unroll
+        for (int b = 0; b < 4; ++b)
+#pragma unroll
+          for (int r = 0; r < 4; ++r) acc[b][r] = Qs[(j0 + 16 * hw + lj) * LDQ2 + (rb0 + b) * 16 + 4 * r + li];
+#pragma unroll
+        for (int s2 = 0; s2 < 8 * J; ++s2) {
+#pragma unroll
+          for (int b = 0; b < 4; ++b)
+            acc[b] = mfma_f64(-Qs[(4 * s2 + li) * LDQ2 + (rb0 + b) * 16 + lj], rf[off + s2], acc[b]);
+          __builtin_amdgcn_sched_barrier(0);    // operand reads of one K step at a time
+        }
+#pragma unroll
+        for (int b = 0; b < 4; ++b)
+#pragma unroll
+          for (int r = 0; r < 4; ++r) Qs[(j0 + 16 * hw + lj) * LDQ2 + (rb0 + b) * 16 + 4 * r + li] = acc[b][r];
+      }
+      __syncthreads();
+      {
+        double x0[8], x1[8];
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+          x0[e] = Qs[(j0 + sub + 4 * e) * LDQ2 + row];
+          x1[e] = Qs[(j0 + sub + 4 * e) * LDQ2 + row + 64];
+        }
+        // R row c of the block for this lane's columns sub + 4e (> c), staged one step ahead; for
+        // columns <= c the index falls on other entries of the array (>= 0 with the padding entry),
+        // whose values are never used
+        double rzc[8], rzn[8], ric = rinv[J][0], rin = 1.0;
+        const double* rzl = &RZ[J][RZO + sub - 1];
+        auto stage = [&](double (&v)[8], int c) {
+#pragma unroll
+          for (int e = 0; e < 8; ++e) v[e] = rzl[rz_row(c) + 4 * e - c];
+        };
+        stage(rzc, 0);
+#pragma unroll
+        for (int c = 0; c < JB; ++c) {
+          if (c + 1 < JB) {
+            stage(rzn, c + 1);
+            rin = rinv[J][c + 1];
+          }
+          const int owner = c & 3, ec = c >> 2;
+          const double q0 = quad_bcast(x0[ec] * ric, owner);
+          const double q1 = quad_bcast(x1[ec] * ric, owner);
+#pragma unroll
+          for (int e = 0; e < 8; ++e)
+            if (4 * e + 3 > c) {
+              const bool live = sub + 4 * e > c;
+              x0[e] = live ? __builtin_fma(-q0, rzc[e], x0[e]) : x0[e];
+              x1[e] = live ? __builtin_fma(-q1, rzc[e], x1[e]) : x1[e];
+            }
+          x0[ec] = (sub == owner) ? q0 : x0[ec];
+          x1[ec] = (sub == owner) ? q1 : x1[ec];
+#pragma unroll
+          for (int e = 0; e < 8; ++e) rzc[e] = rzn[e];
+          ric = rin;
+          __builtin_amdgcn_sched_barrier(0);    // the R row of step c + 1 only
+        }
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+          Qs[(j0 + sub + 4 * e) * LDQ2 + row] = x0[e];
+          Qs[(j0 + sub + 4 * e) * LDQ2 + row + 64] = x1[e];
+        }
+      }
+      __syncthreads();
+    }
+    if (i0 + pi < m) {
+#pragma unroll
+      for (int u = 0; u < PU; ++u) {
+        const int j = pj + 2 * u;
+        if (j < n) Q[(int64_t)j * ldq + i0 + pi] = Qs[j * LDQ2 + pi];
+      }
+    }
+    __syncthreads();
+  }
+}
+
 // W = A Z for the 7-point operator (Dirichlet boundary, index p = x + nx (y + ny z)).
 // A thread owns one (x, y) point of one column and marches through z: the values at z-1, z and z+1
 // stay in registers, so each plane is read from HBM once; the four in-plane neighbours come from
@@ -339,10 +492,12 @@ hipError_t launch_trsm(const double* Z, int64_t ldz, const double* R, int64_t ld
   const int cus = device_cu_count();
   if (n <= 128 && ntiles >= 4 * cus && ntiles < 0x7fffffff) {
     const int grid = (n <= 64) ? 2 * cus : cus;   // 188 / 388 VGPRs: two or one workgroup per CU
-    if (n <= 64)
+    if (n <= 64) {
       trsm_persist_kernel<64><<<grid, NT, 0, s>>>(Z, ldz, R, ldr, Q, ldq, (int)m, (int)n, (int)ntiles, info);
-    else
-      trsm_persist_kernel<128><<<grid, NT, 0, s>>>(Z, ldz, R, ldr, Q, ldq, (int)m, (int)n, (int)ntiles, info);
+    } else {
+      const int64_t nt2 = (m + BM2 - 1) / BM2;
+      trsm_persist2_kernel<<<grid, NT, 0, s>>>(Z, ldz, R, ldr, Q, ldq, (int)m, (int)n, (int)nt2, info);
+    }
     return hipGetLastError();
   }
   if (n <= 64)
