@@ -294,10 +294,11 @@ __global__ __launch_bounds__(NT, 1) void trsm_persist_kernel(const double* Z, in
 // Persistent variant for 64 < n <= 128 with 128-row tiles: one workgroup (four waves, one per SIMD)
 // per CU; every thread carries two rows (t / 4 and t / 4 + 64) through the substitution, so two
 // independent chains share each pivot's R row, and every wave updates four 16-row blocks of one
-// 16-column half on MFMA (four accumulator chains, half the R fragments of a wave in registers).  The diagonal blocks of R are kept packed (strictly upper rows only) so that the
-// 128-row tile fits in LDS; the R fragments take the registers a next-tile prefetch would need, so a
-// tile's Z is loaded at its start.  Same operations in the same order per row as
-// trsm_persist_kernel<128>, so the results are identical.
+// 16-column half on MFMA (four accumulator chains, half the R fragments of a wave in registers).
+// The diagonal blocks of R are kept packed (strictly upper rows only) so that the 128-row tile fits
+// in LDS; the R fragments take the registers a next-tile prefetch would need, so a tile's Z is loaded
+// at its start.  Every row sees the same operations in the same order as in trsm_persist_kernel
+// instantiated for 128 columns (the 64-row layout this one replaces), so the results are identical.
 constexpr int NM2 = 128, BM2 = 128, LDQ2 = BM2 + 1, NBLK2 = NM2 / JB;
 constexpr int RZP = JB * (JB - 1) / 2;          // packed strictly upper entries of one diagonal block
 constexpr int RZO = 1;                            // entry 0 is padding: lane reads of columns <= c (unused)
