@@ -382,8 +382,9 @@ def main():
     args = parse()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path "
-              "(how it would shard is described in DESIGN.md)", file=sys.stderr)
+        print("bench.py measures one GPU only: the library has no multi-GPU path (sharded, each "
+              "GPU would hold a row block of Z and Q and the passes would all-reduce the n x n Gram)",
+              file=sys.stderr)
         sys.exit(2)
     import torch
     import paper_1401_5171_amd as oqr

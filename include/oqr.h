@@ -50,7 +50,7 @@ typedef enum {
   OQR_E_NOT_SPD = 2,      /* reserved: numerical failure is reported in info_dev */
   OQR_E_HIP = 3,          /* a HIP launch or runtime call failed */
   OQR_E_WORKSPACE = 4,    /* workspace too small or misaligned */
-  OQR_E_UNSUPPORTED = 5   /* valid request this build does not implement (e.g. n too large) */
+  OQR_E_UNSUPPORTED = 5   /* valid request the library does not implement (e.g. n too large) */
 } oqr_status;
 
 /* Storage type of A, Z, Q and R. */
@@ -93,7 +93,7 @@ typedef struct oqr_op {
  *             lo = bf16(x - hi)), products hi*hi + hi*lo + lo*hi on MFMA,
  *             FP32 accumulation inside a tile of K, FP64 across tiles.
  *   BF16X3  : three slices, the six products with slice indices i + j < 3.
- *   FP32    : reserved (OQR_E_UNSUPPORTED in this build for single instances). */
+ *   FP32    : reserved (OQR_E_UNSUPPORTED for single instances). */
 typedef enum { OQR_P_FP64 = 0, OQR_P_FP32 = 1, OQR_P_BF16X2 = 2, OQR_P_BF16X3 = 3 } oqr_prec;
 
 /* Gram-Schmidt variants for oqr_gs (Section 6 and the comments of Section 8). */

@@ -316,7 +316,7 @@ const char* oqr_status_string(int status) {
     case OQR_E_NOT_SPD: return "OQR_E_NOT_SPD: operator is not symmetric positive definite";
     case OQR_E_HIP: return "OQR_E_HIP: a HIP launch or runtime call failed";
     case OQR_E_WORKSPACE: return "OQR_E_WORKSPACE: workspace too small or not 256-byte aligned";
-    case OQR_E_UNSUPPORTED: return "OQR_E_UNSUPPORTED: request not implemented by this build";
+    case OQR_E_UNSUPPORTED: return "OQR_E_UNSUPPORTED: request not implemented by the library";
     default: return "unknown oqr status";
   }
 }
