@@ -215,6 +215,12 @@ typedef struct oqr_batch_item {
   int32_t m, n;
 } oqr_batch_item;
 
+/* info_dev values of oqr_cholqr2_batched, one per instance: 0 success; k > 0 the
+ * Cholesky of the Gram broke down at pivot k in spite of the allowed shifted
+ * retries; OQR_BATCH_BAD_ITEM the item breaks the limits stated below, checked
+ * on the device before anything of the instance is read or written. */
+enum { OQR_BATCH_BAD_ITEM = -1 };
+
 /* Workspace bytes for oqr_cholqr2_batched. */
 size_t oqr_batched_workspace_bytes(int64_t batch, int32_t max_m, int32_t max_n, int32_t dtype);
 
@@ -222,10 +228,17 @@ size_t oqr_batched_workspace_bytes(int64_t batch, int32_t max_m, int32_t max_n, 
  * persistent launch: workgroups take instances from a device work queue
  * (largest first), each instance runs both passes inside one workgroup with
  * FP64 Gram accumulation, Cholesky (shift/retry as in opts) and substitution.
- * items_dev: device array of `batch` items; m_i >= n_i >= 1, n_i <= 64,
- * m_i <= max_m.  dtype: OQR_F64 or OQR_F32 (FP32 storage and FP32 operator
- * products, FP64 Gram/Cholesky/substitution).  info_dev: `batch` int32, one per
- * instance.  The call allocates nothing and may be captured in a hipGraph.
+ * items_dev: device array of `batch` items with 1 <= n_i <= max_n <= 64,
+ * n_i <= m_i <= max_m, non-null pointers, lda >= m_i, ldz >= m_i, ldq >= m_i,
+ * ldr >= n_i, and A_i, Z_i and Q_i each spanning at most 2^31 - 1 bytes
+ * ((m_i - 1) lda + m_i elements, (n_i - 1) ldz + m_i, (n_i - 1) ldq + m_i);
+ * an item outside these limits gets OQR_BATCH_BAD_ITEM.  dtype: OQR_F64 or
+ * OQR_F32 (FP32 storage, widened to FP64 on load: every product, the Gram, the
+ * Cholesky and the substitution are FP64; Q and R are rounded to FP32 on
+ * store).  info_dev: `batch` int32, one per instance (values above).  Host
+ * errors: OQR_E_ARG for batch, max_m, max_n, dtype, tile or options out of
+ * range; OQR_E_UNSUPPORTED for a precision other than FP64.  The call
+ * allocates nothing and may be captured in a hipGraph.
  * tile: 0 = use the built-in tile table, else a tile id from
  * oqr_batched_tile_count() (autotuning). */
 int oqr_cholqr2_batched(int64_t batch, const oqr_batch_item* items_dev, int32_t dtype,

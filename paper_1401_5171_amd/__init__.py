@@ -24,6 +24,7 @@ LIB_PATH = os.path.join(_HERE, "liboqr.so")
 
 OQR_OK, OQR_E_ARG, OQR_E_NOT_SPD, OQR_E_HIP, OQR_E_WORKSPACE, OQR_E_UNSUPPORTED = range(6)
 OQR_F64, OQR_F32 = 0, 1
+OQR_BATCH_BAD_ITEM = -1          # info of a batch item outside the entry point's limits
 OQR_OP_DENSE, OQR_OP_STENCIL7, OQR_OP_TRIDIAG = 0, 1, 2
 PREC = {"fp64": 0, "fp32": 1, "bf16x2": 2, "bf16x3": 3}
 GS = {"cgs": 0, "mgs_row": 1, "mgs_col": 2, "cgs2": 3}

@@ -355,9 +355,22 @@ __device__ __noinline__ int cholqr_pass_wg(const T* A, int64_t lda, const T* Xin
   return 0;
 }
 
+// An item the kernel can run: the documented shape limits, leading dimensions that hold the matrices,
+// and every operand within the byte range of a buffer resource (the streaming loads take 32-bit
+// offsets).  Checked before anything of the item is read, so a malformed item only sets its info.
+template <class T>
+__device__ __forceinline__ bool item_ok(const oqr_batch_item& it, int max_m) {
+  const int64_t m = it.m, n = it.n, lim = 0x7fffffff / (int64_t)sizeof(T);
+  if (n < 1 || n > NB || m < n || m > max_m) return false;
+  if (!it.a || !it.z || !it.q || !it.r) return false;
+  if (it.lda < m || it.ldz < m || it.ldq < m || it.ldr < n) return false;
+  if (it.lda > lim || it.ldz > lim || it.ldq > lim || it.ldr > lim) return false;
+  return (m - 1) * it.lda + m <= lim && (n - 1) * it.ldz + m <= lim && (n - 1) * it.ldq + m <= lim;
+}
+
 template <class T>
 __global__ __launch_bounds__(NT, 2) void batch_kernel(const oqr_batch_item* __restrict__ items,
-                                                    const int32_t* __restrict__ order, int batch,
+                                                    const int32_t* __restrict__ order, int batch, int max_m,
                                                     int32_t* __restrict__ counter, int32_t* __restrict__ info,
                                                     double c_retry, int max_retries) {
   __shared__ Smem S;
@@ -370,6 +383,11 @@ __global__ __launch_bounds__(NT, 2) void batch_kernel(const oqr_batch_item* __re
     if (slot >= batch) break;
     const int id = order[slot];
     const oqr_batch_item it = items[id];
+    if (!item_ok<T>(it, max_m)) {
+      if (t == 0) info[id] = OQR_BATCH_BAD_ITEM;
+      __syncthreads();
+      continue;
+    }
     const T* A = (const T*)it.a;
     const T* Z = (const T*)it.z;
     T* Q = (T*)it.q;
@@ -425,7 +443,7 @@ __global__ __launch_bounds__(1024) void order_kernel(const oqr_batch_item* __res
   for (int i = t; i < p2; i += 1024) {
     unsigned long long k = ~0ull;                      // padding sorts last
     if (i < batch) {
-      const double cost = fmin((double)items[i].m * items[i].m * items[i].n, 1125899906842624.0);
+      const double cost = fmax(fmin((double)items[i].m * items[i].m * items[i].n, 1125899906842624.0), 0.0);
       k = ((unsigned long long)(1125899906842624.0 - cost) << 13) | (unsigned long long)i;
     }
     key[i] = k;
@@ -516,11 +534,11 @@ int oqr_cholqr2_batched(int64_t batch, const oqr_batch_item* items_dev, int32_t 
   if (grid > batch) grid = batch;
   trace_pre(K_BATCH, s);
   if (dtype == OQR_F64)
-    batch_kernel<double><<<(unsigned)grid, NT, 0, s>>>(items_dev, order, (int)batch, counter, info_dev, o.shift_c,
-                                                       o.max_retries);
+    batch_kernel<double><<<(unsigned)grid, NT, 0, s>>>(items_dev, order, (int)batch, max_m, counter, info_dev,
+                                                       o.shift_c, o.max_retries);
   else
-    batch_kernel<float><<<(unsigned)grid, NT, 0, s>>>(items_dev, order, (int)batch, counter, info_dev, o.shift_c,
-                                                      o.max_retries);
+    batch_kernel<float><<<(unsigned)grid, NT, 0, s>>>(items_dev, order, (int)batch, max_m, counter, info_dev,
+                                                      o.shift_c, o.max_retries);
   const hipError_t e = hipGetLastError();
   trace_post(K_BATCH, s);
   return e == hipSuccess ? OQR_OK : OQR_E_HIP;

@@ -132,6 +132,38 @@ def test_failing_instance_does_not_stop_the_batch():
         assert metrics.residual_f(z, to_host(plan.Qs[k]), to_host(plan.Rs[k])) <= 1e-12
 
 
+def test_malformed_items_are_flagged_and_left_alone():
+    """Items outside the entry point's limits (n above 64, m above max_m, lda below m, a null R,
+    an A whose leading dimension spans more than 2^31 - 1 bytes) get OQR_BATCH_BAD_ITEM, their
+    outputs stay untouched, and every other instance is solved as usual."""
+    insts = make_batch(8, seed=13)
+    As, Zs = upload(insts, np.float64)
+    plan = oqr.BatchPlan(As, Zs)
+    items = (oqr.BatchItem * plan.batch).from_buffer_copy(bytes(plan.items.cpu().numpy()))
+    items[1].n = 65
+    items[2].m = plan.max_m + 1
+    items[4].lda = items[4].m - 1
+    items[5].r = None
+    items[6].lda = 2 ** 28
+    bad = [1, 2, 4, 5, 6]
+    plan.items.copy_(torch.frombuffer(bytearray(bytes(items)), dtype=torch.uint8))
+    for k in bad:
+        plan.Qs[k].fill_(float("nan"))
+        plan.Rs[k].fill_(float("nan"))
+    banner("batch with malformed items")
+    plan.run()
+    torch.cuda.synchronize()
+    info = to_host(plan.info)
+    assert np.all(info[bad] == oqr.OQR_BATCH_BAD_ITEM), info
+    for k in bad:
+        assert np.all(np.isnan(to_host(plan.Qs[k]))) and np.all(np.isnan(to_host(plan.Rs[k])))
+    good = [k for k in range(len(insts)) if k not in bad]
+    assert np.all(info[good] == 0), info
+    for k in good:
+        a, z = insts[k]
+        assert metrics.residual_f(z, to_host(plan.Qs[k]), to_host(plan.Rs[k])) <= 1e-12
+
+
 def test_graph_capture_replays_match_eager():
     """The batched launch captured in a graph: several replays, with eager work and syncs between
     them, each equal bit for bit to the eager result."""
