@@ -26,12 +26,6 @@ constexpr int LD = NB + 1;
 
 constexpr double U64 = 1.1102230246251565e-16;
 
-template <class T>
-__device__ __forceinline__ double ldv(const T* p, int64_t i, bool ok) {
-  const T v = p[ok ? i : 0];
-  return ok ? (double)v : 0.0;
-}
-
 // Values the whole workgroup shares, moved to scalar registers (a non-inlined callee receives them in
 // vector registers; buffer resources must be scalar).
 __device__ __forceinline__ int uni(int v) { return __builtin_amdgcn_readfirstlane(v); }
@@ -43,19 +37,23 @@ __device__ __forceinline__ int64_t uni(int64_t v) {
 template <class P>
 __device__ __forceinline__ P* uni(P* p) { return (P*)(uintptr_t)uni((int64_t)(uintptr_t)p); }
 
-// Bounds-checked buffer load of one element (offset in elements; kOOB or beyond the range gives 0).
-// The raw bits are returned so that nothing consumes the value before it is needed.
+// Bounds-checked buffer load of element e, or 0 where `ok` is false: the byte offset is OR-ed with
+// kOOB, which lies beyond every operand's range (items are limited to 2^31 - 1 bytes), so the
+// hardware returns zero.  Branch-free on purpose: a select between the load and its use, or a load
+// under a branch, makes the compiler wait for the load at once and serialises a prefetch.  The raw
+// value is returned so that nothing consumes it before it is needed.
 template <class T> struct Raw;
 template <> struct Raw<double> {
   typedef double type;
-  static __device__ __forceinline__ double load(bufrsrc r, uint32_t e) {
-    return buf_f64(r, e == kOOB ? kOOB : e * 8u);
+  static __device__ __forceinline__ double load(bufrsrc r, int64_t e, bool ok) {
+    return buf_f64(r, ((uint32_t)e * 8u) | (ok ? 0u : kOOB));
   }
 };
 template <> struct Raw<float> {
   typedef float type;
-  static __device__ __forceinline__ float load(bufrsrc r, uint32_t e) {
-    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, (int)(e == kOOB ? kOOB : e * 4u), 0, 0));
+  static __device__ __forceinline__ float load(bufrsrc r, int64_t e, bool ok) {
+    return __builtin_bit_cast(float,
+                              __builtin_amdgcn_raw_buffer_load_b32(r, (int)(((uint32_t)e * 4u) | (ok ? 0u : kOOB)), 0, 0));
   }
 };
 
@@ -70,6 +68,7 @@ struct Fact {
 struct Smem {
   union {
     Tiles tl;                 // streaming phase of G = X^T A X
+    double xb[64][LD];        // half of X_b (64 rows) for the products X_b^T W_b
     double red[3][4][4][64];  // partial G of waves in row groups > 0
     Fact f;                   // Cholesky, substitution, R = R2 R1
   };
@@ -88,7 +87,7 @@ struct Smem {
 // (RG = 4 / CLS groups of 16 * RBW rows).  On return, waves of row group 0 hold G(:, 16 cb ..) in g.
 template <class T, int CLS>
 __device__ __noinline__ void gram_phase(const T* A_, int64_t lda_, const T* X_, int64_t ldx_, int m_, int n_, Smem& S,
-                                        f64x4 (&g)[4]) {
+                                        f64x4 (&g_out)[4]) {
   const T* A = uni(A_);
   const T* X = uni(X_);
   const int64_t lda = uni(lda_), ldx = uni(ldx_);
@@ -99,12 +98,13 @@ __device__ __noinline__ void gram_phase(const T* A_, int64_t lda_, const T* X_, 
   const int cb = wave % CLS, rg = wave / CLS;
   const int nbk = (n + 15) / 16;
   const bool active = cb < nbk;               // wave-uniform
-  f64x4 h[4];                                  // H (the blocks right of the diagonal)
+  f64x4 g[4], h[4];                            // D, H (the blocks right of the diagonal); local, so
+                                               // that they stay in registers
 #pragma unroll
   for (int b = 0; b < 4; ++b) g[b] = h[b] = f64x4{0, 0, 0, 0};
   // tile loads: A 16 values per thread (row t % BR, k = t / BR + 2q), X 8 values (k = t % BK, col t / BK + 8q),
   // unconditional buffer loads (elements outside the matrix read as 0), consumed only at the next LDS store
-  const int ai = t % BR, ak = t / BR;
+  const int ai = t % BR, ak = uni(t / BR);     // ak is wave-uniform (BR > 64)
   const int xk = t % BK, xj = t / BK;
   typedef typename Raw<T>::type RT;
   const bufrsrc abuf = make_buf(A, ((int64_t)(m - 1) * lda + m) * (int64_t)sizeof(T));
@@ -116,36 +116,49 @@ __device__ __noinline__ void gram_phase(const T* A_, int64_t lda_, const T* X_, 
 #pragma unroll
       for (int q = 0; q < BR * BK / NT; ++q) {
         const int k = k0 + ak + 2 * q;
-        ra[q] = Raw<T>::load(abuf, (rok && k < m) ? (uint32_t)((int64_t)k * lda + r0 + ai) : kOOB);
+        ra[q] = Raw<T>::load(abuf, (int64_t)k * lda + r0 + ai, rok && k < m);
       }
 #pragma unroll
       for (int q = 0; q < BK * NB / NT; ++q) {
         const int j = xj + 8 * q, k = k0 + xk;
-        rx[q] = Raw<T>::load(xbuf, (j < n && k < m) ? (uint32_t)((int64_t)j * ldx + k) : kOOB);
+        rx[q] = Raw<T>::load(xbuf, (int64_t)j * ldx + k, j < n && k < m);
       }
     };
     f64x4 w[RBW];
 #pragma unroll
     for (int b = 0; b < RBW; ++b) w[b] = f64x4{0, 0, 0, 0};
-    // dst += X_b^T W_b over this wave's rows
+    // dst += X_b^T W_b over this wave's rows.  X_b (the row block's rows of X) is staged through LDS
+    // in two halves of 64 rows, each one coalesced load (a wave per column, 64 rows) and one barrier,
+    // so that the products wait for two memory round trips per call rather than one per 16-row block.
+    // The tiles of the K loop are dead here (every K step ends with a barrier) and the halves overlay
+    // them; the trailing barrier protects the half from the next K step's tile stores.
     auto accum = [&](f64x4 (&dst)[4]) {
-      if (!active) return;
 #pragma unroll
-      for (int rb = 0; rb < RBW; ++rb) {
-        const int rbase = r0 + 16 * RBW * rg + 16 * rb;
-        double xa[4][4];
+      for (int hf = 0; hf < 2; ++hf) {
+        const int xi = t & 63, xw = uni(t >> 6);   // one column per wave
+        RT xv[4 * CLS];
 #pragma unroll
-        for (int s4 = 0; s4 < 4; ++s4)
+        for (int q = 0; q < 4 * CLS; ++q) {
+          const int j = xw + 4 * q, row = r0 + 64 * hf + xi;
+          xv[q] = Raw<T>::load(xbuf, (int64_t)j * ldx + row, j < n && row < m);
+        }
 #pragma unroll
-          for (int gi = 0; gi < 4; ++gi) {
-            const int row = rbase + 4 * s4 + li, col = 16 * gi + lj;
-            xa[s4][gi] = ldv(X, (int64_t)col * ldx + row, row < m && col < n);
+        for (int q = 0; q < 4 * CLS; ++q) S.xb[xi][xw + 4 * q] = (double)xv[q];
+        __syncthreads();
+        if (active) {
+#pragma unroll
+          for (int rb = 0; rb < RBW; ++rb) {
+            const int rl = 16 * RBW * rg + 16 * rb - 64 * hf;     // first row of the block in this half
+            if (rl >= 0 && rl < 64) {                              // wave-uniform
+#pragma unroll
+              for (int s4 = 0; s4 < 4; ++s4)
+#pragma unroll
+                for (int gi = 0; gi < CLS; ++gi)
+                  if (gi < nbk) dst[gi] = mfma_f64(S.xb[rl + 4 * s4 + li][16 * gi + lj], w[rb][s4], dst[gi]);
+            }
           }
-#pragma unroll
-        for (int s4 = 0; s4 < 4; ++s4)
-#pragma unroll
-          for (int gi = 0; gi < 4; ++gi)
-            if (gi < nbk) dst[gi] = mfma_f64(xa[s4][gi], w[rb][s4], dst[gi]);
+        }
+        __syncthreads();
       }
     };
     const int dend = min(m, r0 + BR);          // end of the diagonal block
@@ -219,6 +232,8 @@ __device__ __noinline__ void gram_phase(const T* A_, int64_t lda_, const T* X_, 
         g[gi][r] += h[gi][r] + ((i < nbk * 16) ? S.f.Ws[j][i] : 0.0);
       }
   }
+#pragma unroll
+  for (int b = 0; b < 4; ++b) g_out[b] = g[b];
   __syncthreads();
 }
 
@@ -323,14 +338,27 @@ __device__ __noinline__ int cholqr_pass_wg(const T* A, int64_t lda, const T* Xin
   __syncthreads();
   // ---- X <- X R^{-1}: four lanes per row (lane `sub` owns columns sub + 4e), the pivot column's
   // value broadcast within the quad; q_ij = (x_ij - sum_{k<j} q_ik r_kj) / r_jj, k ascending ---------
+  // The next 64 rows are loaded while the current ones are solved (rows are disjoint, so X may alias
+  // Xin); loads past the end read zeros.
   {
+    typedef typename Raw<T>::type RT;
     const int sub = t & 3;
+    const bufrsrc inb = make_buf(uni(Xin), (uni((int64_t)(n - 1) * ldxin) + uni(m)) * (int64_t)sizeof(T));
+    RT xn[NB / 4];
+    auto fetch = [&](int r0) {
+      const int row = r0 + (t >> 2);
+#pragma unroll
+      for (int e = 0; e < NB / 4; ++e)
+        xn[e] = Raw<T>::load(inb, (int64_t)(sub + 4 * e) * ldxin + row, row < m && sub + 4 * e < n);
+    };
+    fetch(0);
     for (int r0 = 0; r0 < m; r0 += NT / 4) {
       const int row = r0 + (t >> 2);
       const bool ok = row < m;
       double x[NB / 4];
 #pragma unroll
-      for (int e = 0; e < NB / 4; ++e) x[e] = ldv(Xin, (int64_t)(sub + 4 * e) * ldxin + row, ok && sub + 4 * e < n);
+      for (int e = 0; e < NB / 4; ++e) x[e] = (double)xn[e];
+      fetch(r0 + NT / 4);
 #pragma unroll
       for (int c = 0; c < NB; ++c) {
         if (c < n) {
