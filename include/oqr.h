@@ -50,7 +50,8 @@ typedef enum {
   OQR_E_NOT_SPD = 2,      /* reserved: numerical failure is reported in info_dev */
   OQR_E_HIP = 3,          /* a HIP launch or runtime call failed */
   OQR_E_WORKSPACE = 4,    /* workspace too small or misaligned */
-  OQR_E_UNSUPPORTED = 5   /* valid request the library does not implement (e.g. n too large) */
+  OQR_E_UNSUPPORTED = 5   /* valid request the library does not implement (n or a leading
+                             dimension beyond the limits below OQR_MAX_N) */
 } oqr_status;
 
 /* Storage type of A, Z, Q and R. */
@@ -130,6 +131,15 @@ typedef enum {
 
 /* Largest n the single-instance kernels support. */
 #define OQR_MAX_N 256
+
+/* Size limits of the single-instance entry points, oqr_check and oqr_gls: the
+ * kernels address operands with 32-bit byte offsets from a base that moves
+ * with the tile, a tile spanning up to c = min(columns, 256) columns of an
+ * operand (dense operator) or c = min(columns, 64) (stencil, tridiagonal).
+ * Each leading dimension (of Z and Q with n columns, of B with k columns),
+ * and m + 32, must not exceed (2^31 - 1) / (8 c) rows: at n >= 64 that is
+ * 1048575 rows for a dense operator with n >= 256 and 4194303 otherwise.
+ * Beyond that the call returns OQR_E_UNSUPPORTED before touching the device. */
 
 /* Fills *opts with the defaults: pass1 = pass2 = FP64, shift_c = 1, max_retries = 3, CGS. */
 void oqr_default_opts(oqr_opts* opts);

@@ -116,6 +116,18 @@ int check_op(const oqr_op* A, int64_t m) {
   return OQR_OK;
 }
 
+// The kernels address an operand with 32-bit byte offsets from a base that moves with the tile, and
+// a tile spans at most min(n, 64) columns (Gram tiles, stencil column groups) or min(n, 256) (the
+// right operand of the dense product).  Every leading dimension of an n-column operand, and the
+// library's own m x n workspace (leading dimension below m + 32), must keep that many columns within
+// 2^31 bytes; larger requests are refused rather than read past the reach of an offset.
+bool offsets_fit(const oqr_op* A, int64_t m, int64_t n, int64_t ld) {
+  const int64_t span = (A->kind == OQR_OP_DENSE) ? 256 : 64;
+  const int64_t cols = n < 1 ? 1 : (n < span ? n : span);
+  const int64_t reach = (int64_t)0x7fffffff / 8 / cols;
+  return ld <= reach && m + 32 <= reach;
+}
+
 int check_common(const oqr_op* A, const double* Z, int64_t ldz, int64_t m, int64_t n, const double* Q, int64_t ldq,
                  const double* R, int64_t ldr, const int32_t* info) {
   if (m < 0 || n < 0 || m < n) return OQR_E_ARG;
@@ -126,6 +138,7 @@ int check_common(const oqr_op* A, const double* Z, int64_t ldz, int64_t m, int64
   if (ldz < m || ldq < m || ldr < n || ldz < 1) return OQR_E_ARG;
   int rc = check_op(A, m);
   if (rc) return rc;
+  if (!offsets_fit(A, m, n, ldz > ldq ? ldz : ldq)) return OQR_E_UNSUPPORTED;
   // Q may alias Z exactly; any other overlap is rejected.
   if (Q != Z) {
     const char* zb = (const char*)Z;
@@ -347,11 +360,10 @@ int oqr_cholqr(const oqr_op* A, const double* Z, int64_t ldz, int64_t m, int64_t
   oqr_opts o;
   if ((rc = resolve_opts(opts, &o))) return rc;
   hipStream_t s = (hipStream_t)stream;
+  if (n > 0 && (rc = ws_check(ws, ws_bytes, pass_ws(A, m, n, o, false, nullptr, nullptr)))) return rc;
   if (launch_fill_i32(info_dev, 0, 1, s) != hipSuccess) return OQR_E_HIP;
   if (n == 0) return OQR_OK;
   PassWs w;
-  const size_t need = pass_ws(A, m, n, o, false, nullptr, nullptr);
-  if ((rc = ws_check(ws, ws_bytes, need))) return rc;
   pass_ws(A, m, n, o, false, &w, ws);
   return cholqr_pass(A, Z, ldz, m, n, Q, ldq, R, ldr, o.pass1, o, w, w.shifts, info_dev, s);
 }
@@ -364,9 +376,10 @@ int oqr_pre_cholqr(const oqr_op* A, const double* Z, int64_t ldz, int64_t m, int
   oqr_opts o;
   if ((rc = resolve_opts(opts, &o))) return rc;
   hipStream_t s = (hipStream_t)stream;
+  if (n > 0 && (rc = ws_check(ws, ws_bytes, pre_ws(A, m, n, o)))) return rc;
   if (launch_fill_i32(info_dev, 0, 1, s) != hipSuccess) return OQR_E_HIP;
   if (n == 0) return OQR_OK;
-  if ((rc = ws_check(ws, ws_bytes, pre_ws(A, m, n, o)))) return rc;
+
   PassWs w;
   char* base = (char*)ws;
   const size_t pw = align256(pass_ws(A, m, n, o, false, &w, base));
@@ -390,11 +403,10 @@ int oqr_cholqr2(const oqr_op* A, const double* Z, int64_t ldz, int64_t m, int64_
   oqr_opts o;
   if ((rc = resolve_opts(opts, &o))) return rc;
   hipStream_t s = (hipStream_t)stream;
+  if (n > 0 && (rc = ws_check(ws, ws_bytes, pass_ws(A, m, n, o, true, nullptr, nullptr)))) return rc;
   if (launch_fill_i32(info_dev, 0, 1, s) != hipSuccess) return OQR_E_HIP;
   if (n == 0) return OQR_OK;
   PassWs w;
-  const size_t need = pass_ws(A, m, n, o, true, nullptr, nullptr);
-  if ((rc = ws_check(ws, ws_bytes, need))) return rc;
   pass_ws(A, m, n, o, true, &w, ws);
   // pass 1: Z -> (Q1, R1);  pass 2: Q1 -> (Q, R2);  R = R2 R1.  Q1 is kept in Q (pass 2 in place), or, for
   // the stencil with the fused Gram, in the padded workspace W, whose A Q1 the second pass never stores.
@@ -415,9 +427,10 @@ int oqr_gs(const oqr_op* A, const double* Z, int64_t ldz, int64_t m, int64_t n, 
   if ((rc = resolve_opts(opts, &o))) return rc;
   if (o.gs_variant < OQR_GS_CGS || o.gs_variant > OQR_GS_CGS2) return OQR_E_ARG;
   hipStream_t s = (hipStream_t)stream;
+  if (n > 0 && (rc = ws_check(ws, ws_bytes, gs_workspace_bytes(A, m, n)))) return rc;
   if (launch_fill_i32(info_dev, 0, 1, s) != hipSuccess) return OQR_E_HIP;
   if (n == 0) return OQR_OK;
-  if ((rc = ws_check(ws, ws_bytes, gs_workspace_bytes(A, m, n)))) return rc;
+
   return gs_run(A, Z, ldz, m, n, Q, ldq, R, ldr, o.gs_variant, ws, info_dev, s);
 }
 
@@ -430,13 +443,11 @@ int oqr_chol_a(const oqr_op* A, const double* Z, int64_t ldz, int64_t m, int64_t
   oqr_opts o;
   if ((rc = resolve_opts(opts, &o))) return rc;
   hipStream_t s = (hipStream_t)stream;
+  const size_t need = A->kind == OQR_OP_TRIDIAG ? chol_a_tridiag_workspace_bytes(m, n) : chol_a_workspace_bytes(m, n);
+  if (n > 0 && (rc = ws_check(ws, ws_bytes, need))) return rc;
   if (launch_fill_i32(info_dev, 0, 1, s) != hipSuccess) return OQR_E_HIP;
   if (n == 0) return OQR_OK;
-  if (A->kind == OQR_OP_TRIDIAG) {
-    if ((rc = ws_check(ws, ws_bytes, chol_a_tridiag_workspace_bytes(m, n)))) return rc;
-    return chol_a_tridiag_run(A, Z, ldz, m, n, Q, ldq, R, ldr, ws, info_dev, s);
-  }
-  if ((rc = ws_check(ws, ws_bytes, chol_a_workspace_bytes(m, n)))) return rc;
+  if (A->kind == OQR_OP_TRIDIAG) return chol_a_tridiag_run(A, Z, ldz, m, n, Q, ldq, R, ldr, ws, info_dev, s);
   return chol_a_run(A, Z, ldz, m, n, Q, ldq, R, ldr, ws, info_dev, s);
 }
 
@@ -449,9 +460,10 @@ int oqr_eig_a(const oqr_op* A, const double* Z, int64_t ldz, int64_t m, int64_t 
   oqr_opts o;
   if ((rc = resolve_opts(opts, &o))) return rc;
   hipStream_t s = (hipStream_t)stream;
+  if (n > 0 && (rc = ws_check(ws, ws_bytes, eig_a_workspace_bytes(m, n)))) return rc;
   if (launch_fill_i32(info_dev, 0, 1, s) != hipSuccess) return OQR_E_HIP;
   if (n == 0) return OQR_OK;
-  if ((rc = ws_check(ws, ws_bytes, eig_a_workspace_bytes(m, n)))) return rc;
+
   return eig_a_run(A, Z, ldz, m, n, Q, ldq, R, ldr, ws, info_dev, s);
 }
 
@@ -466,6 +478,7 @@ int oqr_gls(const oqr_op* A, const double* Q, int64_t ldq, const double* R, int6
   if (m < n || n < 1 || n > OQR_MAX_N || k < 0) return OQR_E_ARG;
   if (ldq < m || ldr < n || ldb < m || ldx < n) return OQR_E_ARG;
   if (check_op(A, m) != OQR_OK) return OQR_E_ARG;
+  if (!offsets_fit(A, m, n, ldq) || !offsets_fit(A, m, k, ldb) || k > 0x7fffffff) return OQR_E_UNSUPPORTED;
   if (k == 0) return OQR_OK;
   int rc;
   if ((rc = ws_check(ws, ws_bytes, gls_workspace_bytes(A, m, n, k)))) return rc;
@@ -478,6 +491,7 @@ int oqr_check(const oqr_op* A, const double* Z, int64_t ldz, int64_t m, int64_t 
   if (m < n || n < 1 || n > OQR_MAX_N || !Z || !Q || !R || ldz < m || ldq < m || ldr < n) return OQR_E_ARG;
   int rc = check_op(A, m);
   if (rc) return rc;
+  if (!offsets_fit(A, m, n, ldz > ldq ? ldz : ldq)) return OQR_E_UNSUPPORTED;
   if ((rc = ws_check(ws, ws_bytes, check_workspace_bytes(A, m, n)))) return rc;
   return check_run(A, Z, ldz, m, n, Q, ldq, R, ldr, ws, ws_bytes, out_dev, (hipStream_t)stream);
 }

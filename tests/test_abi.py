@@ -86,6 +86,30 @@ def test_argument_errors_before_any_launch(L, fn):
              None) == oqr.OQR_E_ARG
 
 
+def test_offset_reach_limits(L):
+    """Leading dimensions or m beyond what 32-bit tile offsets reach over min(n, 256) columns (dense
+    operator) or min(n, 64) (others), m + 32 included, are refused with OQR_E_UNSUPPORTED before any
+    launch; the largest accepted values pass validation (they stop at the workspace check).  The fake
+    operands lie 2^40 bytes apart, so that they do not overlap at these leading dimensions."""
+    fake = 1 << 40
+    op = _dense_op(1000)
+    for n, ldz, rc in ((256, 1048575, oqr.OQR_E_WORKSPACE), (256, 1048576, oqr.OQR_E_UNSUPPORTED),
+                       (8, 33554431, oqr.OQR_E_WORKSPACE), (8, 33554432, oqr.OQR_E_UNSUPPORTED)):
+        assert L.oqr_cholqr2(ctypes.byref(op), fake, ldz, 1000, n, fake * 2, ldz, fake * 3, n, None, fake * 4, 0,
+                             fake * 5, None) == rc, (n, ldz)
+    st = oqr._Op()
+    st.kind, st.nx, st.ny, st.nz, st.center, st.off = oqr.OQR_OP_STENCIL7, 2048, 2048, 1, 6.001, -1.0
+    m = 2048 * 2048                      # n = 64: m + 32 beyond 4194303
+    assert L.oqr_cholqr(ctypes.byref(st), fake, m, m, 64, fake * 2, m, fake * 3, 64, None, fake * 4, 0, fake * 5,
+                        None) == oqr.OQR_E_UNSUPPORTED
+    assert L.oqr_cholqr(ctypes.byref(st), fake, m, m, 8, fake * 2, m, fake * 3, 8, None, fake * 4, 0, fake * 5,
+                        None) == oqr.OQR_E_WORKSPACE
+    st.nx = 2047
+    m = 2047 * 2048
+    assert L.oqr_cholqr(ctypes.byref(st), fake, m, m, 64, fake * 2, m, fake * 3, 64, None, fake * 4, 0, fake * 5,
+                        None) == oqr.OQR_E_WORKSPACE
+
+
 def test_bad_options_rejected(L):
     op = _dense_op(10)
     o = oqr.make_opts()
