@@ -17,7 +17,7 @@ time taken from HIP events recorded around each launch inside the timed
 region.  The CPU baseline times the CPU oracle (CHOL-EQR, Algorithm 3) on the
 leading m' x m' sub-problem.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload dense32768|dense8192|stencil|tridiag|batch]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload dense32768|dense8192|stencil|tridiag|batch|small500]
 
 The batch workload (4096 independent instances, m log-uniform in [256, 4096], n in {8, 16, 32, 64},
 kappa(A_i) log-uniform in [1e2, 1e8], Gaussian Z_i) times one persistent launch of the batched
@@ -64,7 +64,7 @@ def parse():
     p.add_argument("--steps", type=int, default=10)
     p.add_argument("--warmup", type=int, default=3)
     p.add_argument("--workload", default="dense32768",
-                   choices=["dense32768", "dense8192", "stencil", "tridiag", "batch", "copycal"])
+                   choices=["dense32768", "dense8192", "stencil", "tridiag", "batch", "small500", "copycal"])
     p.add_argument("--batch-count", type=int, default=4096)
     p.add_argument("--batch-dtype", default="f64", choices=["f64", "f32"], help="storage type of the batch")
     p.add_argument("--tile", type=int, default=-1, help="batched tile id (-1: time every id, keep the best)")
@@ -378,6 +378,83 @@ def run_copycal(torch):
                       "ms_per_copy": round(dt * 1e3, 4), "GBs": round(2 * nbytes / dt / 1e9, 1)}), flush=True)
 
 
+def run_small(args, torch, oqr):
+    """The smallest workload of the paper's tables: dense A, m = 500 (Haar eigenvectors, kappa(A) = 1e4),
+    Z with kappa(Z) = 1e3, n = 20, every variant in FP64.  About 1e7 flops: launch- and latency-bound,
+    so the line reports the latency of one factorisation per variant (host call to completion, min and
+    median of `steps`) and no roofline fraction."""
+    import numpy as np
+    import workloads as W
+    rng = W.rng_for(1)
+    m, n = 500, 20
+    a, _, _ = W.dense_spd(rng, m, 1e4)
+    z = W.tall_skinny(rng, m, n, 1e3)
+    A = torch.from_numpy(np.ascontiguousarray(a)).cuda()
+    Z = torch.from_numpy(np.ascontiguousarray(z.T)).cuda().t()
+    flops = 2.0 * m * m * n + 2.0 * m * n * n
+    specs = [("cholqr", "cholqr", {}), ("cholqr2", "cholqr2", {}), ("pre_cholqr", "pre_cholqr", {}),
+             ("chol_eqr", "chol_a", {}), ("eqr_syev", "eig_a", {}), ("cgs", "gs", {"gs_variant": "cgs"}),
+             ("cgs2", "gs", {"gs_variant": "cgs2"}), ("mgs_row", "gs", {"gs_variant": "mgs_row"}),
+             ("mgs_col", "gs", {"gs_variant": "mgs_col"})]
+    out = {}
+    for name, alg, kw in specs:
+        plan = oqr.Plan(alg, A, n, **kw)
+        Q = torch.empty(n, m, dtype=torch.float64, device="cuda").t()
+        R = torch.empty(n, n, dtype=torch.float64, device="cuda").t()
+        for _ in range(max(args.warmup, 1)):
+            plan.run(Z, Q, R)
+        torch.cuda.synchronize()
+        ts = []
+        for _ in range(args.steps):
+            t0 = time.perf_counter()
+            plan.run(Z, Q, R)
+            torch.cuda.synchronize()
+            ts.append(time.perf_counter() - t0)
+        orth, res = oqr.check(A, Z, Q, R)
+        out[name] = {"us_min": round(min(ts) * 1e6, 1), "us_median": round(float(np.median(ts)) * 1e6, 1),
+                     "orth_loss_fro": orth, "residual_fro": res, "info": int(plan.info.item())}
+        log(f"{name}: {min(ts) * 1e6:.1f} us (median {np.median(ts) * 1e6:.1f}), orth {orth:.2e}")
+        if name == "cholqr2":
+            # the same call captured in a HIP graph: one graph launch per factorisation
+            g = plan.capture(Z, Q, R)
+            g.replay()
+            torch.cuda.synchronize()
+            ts = []
+            for _ in range(args.steps):
+                t0 = time.perf_counter()
+                g.replay()
+                torch.cuda.synchronize()
+                ts.append(time.perf_counter() - t0)
+            orth, res = oqr.check(A, Z, Q, R)
+            out["cholqr2_graph"] = {"us_min": round(min(ts) * 1e6, 1),
+                                    "us_median": round(float(np.median(ts)) * 1e6, 1),
+                                    "orth_loss_fro": orth, "residual_fro": res, "info": int(plan.info.item())}
+            log(f"cholqr2 (graph replay): {min(ts) * 1e6:.1f} us (median {np.median(ts) * 1e6:.1f})")
+    # the oracle (CHOL-EQR) on the same problem, repeated for about two seconds
+    from threadpoolctl import threadpool_info
+    from oracle import reference
+    reps, t0 = 0, time.perf_counter()
+    while time.perf_counter() - t0 < 2.0:
+        reference.chol_eqr(a, z)
+        reps += 1
+    tc = (time.perf_counter() - t0) / reps
+    threads = max([i.get("num_threads", 1) for i in threadpool_info()] or [1])
+    c2 = out["cholqr2"]
+    line = {
+        "metric": METRIC, "value": round(flops / (c2["us_median"] * 1e-6) / 1e9, 3), "unit": "GFLOP/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(c2["us_median"] / 1e3, 4),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": f"dense SPD A m={m} n={n} kappa(A)=1e4 kappa(Z)=1e3 (Haar), every variant FP64",
+                   "flops_per_step": flops, "flop_count": "2m^2n+2mn^2 (paper normalisation)"},
+        "variants_latency": out,
+        "roofline": None,
+        "roofline_note": "about 1e7 flops per factorisation: launch- and latency-bound, no roofline fraction",
+        "cpu_baseline": {"value": round(flops / tc / 1e9, 3), "unit": "GFLOP/s", "cores": threads, "kind": "oracle",
+                         "sample": f"chol_eqr on the whole problem, {reps} repetitions", "us_per_call": round(tc * 1e6, 1)},
+    }
+    print(json.dumps(line), flush=True)
+
+
 def main():
     args = parse()
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -397,6 +474,8 @@ def main():
         return run_batch(args, torch, oqr)
     if args.workload == "copycal":
         return run_copycal(torch)
+    if args.workload == "small500":
+        return run_small(args, torch, oqr)
     A, Z, z_host, m, n, desc, flops, dom_kernel, dom_flops = make_inputs(args.workload, torch)
     dense = not hasattr(A, "nx") and not hasattr(A, "host")
     # pass 1 of the mixed schedule: hi/lo bfloat16 operands (two slices, products hi*hi + hi*lo + lo*hi),

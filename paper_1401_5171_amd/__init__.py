@@ -233,6 +233,25 @@ class Plan:
                      self.info.data_ptr(), s)
         _raise(rc, "oqr_" + self.alg)
 
+    def capture(self, Z, Q, R):
+        """Capture one call on these tensors into a HIP graph (a torch.cuda.CUDAGraph) and return it:
+        `graph.replay()` re-runs the factorisation of whatever Z then holds into the same Q, R and
+        `info`, as one graph launch instead of one launch per kernel.  The call is made once eagerly on
+        the capture stream first, so that the library's one-time device queries run outside the
+        capture.  The library issues no memset or allocation, so every replay repeats the eager
+        result bit for bit."""
+        torch = _torch()
+        s = torch.cuda.Stream(self.device)
+        s.wait_stream(torch.cuda.current_stream(self.device))
+        with torch.cuda.stream(s):
+            self.run(Z, Q, R)
+        torch.cuda.current_stream(self.device).wait_stream(s)
+        torch.cuda.synchronize(self.device)
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g, stream=s):
+            self.run(Z, Q, R)
+        return g
+
     def __call__(self, Z, check_info=True):
         torch = _torch()
         Z = colmajor(Z)
