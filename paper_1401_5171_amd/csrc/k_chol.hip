@@ -7,8 +7,8 @@
 //   (a) wave w forms block (K, K+w) of G - sum_{P<K} R_PK^T R_PJ on FP64 MFMA,
 //       reading the finished rows of R (L2-resident) and keeping the result in
 //       LDS,
-//   (b) the diagonal block is factored in LDS (double-buffered, 2 entries per
-//       thread, one barrier per pivot),
+//   (b) the diagonal block is factored by one wave in registers (lane j holds
+//       column j; pivots and pivot rows broadcast by readlane),
 //   (c) the rest of the block row is solved column by column,
 //       R_KJ = R_KK^{-T} (G_KJ - ...), and written to R.
 // A pivot that is not positive (or NaN) restarts the factorisation from G with
@@ -26,11 +26,56 @@ constexpr int NTC = 512;
 constexpr int NW = NTC / 64;
 constexpr int DPT = CB * CB / NTC;   // diagonal-block entries per thread
 
+// v of lane l, in every lane (a register read, no LDS)
+__device__ __forceinline__ double bcast_lane(double v, int l) {
+  const long long b = __builtin_bit_cast(long long, v);
+  const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffff), l);
+  const int hi = __builtin_amdgcn_readlane((int)(b >> 32), l);
+  return __builtin_bit_cast(double, ((long long)hi << 32) | (unsigned int)lo);
+}
+
+// Factors the diagonal block Dk (CB x CB, upper triangle used) in place on one wave, in registers:
+// lane j keeps column j; the pivot and pivot row k's entries are broadcast with readlane, so a pivot
+// costs neither an LDS round trip nor a workgroup barrier.  Lanes j <= k keep their lower entries,
+// which are never read; lanes 32..63 mirror 0..31 and store nothing.  1 / r_kk goes to rdiag; a pivot
+// that is not positive (or NaN) stores its 1-based index plus k0 in *s_fail and leaves Dk unchanged.
+// Kept out of line so that its 32 register columns do not add to the pressure of the MFMA update.
+__device__ __noinline__ void diag_factor(double (*Dk)[CB + 1], double* rdiag, int* s_fail, int k0, int lane) {
+  const int j = lane & (CB - 1);
+  double d[CB];
+#pragma unroll
+  for (int i = 0; i < CB; ++i) d[i] = Dk[i][j];
+  int fail = 0;
+  // fully unrolled (constant register indices); after a failed pivot the rest is skipped, a
+  // uniform branch since the pivot is a broadcast value
+#pragma unroll
+  for (int k = 0; k < CB; ++k) {
+    if (fail == 0) {
+      const double piv = bcast_lane(d[k], k);
+      if (!(piv > 0.0)) {
+        fail = k0 + k + 1;
+      } else {
+        const double ri = rsqrt_nr(piv), rkk = piv * ri;   // one refined reciprocal square root per pivot
+        if (lane == 0) rdiag[k] = ri;
+        d[k] = (j == k) ? rkk : ((j > k) ? d[k] * ri : d[k]);      // row k of R
+#pragma unroll
+        for (int i = k + 1; i < CB; ++i) d[i] = d[i] - bcast_lane(d[k], i) * d[k];   // r_ki r_kj
+      }
+    }
+  }
+  if (fail) {
+    if (lane == 0) *s_fail = fail;
+  } else if (lane < CB) {
+#pragma unroll
+    for (int i = 0; i < CB; ++i) Dk[i][j] = d[i];
+  }
+}
+
 __global__ __launch_bounds__(NTC) void chol_kernel(const double* __restrict__ G, int n, double* __restrict__ R,
                                                     int64_t ldr, double unit, double c_first, double c_retry,
                                                     int max_retries, int32_t* __restrict__ info,
                                                     double* __restrict__ shift_used) {
-  __shared__ double Dk[2][CB][CB + 1];
+  __shared__ double Dk[1][CB][CB + 1];         // the diagonal block of block row K
   __shared__ double P[CB][OQR_MAX_N + 2];     // block row K: P[p][j] = entry (k0 + p, j), j absolute column
   __shared__ double red[NW];
   __shared__ double rdiag[CB];                // 1 / r_kk of the current diagonal block
@@ -131,26 +176,8 @@ __global__ __launch_bounds__(NTC) void chol_kernel(const double* __restrict__ G,
             }
       }
       __syncthreads();
-      // (b) factor the diagonal block (double-buffered, one barrier per step)
-      for (int k = 0; k < CB; ++k) {
-        const int cur = k & 1, nxt = cur ^ 1;
-        const double piv = Dk[cur][k][k];
-        if (!(piv > 0.0)) {                    // every thread reads the same value: uniform exit
-          if (t == 0) s_fail = k0 + k + 1;
-          break;
-        }
-        const double ri = rsqrt_nr(piv), rkk = piv * ri;   // one refined reciprocal square root per pivot
-        if (t == 0) rdiag[k] = ri;
-#pragma unroll
-        for (int e = 0; e < DPT; ++e) {
-          const int di = (t + NTC * e) >> 5, dj = (t + NTC * e) & 31;
-          double nv = Dk[cur][di][dj];
-          if (di == k && dj >= k) nv = (dj == k) ? rkk : nv * ri;
-          else if (di > k && dj >= di) nv = nv - (Dk[cur][k][di] * ri) * (Dk[cur][k][dj] * ri);
-          Dk[nxt][di][dj] = nv;
-        }
-        __syncthreads();
-      }
+      // (b) factor the diagonal block on wave 0, in registers
+      if (wave == 0) diag_factor(Dk[0], rdiag, &s_fail, k0, lane);
       __syncthreads();
       if (s_fail) break;
       // (c) write the diagonal block; solve the rest of the block row, one thread per column
