@@ -138,7 +138,8 @@ typedef enum {
  * operand (dense operator) or c = min(columns, 64) (stencil, tridiagonal).
  * Each leading dimension (of Z and Q with n columns, of B with k columns),
  * and m + 32, must not exceed (2^31 - 1) / (8 c) rows: at n >= 64 that is
- * 1048575 rows for a dense operator with n >= 256 and 4194303 otherwise.
+ * 1048575 rows for a dense operator with n >= 256 and 4194303 otherwise; and
+ * n * ldr must not exceed (2^31 - 1) / 8.
  * Beyond that the call returns OQR_E_UNSUPPORTED before touching the device. */
 
 /* Fills *opts with the defaults: pass1 = pass2 = FP64, shift_c = 1, max_retries = 3, CGS. */

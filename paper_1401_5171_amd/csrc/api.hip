@@ -139,6 +139,7 @@ int check_common(const oqr_op* A, const double* Z, int64_t ldz, int64_t m, int64
   int rc = check_op(A, m);
   if (rc) return rc;
   if (!offsets_fit(A, m, n, ldz > ldq ? ldz : ldq)) return OQR_E_UNSUPPORTED;
+  if (n * ldr > (int64_t)0x7fffffff / 8) return OQR_E_UNSUPPORTED;    // R through a buffer resource
   // Q may alias Z exactly; any other overlap is rejected.
   if (Q != Z) {
     const char* zb = (const char*)Z;

@@ -98,6 +98,9 @@ __global__ __launch_bounds__(NTC) void chol_kernel(const double* __restrict__ G,
   __syncthreads();
   const double dmax = s_dmax;
   const int li = lane >> 4, lj = lane & 15;   // MFMA layouts
+  // G (n x n) and R (n columns of ldr) through buffer resources; the host keeps n * ldr * 8 below 2^31
+  const bufrsrc gbuf = make_buf(G, (int64_t)n * n * 8);
+  const bufrsrc rbuf = make_buf(R, ((int64_t)(n - 1) * ldr + n) * 8);
 
   double c = c_first;
   for (int attempt = 0;; ++attempt) {
@@ -110,6 +113,8 @@ __global__ __launch_bounds__(NTC) void chol_kernel(const double* __restrict__ G,
       const int J = K + wave;
       if (J < nb) {
         const int J0 = J * CB;
+        // G's upper triangle (identity beyond n).  Branch-free buffer loads, lanes outside the triangle
+        // masked with kOOB (they read 0), so that the 16 loads are in flight together.
         f64x4 acc[2][2];
 #pragma unroll
         for (int x = 0; x < 2; ++x)
@@ -118,20 +123,26 @@ __global__ __launch_bounds__(NTC) void chol_kernel(const double* __restrict__ G,
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
               const int i = k0 + 16 * x + 4 * r + li, j = J0 + 16 * y + lj;
-              double g = (i == j) ? 1.0 : 0.0;      // identity beyond n
-              if (i < n && j < n) g = (i <= j) ? G[(int64_t)j * n + i] + (i == j ? s : 0.0) : 0.0;
-              acc[x][y][r] = g;
+              const bool in = i < n && j < n && i <= j;
+              acc[x][y][r] = buf_f64(gbuf, ((uint32_t)(j * n + i) * 8u) | (in ? 0u : kOOB));
             }
-        const double* Ra[2];
-        const double* Rb[2];
-        bool oka[2], okb[2];
+#pragma unroll
+        for (int x = 0; x < 2; ++x)
+#pragma unroll
+          for (int y = 0; y < 2; ++y)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+              const int i = k0 + 16 * x + 4 * r + li, j = J0 + 16 * y + lj;
+              if (i == j) acc[x][y][r] = (i < n) ? acc[x][y][r] + s : 1.0;
+            }
+        // byte offsets of this lane's entries of R in columns k0 + 16 x + lj (A operand) and
+        // J0 + 16 x + lj (B operand), rows li + 4 u of a chunk; columns beyond n read 0
+        uint32_t aoff[2], boff[2];
 #pragma unroll
         for (int x = 0; x < 2; ++x) {
           const int ca = k0 + 16 * x + lj, cb = J0 + 16 * x + lj;
-          oka[x] = ca < n;
-          okb[x] = cb < n;
-          Ra[x] = R + (int64_t)min(ca, n - 1) * ldr + li;
-          Rb[x] = R + (int64_t)min(cb, n - 1) * ldr + li;
+          aoff[x] = ((uint32_t)((int64_t)ca * ldr + li) * 8u) | (ca < n ? 0u : kOOB);
+          boff[x] = ((uint32_t)((int64_t)cb * ldr + li) * 8u) | (cb < n ? 0u : kOOB);
         }
         // rows of R in chunks of 32 (8 MFMA k steps), the next chunk loaded during the current one
         double a[8][2], b[8][2];
@@ -140,8 +151,8 @@ __global__ __launch_bounds__(NTC) void chol_kernel(const double* __restrict__ G,
           for (int u = 0; u < 8; ++u)
 #pragma unroll
             for (int x = 0; x < 2; ++x) {
-              aa[u][x] = -sel_load(Ra[x], p0 + 4 * u, oka[x]);
-              bb[u][x] = sel_load(Rb[x], p0 + 4 * u, okb[x]);
+              aa[u][x] = buf_f64(rbuf, aoff[x] + (uint32_t)(p0 + 4 * u) * 8u);
+              bb[u][x] = buf_f64(rbuf, boff[x] + (uint32_t)(p0 + 4 * u) * 8u);
             }
         };
         if (k0 > 0) load_chunk(0, a, b);
@@ -153,7 +164,7 @@ __global__ __launch_bounds__(NTC) void chol_kernel(const double* __restrict__ G,
 #pragma unroll
             for (int x = 0; x < 2; ++x)
 #pragma unroll
-              for (int y = 0; y < 2; ++y) acc[x][y] = mfma_f64(a[u][x], b[u][y], acc[x][y]);
+              for (int y = 0; y < 2; ++y) acc[x][y] = mfma_f64(-a[u][x], b[u][y], acc[x][y]);
           if (p0 + CB < k0) {
 #pragma unroll
             for (int u = 0; u < 8; ++u)
