@@ -123,20 +123,42 @@ __global__ __launch_bounds__(NT, 2) void gemm_f64_kernel(const double* __restric
       store();
       __syncthreads();
     }
+    if (MODE == GEMM_DIAG) {
+      // W = acc + Wadd: the addends of one row block are loaded together (branch-free buffer loads,
+      // lanes outside the matrix masked with kOOB) before any is used, one round trip per row block
+      const bufrsrc wb = make_buf(Wadd, ((int64_t)(n - 1) * ldadd + m) * 8);
 #pragma unroll
-    for (int a = 0; a < 4; ++a)
+      for (int a = 0; a < 4; ++a) {
+        double add[CB][4];
 #pragma unroll
-      for (int b = 0; b < CB; ++b)
+        for (int b = 0; b < CB; ++b)
 #pragma unroll
-        for (int r = 0; r < 4; ++r) {
-          const int i = i0 + a * 16 + 4 * r + (lane >> 4);
-          const int j = j0 + wc + b * 16 + (lane & 15);
-          if (i < m && j < n) {
-            double v = acc[a][b][r];
-            if (MODE == GEMM_DIAG) v += Wadd[(int64_t)j * ldadd + i];
-            W[(int64_t)j * ldw + i] = v;
+          for (int r = 0; r < 4; ++r) {
+            const int i = i0 + a * 16 + 4 * r + (lane >> 4);
+            const int j = j0 + wc + b * 16 + (lane & 15);
+            add[b][r] = buf_f64(wb, ((uint32_t)((int64_t)j * ldadd + i) * 8u) | ((i < m && j < n) ? 0u : kOOB));
           }
-        }
+#pragma unroll
+        for (int b = 0; b < CB; ++b)
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            const int i = i0 + a * 16 + 4 * r + (lane >> 4);
+            const int j = j0 + wc + b * 16 + (lane & 15);
+            if (i < m && j < n) W[(int64_t)j * ldw + i] = acc[a][b][r] + add[b][r];
+          }
+      }
+    } else {
+#pragma unroll
+      for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < CB; ++b)
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            const int i = i0 + a * 16 + 4 * r + (lane >> 4);
+            const int j = j0 + wc + b * 16 + (lane & 15);
+            if (i < m && j < n) W[(int64_t)j * ldw + i] = acc[a][b][r];
+          }
+    }
   };
 
   if (MODE == GEMM_UPPER) {
