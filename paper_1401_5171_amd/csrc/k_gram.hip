@@ -67,16 +67,25 @@ __global__ __launch_bounds__(NT) void gram_f64_kernel(const double* __restrict__
   for (int b = 0; b < 4; ++b) acc[b] = f64x4{0, 0, 0, 0};
   const int lk = t % BK, lc = t / BK;   // k = lk, column = lc + 16 r
   double rx[4], ry[4], rx2[SYM ? 4 : 1], rxj[SYM ? 4 : 1];
+  // the 64 columns of blocks I and J through buffer resources based at the block (offsets stay below
+  // 2^31 bytes); branch-free loads, lanes past r1 or n masked with kOOB (they read 0), so that the next
+  // K step's loads stay in flight during this step's products
+  const int wi = min(TB, n - I0), wj = min(TB, n - J0);
+  const bufrsrc bx = make_buf(X + (int64_t)I0 * ldx, ((int64_t)(wi - 1) * ldx + m) * 8);
+  const bufrsrc by = make_buf(Y + (int64_t)J0 * ldy, ((int64_t)(wj - 1) * ldy + m) * 8);
+  const bufrsrc bx2 = make_buf(SYM ? X2 + (int64_t)I0 * ldx2 : X, SYM ? ((int64_t)(wi - 1) * ldx2 + m) * 8 : 0);
+  const bufrsrc bxj = make_buf(X + (int64_t)J0 * ldx, ((int64_t)(wj - 1) * ldx + m) * 8);
   auto load = [&](int k0) {
     const int k = k0 + lk;
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
-      const int cx = I0 + lc + 16 * r, cy = J0 + lc + 16 * r;
-      rx[r] = sel_load(X, (int64_t)cx * ldx + k, k < r1 && cx < n);
-      ry[r] = sel_load(Y, (int64_t)cy * ldy + k, k < r1 && cy < n);
+      const int c = lc + 16 * r;
+      const uint32_t mx = (k < r1 && I0 + c < n) ? 0u : kOOB, my = (k < r1 && J0 + c < n) ? 0u : kOOB;
+      rx[r] = buf_f64(bx, ((uint32_t)((int64_t)c * ldx + k) * 8u) | mx);
+      ry[r] = buf_f64(by, ((uint32_t)((int64_t)c * ldy + k) * 8u) | my);
       if (SYM) {
-        rx2[r] = sel_load(X2, (int64_t)cx * ldx2 + k, k < r1 && cx < n);
-        rxj[r] = sel_load(X, (int64_t)cy * ldx + k, k < r1 && cy < n);
+        rx2[r] = buf_f64(bx2, ((uint32_t)((int64_t)c * ldx2 + k) * 8u) | mx);
+        rxj[r] = buf_f64(bxj, ((uint32_t)((int64_t)c * ldx + k) * 8u) | my);
       }
     }
   };
@@ -96,7 +105,7 @@ __global__ __launch_bounds__(NT) void gram_f64_kernel(const double* __restrict__
   __syncthreads();
   for (int k0 = r0; k0 < r1; k0 += BK) {
     const bool more = k0 + BK < r1;
-    if (more) load(k0 + BK);
+    load(k0 + BK);                        // past r1: zeros, never stored
 #pragma unroll
     for (int kk = 0; kk < BK; kk += 4) {
       const int kr = kk + (lane >> 4);
