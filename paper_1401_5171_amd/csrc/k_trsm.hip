@@ -35,6 +35,7 @@ __global__ __launch_bounds__(NT, 2) void trsm_kernel(const double* Z, int64_t ld
   const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
   const int i0 = blockIdx.x * BMR;
   const int nblk = (n + JB - 1) / JB;
+  const bufrsrc rb_ = make_buf(R, ((int64_t)(n - 1) * ldr + n) * 8);
 
   auto stage_r = [&](int J) {
     const int j0 = J * JB;
@@ -86,27 +87,30 @@ __global__ __launch_bounds__(NT, 2) void trsm_kernel(const double* Z, int64_t ld
       for (int h = 0; h < NH; ++h)
 #pragma unroll
         for (int r = 0; r < 4; ++r) acc[h][r] = Qs[(j0 + 16 * (h0 + h) + lj) * LDQ + rb * 16 + 4 * r + li];
-      const double* Rc[NH];
-      bool okc[NH];
+      // byte offsets of this lane's R entries (column jc, rows li + ..); columns beyond n read 0.  R
+      // spans less than 2^31 bytes (the host checks n * ldr).
+      uint32_t rco[NH], rcm[NH];
 #pragma unroll
       for (int h = 0; h < NH; ++h) {
         const int jc = j0 + 16 * (h0 + h) + lj;
-        okc[h] = jc < n;
-        Rc[h] = R + (int64_t)min(jc, n - 1) * ldr + li;
+        rco[h] = (uint32_t)((int64_t)jc * ldr + li) * 8u;
+        rcm[h] = jc < n ? 0u : kOOB;
       }
-      // R fragments are read from L2 in chunks of 32 k (8 MFMA steps), one chunk ahead
+      // R fragments are read from L2 in chunks of 32 k (8 MFMA steps), one chunk ahead; branch-free
+      // buffer loads (a chunk past j0 is masked with kOOB), so the loads overlap the products
       double bf[NH][8];
 #pragma unroll
       for (int h = 0; h < NH; ++h)
 #pragma unroll
-        for (int s = 0; s < 8; ++s) bf[h][s] = sel_load(Rc[h], 4 * s, okc[h]);
+        for (int s = 0; s < 8; ++s) bf[h][s] = buf_f64(rb_, (rco[h] + (uint32_t)(4 * s) * 8u) | rcm[h]);
       for (int kc = 0; kc < j0; kc += 32) {
         double nb[NH][8];
-        const bool more = kc + 32 < j0;
+        const uint32_t mm = kc + 32 < j0 ? 0u : kOOB;
 #pragma unroll
         for (int h = 0; h < NH; ++h)
 #pragma unroll
-          for (int s = 0; s < 8; ++s) nb[h][s] = sel_load(Rc[h], kc + 32 + 4 * s, more && okc[h]);
+          for (int s = 0; s < 8; ++s)
+            nb[h][s] = buf_f64(rb_, (rco[h] + (uint32_t)(kc + 32 + 4 * s) * 8u) | rcm[h] | mm);
 #pragma unroll
         for (int s = 0; s < 8; ++s) {
           const int kr = kc + 4 * s + li;
