@@ -163,13 +163,18 @@ __global__ __launch_bounds__(NT) void gram_split_kernel(const double* __restrict
   // thread: column lc = t / 4 (0..63), k = (t % 4) * 8 .. +7
   const int lq = t % 4, lc = t / 4;
   double rx[8], ry[8];
+  // blocks I and J through buffer resources based at the block; branch-free loads masked with kOOB
+  // past r1 or n, so that the next K step's loads overlap this step's products
+  const bufrsrc bx = make_buf(X + (int64_t)I0 * ldx, ((int64_t)(min(TB, n - I0) - 1) * ldx + m) * 8);
+  const bufrsrc by = make_buf(Y + (int64_t)J0 * ldy, ((int64_t)(min(TB, n - J0) - 1) * ldy + m) * 8);
   auto load = [&](int k0) {
-    const int cx = I0 + lc, cy = J0 + lc;
+    const uint32_t cmx = I0 + lc < n ? 0u : kOOB, cmy = J0 + lc < n ? 0u : kOOB;
 #pragma unroll
     for (int e = 0; e < 8; ++e) {
       const int k = k0 + lq * 8 + e;
-      rx[e] = sel_load(X, (int64_t)cx * ldx + k, k < r1 && cx < n);
-      ry[e] = sel_load(Y, (int64_t)cy * ldy + k, k < r1 && cy < n);
+      const uint32_t km = k < r1 ? 0u : kOOB;
+      rx[e] = buf_f64(bx, ((uint32_t)((int64_t)lc * ldx + k) * 8u) | cmx | km);
+      ry[e] = buf_f64(by, ((uint32_t)((int64_t)lc * ldy + k) * 8u) | cmy | km);
     }
   };
   auto store = [&]() {
@@ -191,7 +196,7 @@ __global__ __launch_bounds__(NT) void gram_split_kernel(const double* __restrict
   int since = 0;
   for (int k0 = r0; k0 < r1; k0 += BKS) {
     const bool more = k0 + BKS < r1;
-    if (more) load(k0 + BKS);
+    load(k0 + BKS);                       // past r1: zeros, never stored
     const int kb = 8 * (lane >> 4);
     bf16x8 a[S], b[S][4];
 #pragma unroll
