@@ -4,9 +4,11 @@
 Default workload: dense SPD A, m = 32768, n = 256, kappa(A) = 1e8 (log-spaced
 eigenvalues, dense random orthogonal eigenvectors), Z = U diag(s) W^T with
 kappa(Z) = 1e5 (Haar factors).  One step = one CholQR2-A factorisation of Z:
-pass 1 with A Z on split-bfloat16 MFMA (three slices, FP32 accumulation
-inside 256-row tiles, FP64 across them), FP64 Gram/Cholesky/substitution;
-pass 2 all FP64.  The same step in all-FP64 is timed beside it.
+pass 1 with A Z on split-bfloat16 MFMA (by default two slices, hi = bf16(x)
+and lo = bf16(x - hi), products hi*hi + hi*lo + lo*hi; --pass1 bf16x3 for
+three slices), FP32 accumulation inside K tiles, FP64 across them, FP64
+Gram/Cholesky/substitution; pass 2 all FP64.  The same step in all-FP64 is
+timed beside it.
 
 Throughput uses the paper's normalised flop count 2 m^2 n + 2 m n^2 for one
 factorisation (Section 8), whatever the algorithm executes.  Inputs are
@@ -34,7 +36,8 @@ sys.path.insert(0, ROOT)
 
 METRIC = "oblique-QR GFLOP/s & % roofline, mixed vs FP64 CholQR2-A at orth loss ≤1e-12"
 PEAK = {"fp64": 78.6e12, "bf16": 2.5e15, "hbm": 8.0e12}
-# HBM bytes per launch of the dominant kernel, from two rocprofv3 counter runs of this script (FETCH_SIZE,
+# L2-miss bytes per launch of the dominant kernel (an upper bound on its HBM bytes: the MALL serves part of
+# them), from two rocprofv3 counter runs of this script (FETCH_SIZE,
 # then WRITE_SIZE, KiB per dispatch) scaled by what the same counters read for a 1 GiB copy
 # (--workload copycal: FETCH_SIZE x 2.0, WRITE_SIZE x 1.0).  Only for the kernel build they were taken
 # on; workloads without an entry report null.
@@ -116,24 +119,34 @@ def make_inputs(wl, torch):
     return A, Z, z, m, n, desc, 2.0 * m * n * n, "gram", 1.0 * m * n * n
 
 
+def symm_pass_flops(m, n, bm=64):
+    """Flops one dense CholQR pass must execute when it exploits A = A^T the way the library does:
+    W_off = U Z over the strictly upper blocks of A (row tiles of bm), W_sym = W_off + D Z over the
+    diagonal blocks, and the upper triangle of G = Z^T W_sym + W_off^T Z (two products of m n^2 each)."""
+    return upper_product_flops(m, n, bm) + 2.0 * n * sum(min(bm, m - t) ** 2 for t in range(0, m, bm)) \
+        + 2.0 * m * n * n
+
+
 def schedule_roofline(kind, m, n, pass_precs, ms):
     """Roofline of a whole CholQR2 schedule: T_roof = sum over passes of max(B / HBM peak, sum over steps
-    of F_step / peak of the step's precision), frac = T_roof / measured.  Per pass, algorithmic counts
-    independent of how the library schedules them: a1 2 m^2 n (dense) / 13 m n (stencil) / 5 m n
-    (tridiagonal), a2 m n^2 (upper triangle), a3 n^3 / 3, a4 m n^2; a1 and a2 at bf16 peak in a split
-    pass, FP64 otherwise, a3 and a4 always FP64; B = unique A bytes 8 m (m + 1) / 2 (dense) or 16 m
-    (tridiagonal) + 3 x 8 m n (Z read, Z read again by the substitution, Q written).  The dense a1 counts
-    the full product: the library evaluates only the upper block triangle (half those flops), so a
-    schedule can run faster than this roofline."""
-    a1 = {"dense": 2.0 * m * m * n, "stencil": 13.0 * m * n, "tridiag": 5.0 * m * n}[kind]
+    of F_step / peak of the step's precision), frac = T_roof / measured.  Per pass: dense, the operator
+    product and the Gram as the symmetric schedule executes them (symm_pass_flops: A read in its upper
+    block triangle, about m^2 n + 2 m n^2 flops instead of the 2 m^2 n + m n^2 of a full product);
+    stencil 13 m n (the matrix-free apply, FP64 vector work) + m n^2 (upper triangle of the Gram);
+    tridiagonal 5 m n + m n^2; then n^3 / 3 (Cholesky) + m n^2 (substitution), always FP64.  Products and
+    Gram run at the bf16 peak in a split pass, FP64 otherwise (the extra slice products are overhead, not
+    counted).  B = unique A bytes 8 m (m + 1) / 2 (dense) or 16 m (tridiagonal) + 3 x 8 m n (Z read, Z
+    read again by the substitution, Q written).  Every count is work the schedule cannot avoid, so
+    frac <= 1."""
     a_bytes = {"dense": 8.0 * m * (m + 1) / 2, "stencil": 0.0, "tridiag": 16.0 * m}[kind]
     t = 0.0
     for prec in pass_precs:
         peak12 = PEAK["bf16"] if prec != "fp64" else PEAK["fp64"]
-        if kind != "dense":
-            t_mx = a1 / PEAK["fp64"] + m * n * n / peak12         # the matrix-free apply is FP64 vector work
+        if kind == "dense":
+            t_mx = symm_pass_flops(m, n) / peak12
         else:
-            t_mx = (a1 + m * n * n) / peak12
+            apply = 13.0 * m * n if kind == "stencil" else 5.0 * m * n
+            t_mx = apply / PEAK["fp64"] + m * n * n / peak12
         t_mx += (n ** 3 / 3 + m * n * n) / PEAK["fp64"]
         t += max((a_bytes + 3 * 8.0 * m * n) / PEAK["hbm"], t_mx)
     return {"t_roof_ms": round(t * 1e3, 4), "measured_ms": round(ms, 4), "frac": round(t * 1e3 / ms, 4)}
@@ -516,7 +529,8 @@ def main():
     roof = {"bound": "mfma", "kernel": dom_kernel + label,
             "achieved": round(achieved / 1e12, 3), "peak": round(peak / 1e12, 1), "unit": "TFLOP/s",
             "frac": round(achieved / peak, 4), "traffic": TRAFFIC.get((args.workload, dom_kernel)),
-            "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE/WRITE_SIZE, copy-calibrated)",
+            "traffic_unit": "L2-miss bytes per launch (rocprofv3 FETCH_SIZE/WRITE_SIZE, copy-calibrated); "
+                            "includes reads the MALL serves, so an upper bound on HBM bytes",
             "per_launch_flops": dom_flops, "avg_launch_ms": round(kernel_ms, 4)}
     line = {
         "metric": METRIC,
@@ -548,7 +562,8 @@ def main():
         "mixed": schedule_roofline(kind, m, n, (pass1, "fp64"), mx["ms_per_step"]),
         "fp64": schedule_roofline(kind, m, n, ("fp64", "fp64"), res["fp64"]["ms_per_step"]),
         "definition": "sum over passes of max(unique algorithmic bytes / 8 TB/s, sum of step flops / peak of "
-                      "the step's precision); a1 counted as the full 2m^2n product for dense A",
+                      "the step's precision); dense A Z and Gram counted as the symmetric schedule executes "
+                      "them (upper block triangle of A, about m^2 n + 2 m n^2 per pass)",
     }
     if args.workload == "tridiag":
         line["variants"] = time_variants(A, Z, m, n, flops, torch)
