@@ -63,13 +63,34 @@ def matmul(a: np.ndarray, b: np.ndarray, scheme: str, kt: int = 256) -> np.ndarr
     return out
 
 
-def gram(a, z: np.ndarray, scheme: str, kt: int = 256) -> np.ndarray:
+def gram(a, z: np.ndarray, scheme: str, kt: int = 256, symmetric_blocks=None) -> np.ndarray:
     """G = Z^T (A Z): dense A -> reduced-precision A Z, FP64 Z^T W;
-    stencil A -> exact FP64 stencil, reduced-precision Z^T W."""
+    stencil A -> exact FP64 stencil, reduced-precision Z^T W.
+
+    symmetric_blocks = b (dense A only): the reading of steps 1-2 of Algorithm 1
+    for a symmetric A that touches only A's upper block triangle.  With the
+    rows cut into blocks of b, U holds the blocks strictly right of the
+    diagonal and D the diagonal blocks (A = U + D + U^T):
+        W_off = U Z (reduced precision),  W_sym = W_off + D Z (FP64),
+        G = Z^T W_sym + W_off^T Z (FP64),
+    which is Z^T A Z in exact arithmetic.  The rounding of the reduced-precision
+    product then enters G as Z^T E + E^T Z, a symmetric perturbation."""
     if hasattr(a, "nx"):
         from . import stencil
         w = stencil.apply(a, z)
         return matmul(np.ascontiguousarray(z.T), w, scheme, kt)
+    if symmetric_blocks:
+        b = int(symmetric_blocks)
+        m = a.shape[0]
+        d = np.zeros_like(a)
+        u = np.zeros_like(a)
+        for t0 in range(0, m, b):
+            t1 = min(m, t0 + b)
+            d[t0:t1, t0:t1] = a[t0:t1, t0:t1]
+            u[t0:t1, t1:] = a[t0:t1, t1:]
+        w_off = matmul(u, z, scheme, kt)
+        w_sym = w_off + d @ z
+        return z.T @ w_sym + w_off.T @ z
     w = matmul(a, z, scheme, kt)
     return z.T @ w
 
@@ -79,15 +100,16 @@ def shift_for(g: np.ndarray, scheme: str, c: float) -> float:
     return c * UNIT[scheme] * float(np.max(np.diag(g)))
 
 
-def cholqr_pass(a, z: np.ndarray, scheme: str, shift_c: float = 1.0, max_retries: int = 3, kt: int = 256):
+def cholqr_pass(a, z: np.ndarray, scheme: str, shift_c: float = 1.0, max_retries: int = 3, kt: int = 256,
+                symmetric_blocks=None):
     """One CHOLQR pass with a reduced-precision product, FP64 Cholesky with the
     shift-and-retry rule, FP64 substitution for Q.  A reduced-precision pass
     starts with s = shift_c u_p max diag(G); an FP64 pass starts unshifted and
     retries with shift_c u max diag(G); each further retry multiplies the
-    constant by 10.
+    constant by 10.  symmetric_blocks: see gram.
 
     Returns (Q, R, info, shift_used)."""
-    g = gram(a, z, scheme, kt)
+    g = gram(a, z, scheme, kt, symmetric_blocks)
     g = np.triu(g) + np.triu(g, 1).T          # the library reads the upper triangle
     c = shift_c if scheme != "fp64" else 0.0
     for attempt in range(max_retries + 1):
@@ -99,11 +121,12 @@ def cholqr_pass(a, z: np.ndarray, scheme: str, shift_c: float = 1.0, max_retries
     return None, r, info, s
 
 
-def cholqr2(a, z: np.ndarray, scheme1: str, scheme2: str = "fp64", shift_c: float = 1.0, kt: int = 256):
-    q1, r1, info, s1 = cholqr_pass(a, z, scheme1, shift_c, kt=kt)
+def cholqr2(a, z: np.ndarray, scheme1: str, scheme2: str = "fp64", shift_c: float = 1.0, kt: int = 256,
+            max_retries: int = 3, symmetric_blocks=None):
+    q1, r1, info, s1 = cholqr_pass(a, z, scheme1, shift_c, max_retries, kt, symmetric_blocks)
     if info:
         return None, None, info
-    q, r2, info, _ = cholqr_pass(a, q1, scheme2, shift_c, kt=kt)
+    q, r2, info, _ = cholqr_pass(a, q1, scheme2, shift_c, max_retries, kt, symmetric_blocks)
     if info:
         return None, None, info
     return q, np.triu(r2 @ r1), 0

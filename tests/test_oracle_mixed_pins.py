@@ -313,6 +313,60 @@ def test_stencil_gram_is_split_zt_times_fp64_stencil():
     assert within_fp32_tile_bound(g, np.ascontiguousarray(z.T), w, 3, 256)
 
 
+# ---- the symmetric formation (dense A read in its upper block triangle) ---------------------------
+
+def _int_case(m=10, n=3, seed=21):
+    """Small integers (bf16-exact, every sum exact in FP32 and FP64): both formations give Z^T A Z."""
+    rng = np.random.default_rng(seed)
+    b = rng.integers(-4, 5, (m, m)).astype(np.float64)
+    a = b + b.T + np.diag(np.full(m, 20.0))
+    z = rng.integers(-3, 4, (m, n)).astype(np.float64)
+    return a, z
+
+
+@pytest.mark.parametrize("blocks", [1, 3, 4, 10, 64])
+def test_symmetric_formation_is_zt_a_z_on_exact_inputs(blocks):
+    """Ragged and single blocks: W_sym = (U + D) Z and W_off^T Z add up to Z^T A Z exactly."""
+    a, z = _int_case()
+    want = (z.T @ a @ z).astype(np.int64)
+    for scheme in ("fp64", "bf16x2", "bf16x3"):
+        g = mixed.gram(a, z, scheme, symmetric_blocks=blocks)
+        assert np.array_equal(g, want), (scheme, blocks)
+
+
+def test_symmetric_formation_mutant_without_the_transposed_term_fails():
+    a, z = _int_case()
+    m = a.shape[0]
+    u = np.triu(a, 4)                        # blocks of 4: everything right of the diagonal blocks
+    for t0 in range(0, m, 4):
+        u[t0:t0 + 4, t0:min(m, t0 + 4)] = 0.0
+    d = a - u - u.T
+    mutant = z.T @ (u @ z + d @ z)           # W_off^T Z forgotten
+    assert not np.array_equal(mutant, z.T @ a @ z)
+
+
+def test_symmetric_formation_diagonal_blocks_are_fp64():
+    """A = x I with x = 1 + 3 2^-10 (hi = 1, lo = 3 2^-10) and Z = x I: one diagonal block, so
+    G = x^3 exactly (31 bits); a split product of the diagonal block would drop lo * lo = 9 2^-20."""
+    x = 1 + 3 * 2.0 ** -10
+    a, z = x * np.eye(4), x * np.eye(4)
+    g = mixed.gram(a, z, "bf16x2", symmetric_blocks=4)
+    assert np.array_equal(g, x ** 3 * np.eye(4))
+    assert not np.array_equal(mixed.gram(a, z, "bf16x2"), x ** 3 * np.eye(4))   # the full split product
+
+
+def test_symmetric_formation_off_diagonal_blocks_are_split():
+    """m = 2, blocks of 1: G_12 = z * split(x * z) with the lo * lo product dropped (bf16x2)."""
+    x, zz = 0.5 * (1 + 3 * 2.0 ** -10), 1 + 5 * 2.0 ** -10
+    a = np.array([[1.0, x], [x, 1.0]])
+    z = zz * np.eye(2)
+    g = mixed.gram(a, z, "bf16x2", symmetric_blocks=1)
+    sx, sz = exact_slices(x, 2), exact_slices(zz, 2)
+    kept = sx[0] * sz[0] + sx[0] * sz[1] + sx[1] * sz[0]
+    assert Fraction(float(g[0, 1])) == Fraction(zz) * kept
+    assert Fraction(float(g[0, 1])) != Fraction(zz) * Fraction(x) * Fraction(zz)
+
+
 # ---- the shift rule --------------------------------------------------------------------------
 
 def _gram_needing(delta):
@@ -330,7 +384,7 @@ def _gram_needing(delta):
 ])
 def test_shift_sequence(monkeypatch, scheme, delta, attempt):
     g = _gram_needing(delta)
-    monkeypatch.setattr(mixed, "gram", lambda a, z, s, kt=256: g.copy())
+    monkeypatch.setattr(mixed, "gram", lambda a, z, s, kt=256, sb=None: g.copy())
     z = np.eye(2)
     q, r, info, s = mixed.cholqr_pass(None, z, scheme, shift_c=1.0, max_retries=4)
     u = 2.0 ** -24 if scheme != "fp64" else 2.0 ** -53
@@ -343,7 +397,7 @@ def test_shift_sequence(monkeypatch, scheme, delta, attempt):
 
 def test_shift_failure_reports_pivot(monkeypatch):
     g = np.array([[1.0, 0.0], [0.0, -1.0]])
-    monkeypatch.setattr(mixed, "gram", lambda a, z, s, kt=256: g.copy())
+    monkeypatch.setattr(mixed, "gram", lambda a, z, s, kt=256, sb=None: g.copy())
     q, r, info, s = mixed.cholqr_pass(None, np.eye(2), "bf16x2", shift_c=1.0, max_retries=3)
     assert q is None and info == 2 and s == 1e3 * 2.0 ** -24
 
@@ -370,6 +424,6 @@ def test_shift_mutants_fail(monkeypatch):
     assert _mutant_cholqr_pass(g, "bf16x2", factor=2.0) != 100 * 2.0 ** -24
     g = np.array([[1.0, 0.5], [0.5, 1.0]])
     assert _mutant_cholqr_pass(g, "fp64", fp64_starts_shifted=True) != 0.0
-    monkeypatch.setattr(mixed, "gram", lambda a, z, s, kt=256: g.copy())
+    monkeypatch.setattr(mixed, "gram", lambda a, z, s, kt=256, sb=None: g.copy())
     assert mixed.cholqr_pass(None, np.eye(2), "fp64")[3] == 0.0
     assert mixed.cholqr_pass(None, np.eye(2), "bf16x2")[3] == 2.0 ** -24
