@@ -50,8 +50,9 @@ typedef enum {
   OQR_E_NOT_SPD = 2,      /* reserved: numerical failure is reported in info_dev */
   OQR_E_HIP = 3,          /* a HIP launch or runtime call failed */
   OQR_E_WORKSPACE = 4,    /* workspace too small or misaligned */
-  OQR_E_UNSUPPORTED = 5   /* valid request the library does not implement (n or a leading
+  OQR_E_UNSUPPORTED = 5,  /* valid request the library does not implement (n or a leading
                              dimension beyond the limits below OQR_MAX_N) */
+  OQR_E_SCRATCH = 6       /* oqr_cholqr2_noalloc: the request needs more than its fixed scratch */
 } oqr_status;
 
 /* Storage type of A, Z, Q and R. */
@@ -165,6 +166,29 @@ int oqr_cholqr(const oqr_op* A, const double* Z, int64_t ldz, int64_t m, int64_t
 int oqr_cholqr2(const oqr_op* A, const double* Z, int64_t ldz, int64_t m, int64_t n,
                 double* Q, int64_t ldq, double* R, int64_t ldr, const oqr_opts* opts,
                 void* ws, size_t ws_bytes, int32_t* info_dev, void* stream);
+
+/* Allocation-free CholQR2-A, for callers that cannot allocate device memory
+ * or pass a workspace (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc).  Same arguments, kernels, results (bit
+ * for bit) and info_dev convention as oqr_cholqr2, without ws / ws_bytes:
+ * the scratch is a device array of OQR_NOALLOC_SCRATCH_BYTES owned by the
+ * library, one per device, held from the first use on that device until the
+ * process ends.  The first call on a device looks up the array's device
+ * address (hipGetSymbolAddress, with that device current) and keeps it; make
+ * that first call outside any graph capture.  No call allocates (no hipMalloc,
+ * no hipFree, no allocating library routine); the caller still passes Z, Q,
+ * R and info_dev.
+ * Limits: a request whose oqr_cholqr2 workspace (oqr_workspace_bytes with
+ * OQR_ALG_CHOLQR2) exceeds OQR_NOALLOC_SCRATCH_BYTES returns OQR_E_SCRATCH
+ * before anything is enqueued.  Every call on one device shares that device's
+ * scratch, which keeps the last call's contents (nothing in it needs to start
+ * at zero): calls that overlap on one device (two streams, two host threads)
+ * race and give undefined results; calls on one stream are ordered and safe. */
+#define OQR_NOALLOC_SCRATCH_BYTES ((size_t)64 << 20)
+size_t oqr_noalloc_scratch_bytes(void);
+int oqr_cholqr2_noalloc(const oqr_op* A, const double* Z, int64_t ldz, int64_t m, int64_t n,
+                        double* Q, int64_t ldq, double* R, int64_t ldr, const oqr_opts* opts,
+                        int32_t* info_dev, void* stream);
 
 /* PRE-CHOLQR-A (Algorithm 2, Section 3): Householder QR of Z in the Euclidean
  * product, Z = Y U (Y orthonormal, diag(U) > 0), then CHOLQR-A on Y in FP64,

@@ -22,7 +22,7 @@ from typing import Optional, Tuple
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "liboqr.so")
 
-OQR_OK, OQR_E_ARG, OQR_E_NOT_SPD, OQR_E_HIP, OQR_E_WORKSPACE, OQR_E_UNSUPPORTED = range(6)
+OQR_OK, OQR_E_ARG, OQR_E_NOT_SPD, OQR_E_HIP, OQR_E_WORKSPACE, OQR_E_UNSUPPORTED, OQR_E_SCRATCH = range(7)
 OQR_F64, OQR_F32 = 0, 1
 OQR_BATCH_BAD_ITEM = -1          # info of a batch item outside the entry point's limits
 OQR_OP_DENSE, OQR_OP_STENCIL7, OQR_OP_TRIDIAG = 0, 1, 2
@@ -35,6 +35,7 @@ EXPORTS = (
     "oqr_default_opts", "oqr_workspace_bytes", "oqr_cholqr", "oqr_cholqr2", "oqr_pre_cholqr", "oqr_chol_a", "oqr_eig_a",
     "oqr_gs", "oqr_check", "oqr_batched_workspace_bytes", "oqr_cholqr2_batched", "oqr_batched_tile_count",
     "oqr_status_string", "oqr_version", "oqr_trace_start", "oqr_trace_stop", "oqr_gls", "oqr_gls_workspace_bytes",
+    "oqr_cholqr2_noalloc", "oqr_noalloc_scratch_bytes",
 )
 
 
@@ -78,6 +79,9 @@ def lib():
             f = getattr(L, name)
             f.argtypes = sig
             f.restype = ctypes.c_int
+        L.oqr_cholqr2_noalloc.argtypes = sig[:10] + [vp, vp]
+        L.oqr_cholqr2_noalloc.restype = ctypes.c_int
+        L.oqr_noalloc_scratch_bytes.restype = sz
         L.oqr_workspace_bytes.argtypes = [i32, ctypes.POINTER(_Op), i64, i64, ctypes.POINTER(_Opts)]
         L.oqr_workspace_bytes.restype = sz
         L.oqr_gls.argtypes = [ctypes.POINTER(_Op), vp, i64, vp, i64, i64, i64, vp, i64, i64, vp, i64, vp, sz, vp]
@@ -379,6 +383,42 @@ def cholqr(A, Z, prec="fp64", shift_c=1.0, max_retries=3):
 def cholqr2(A, Z, pass1="fp64", pass2="fp64", shift_c=1.0, max_retries=3):
     """CholQR2-A (CHOLQR-A twice, R = R2 R1): returns (Q, R)."""
     return _run("cholqr2", A, Z, pass1=pass1, pass2=pass2, shift_c=shift_c, max_retries=max_retries)
+
+
+def noalloc_scratch_bytes() -> int:
+    """Size of the library's fixed scratch used by cholqr2_noalloc (per device)."""
+    return int(lib().oqr_noalloc_scratch_bytes())
+
+
+def cholqr2_noalloc_into(A, Z, Q, R, info, pass1="fp64", pass2="fp64", shift_c=1.0, max_retries=3, stream=None):
+    """oqr_cholqr2_noalloc on caller-owned column-major Z, Q (may be Z), R and a 1-element int32
+    `info`: enqueues CholQR2-A on the library's own scratch and allocates nothing (graph-capturable
+    after a first call on the device).  Raises OQRError on a host status; `info` is left on the device."""
+    torch = _torch()
+    op, m = make_op(A)
+    n = Z.shape[1]
+    if Z.shape[0] != m or Q.shape != (m, n) or R.shape != (n, n):
+        raise ValueError("shapes of A, Z, Q and R do not match")
+    opts = make_opts(pass1=pass1, pass2=pass2, shift_c=shift_c, max_retries=max_retries)
+    s = stream if stream is not None else torch.cuda.current_stream(Z.device).cuda_stream
+    rc = lib().oqr_cholqr2_noalloc(ctypes.byref(op), Z.data_ptr(), _ld(Z), m, n, Q.data_ptr(), _ld(Q), R.data_ptr(),
+                                   _ld(R), ctypes.byref(opts), info.data_ptr(), s)
+    _raise(rc, "oqr_cholqr2_noalloc")
+
+
+def cholqr2_noalloc(A, Z, pass1="fp64", pass2="fp64", shift_c=1.0, max_retries=3):
+    """CholQR2-A through the allocation-free entry point (outputs allocated here): returns (Q, R)."""
+    torch = _torch()
+    Z = colmajor(Z)
+    m, n = Z.shape
+    Q = torch.empty(n, m, dtype=torch.float64, device=Z.device).t()
+    R = torch.empty(n, n, dtype=torch.float64, device=Z.device).t()
+    info = torch.zeros(1, dtype=torch.int32, device=Z.device)
+    cholqr2_noalloc_into(A, Z, Q, R, info, pass1, pass2, shift_c, max_retries)
+    k = int(info.item())
+    if k != 0:
+        raise OQRError(f"oqr_cholqr2_noalloc: numerical failure, info = {k}", info=k)
+    return Q, R
 
 
 def pre_cholqr(A, Z, prec="fp64", shift_c=1.0, max_retries=3):

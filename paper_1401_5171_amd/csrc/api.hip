@@ -4,9 +4,15 @@
 #include <math.h>
 #include <string.h>
 
+#include <mutex>
 #include <vector>
 
 #include "common.hpp"
+
+// Scratch of oqr_cholqr2_noalloc: every device holds its own copy, at its own address, from the load
+// of the library's code object until the process ends.  Host code never passes this name to a kernel
+// (on the host it is only a handle); it uses the device address looked up by noalloc_scratch().
+static __device__ __align__(256) unsigned char scratch[OQR_NOALLOC_SCRATCH_BYTES];
 
 namespace oqr {
 
@@ -279,6 +285,26 @@ int ws_check(void* ws, size_t ws_bytes, size_t need) {
   return OQR_OK;
 }
 
+// Device address of `scratch` on the current device, looked up once per device (with that device
+// current) and kept.
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_dev[kMaxDevices] = {};
+
+int noalloc_scratch(void** out) {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return OQR_E_HIP;
+  if (dev < 0 || dev >= kMaxDevices) return OQR_E_UNSUPPORTED;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_dev[dev]) {
+    void* p = nullptr;
+    if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) return OQR_E_HIP;
+    g_scratch_dev[dev] = p;
+  }
+  *out = g_scratch_dev[dev];
+  return OQR_OK;
+}
+
 }  // namespace
 }  // namespace oqr
 
@@ -331,6 +357,9 @@ const char* oqr_status_string(int status) {
     case OQR_E_HIP: return "OQR_E_HIP: a HIP launch or runtime call failed";
     case OQR_E_WORKSPACE: return "OQR_E_WORKSPACE: workspace too small or not 256-byte aligned";
     case OQR_E_UNSUPPORTED: return "OQR_E_UNSUPPORTED: request not implemented by the library";
+    case OQR_E_SCRATCH:
+      return "OQR_E_SCRATCH: the request needs more scratch than the fixed OQR_NOALLOC_SCRATCH_BYTES of "
+             "oqr_cholqr2_noalloc (use oqr_cholqr2 with a workspace)";
     default: return "unknown oqr status";
   }
 }
@@ -418,6 +447,21 @@ int oqr_cholqr2(const oqr_op* A, const double* Z, int64_t ldz, int64_t m, int64_
   if ((rc = cholqr_pass(A, q1, ldq1, m, n, Q, ldq, w.R2, n, o.pass2, o, w, w.shifts + 1, info_dev, s))) return rc;
   if (launch_trmm_upper(w.R2, n, w.R1, n, R, ldr, n, info_dev, s) != hipSuccess) return OQR_E_HIP;
   return OQR_OK;
+}
+
+size_t oqr_noalloc_scratch_bytes(void) { return OQR_NOALLOC_SCRATCH_BYTES; }
+
+int oqr_cholqr2_noalloc(const oqr_op* A, const double* Z, int64_t ldz, int64_t m, int64_t n, double* Q, int64_t ldq,
+                        double* R, int64_t ldr, const oqr_opts* opts, int32_t* info_dev, void* stream) {
+  int rc = check_common(A, Z, ldz, m, n, Q, ldq, R, ldr, info_dev);
+  if (rc) return rc;
+  oqr_opts o;
+  if ((rc = resolve_opts(opts, &o))) return rc;
+  if (n > 0 && pass_ws(A, m, n, o, true, nullptr, nullptr) > OQR_NOALLOC_SCRATCH_BYTES) return OQR_E_SCRATCH;
+  void* ws = nullptr;
+  if (n > 0 && (rc = noalloc_scratch(&ws))) return rc;
+  // the same kernel sequence as oqr_cholqr2, on the library's scratch instead of a caller's workspace
+  return oqr_cholqr2(A, Z, ldz, m, n, Q, ldq, R, ldr, opts, ws, OQR_NOALLOC_SCRATCH_BYTES, info_dev, stream);
 }
 
 int oqr_gs(const oqr_op* A, const double* Z, int64_t ldz, int64_t m, int64_t n, double* Q, int64_t ldq, double* R,

@@ -45,7 +45,7 @@ def test_every_declared_symbol_is_exported(L):
 
 
 def test_status_strings(L):
-    for code in range(6):
+    for code in range(7):
         assert oqr.status_string(code).startswith("OQR_")
     assert "unknown" in oqr.status_string(99)
     assert L.oqr_version() >= 100
@@ -84,6 +84,21 @@ def test_argument_errors_before_any_launch(L, fn):
     # overlapping Q and Z that are not the same matrix
     assert f(ctypes.byref(op), fake, 10, 10, 4, fake + 8, 10, fake * 3, 4, None, fake * 4, 1 << 20, fake * 5,
              None) == oqr.OQR_E_ARG
+
+
+def test_noalloc_host_checks_before_any_launch(L):
+    """oqr_cholqr2_noalloc: argument errors, and a request beyond its fixed scratch, are refused on the
+    host before the scratch is looked up or anything is enqueued."""
+    f = L.oqr_cholqr2_noalloc
+    fake = 0x10000
+    op = _dense_op(10)
+    assert f(ctypes.byref(op), fake, 10, 4, 5, fake * 2, 10, fake * 3, 5, None, fake * 5, None) == oqr.OQR_E_ARG
+    assert f(ctypes.byref(op), fake, 10, 10, 4, fake * 2, 10, fake * 3, 4, None, None, None) == oqr.OQR_E_ARG
+    m, n = 30000, 256                      # W and A W of this shape alone exceed the scratch
+    op2 = _dense_op(m)
+    assert 2 * 8 * m * n > L.oqr_noalloc_scratch_bytes() == 64 << 20
+    big = 1 << 40
+    assert f(ctypes.byref(op2), big, m, m, n, 2 * big, m, 3 * big, n, None, 4 * big, None) == oqr.OQR_E_SCRATCH
 
 
 def test_offset_reach_limits(L):
