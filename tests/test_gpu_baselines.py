@@ -154,16 +154,6 @@ def test_chol_a_ragged(m, n):
     assert metrics.r_forward_error(r, r0) <= chol_eqr_tol(a, r0, n)
 
 
-def test_chol_a_config2_shape():
-    """m=8192, n=64, kappa(A)=1e6, kappa(Z)=1e4 (the second workload's shape)."""
-    a, z = dense_case(2, 8192, 64, 1e6, 1e4)
-    q0, r0 = reference.chol_eqr(a, z)
-    banner("chol_a m=8192 n=64")
-    q, r = gpu("chol_a", to_dev(a), z)
-    common_checks(a, z, q, r, q0, r0)
-    assert metrics.r_forward_error(r, r0) <= chol_eqr_tol(a, r0, 64)
-
-
 def test_chol_a_reports_first_failing_pivot():
     m, n = 150, 4
     rng = W.rng_for(66)

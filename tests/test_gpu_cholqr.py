@@ -79,19 +79,6 @@ def test_config2_shape_kappa_sweep(kz):
     assert metrics.r_forward_error(r, r0) <= 10 * 64 * U * np.linalg.cond(r0)
 
 
-@pytest.mark.parametrize("pass1", ["fp64", "bf16x3"])
-def test_config2_full_size(pass1):
-    """m = 8192, n = 64, kappa(A) = 1e6, kappa(Z) = 1e4 (butterfly eigenvectors): the dense products
-    split K over workgroups at this shape."""
-    a, z = dense_case(2, 8192, 64, 1e6, 1e4, seed=7, kind="butterfly")
-    q0, r0 = reference.chol_eqr(a, z)
-    banner(f"config2 full size pass1={pass1}")
-    q, r = run_dense("cholqr2", a, z, pass1=pass1)
-    assert metrics.residual_f(z, q, r) <= 1e-12
-    assert metrics.orth_loss(a, q) <= 1e-12
-    assert metrics.r_forward_error(r, r0) <= 10 * 64 * U * np.linalg.cond(r0)
-
-
 @pytest.mark.parametrize("m,n", [(1, 1), (7, 3), (65, 65), (130, 1), (1000, 37), (777, 100), (1531, 129), (600, 256),
                                  (3000, 50), (5003, 130)])
 def test_ragged_shapes(m, n):

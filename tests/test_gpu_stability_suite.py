@@ -1,5 +1,8 @@
-"""The stability study of Section 7 run through every GPU variant: test Cases 1-5 at m = 80, n = 10,
-kappa(A) swept 1e1 .. 1e15 with kappa(Z) = kappa(A)^{1/2} (the paper's setting).
+"""The stability study of Section 7 run through every GPU variant: test Cases 1-5 at the paper's size
+(m = 80, n = 10, kappa(A) swept 1e1 .. 1e15) and scaled up (m = 2048, n = 64, kappa(A) 1e1 .. 1e13),
+with kappa(Z) = kappa(A)^{1/2} (the paper's setting).  Besides the paper's variants the suite runs the
+library's mixed schedule: CholQR2-A with a bf16x2 (hi/lo split) first pass, its shift and retries, and
+an FP64 second pass, against the CPU emulation of the same schedule (`oracle.mixed.cholqr2`).
 
 For each (case, kappa, variant) the GPU result is compared with the oracle's FP64 run of the same
 algorithm on the same inputs: where the oracle completes with a loss of orthogonality below 1e-2,
@@ -12,7 +15,8 @@ edge, where Theorem 2.1's bound on the loss of CHOLQR-A (without its constant c 
 u ||R^-1|| ||Z|| (||R^-1|| ||A Z|| + ||Q|| ||A||), or u kappa(A) exceeds 1e-3, or the oracle's loss
 exceeds 1e-6: there the rounding of the Gram is within three orders of its smallest eigenvalue and the
 breakdown point moves with the order of summation (in Case 1, Z in the span of A's smallest
-eigenvectors, the bound is about u kappa(R)^2 kappa(A)).
+eigenvectors, the bound is about u kappa(R)^2 kappa(A)).  For the mixed schedule u in that bound is
+2^-16, the precision of the two-slice products.
 The scaling laws themselves are pinned on the CPU (test_oracle_claims.py); this suite shows that the
 GPU variants follow the same laws.
 """
@@ -21,13 +25,15 @@ import pytest
 
 import workloads as W
 from gpu_util import banner, to_dev, to_dev_colmajor, to_host
-from oracle import metrics, reference, variants
+from oracle import metrics, mixed, reference, variants
 
 pytestmark = pytest.mark.gpu
 oqr = pytest.importorskip("paper_1401_5171_amd")
 
 M, N = 80, 10
 KAPPAS = [1e1, 1e3, 1e5, 1e7, 1e9, 1e11, 1e13, 1e15]
+M_SCALED, N_SCALED = 2048, 64
+KAPPAS_SCALED = [1e1, 1e4, 1e7, 1e10, 1e13]
 
 # The Cholesky-based variants are compared under the GPU's Gram convention: the factorisation
 # reads the upper triangle of C = Z^T (A Z), as the listing's chol(C) does.  In Case 1 (Z in the span
@@ -43,7 +49,15 @@ ORACLE = {
     "mgs_row": lambda a, z: variants.mgs_row(a, z),
     "mgs_col": lambda a, z: variants.mgs_col(a, z),
     "cgs2": lambda a, z: variants.cgs2(a, z),
+    "mixed": lambda a, z: _emulated_mixed(a, z),
 }
+
+
+def _emulated_mixed(a, z):
+    q, r, info = mixed.cholqr2(a, z, "bf16x2", "fp64", symmetric_blocks=64)
+    if info:
+        raise np.linalg.LinAlgError(f"emulated mixed CholQR2 broke down at pivot {info}")
+    return q, r
 
 
 U = 2.0 ** -53
@@ -59,22 +73,25 @@ BOUND = {
 }
 
 
-def theorem_bound(a, z, q0, r0):
+def theorem_bound(a, z, q0, r0, u=U):
     """Theorem 2.1 (Section 2), without the constant c m n:
     u ||R^-1|| ||Z|| (||R^-1|| ||A Z|| + ||Q|| ||A||)."""
     ri = np.linalg.norm(np.linalg.inv(r0), 2)
-    return U * ri * np.linalg.norm(z, 2) * (ri * np.linalg.norm(a @ z, 2)
+    return u * ri * np.linalg.norm(z, 2) * (ri * np.linalg.norm(a @ z, 2)
                                            + np.linalg.norm(q0, 2) * np.linalg.norm(a, 2))
 
 
-def gpu_run(name, A, Zd):
+def gpu_run(name, A, Zd, n=N):
     if name in ("cgs", "mgs_row", "mgs_col", "cgs2"):
-        plan = oqr.Plan("gs", A, N, gs_variant=name)
+        plan = oqr.Plan("gs", A, n, gs_variant=name)
     elif name in ("cholqr", "cholqr2", "pre_cholqr"):
         # the FP64 paths start unshifted; no retry so that breakdown shows as in the oracle
-        plan = oqr.Plan(name, A, N, max_retries=0)
+        plan = oqr.Plan(name, A, n, max_retries=0)
+    elif name == "mixed":
+        # the library's mixed schedule as shipped: shifted first attempt, retries on breakdown
+        plan = oqr.Plan("cholqr2", A, n, pass1="bf16x2", pass2="fp64")
     else:
-        plan = oqr.Plan(name, A, N)
+        plan = oqr.Plan(name, A, n)
     q, r = plan(Zd, check_info=False)
     return to_host(q), to_host(r), int(plan.info.item())
 
@@ -90,18 +107,17 @@ def oracle_run(name, a, z):
         return None
 
 
-@pytest.mark.parametrize("case", [1, 2, 3, 4, 5])
-def test_gpu_variants_follow_the_oracle(case):
-    banner(f"stability suite case {case}")
+def _run_suite(case, m, n, kappas, cfg, names):
     compared = 0
-    for ka in KAPPAS:
-        rng = W.rng_for(7, case, int(np.log10(ka)))
-        a, z, _, _ = W.paper_case(case, rng, M, N, ka, np.sqrt(ka))
+    for ka in kappas:
+        rng = W.rng_for(cfg, case, int(np.log10(ka)))
+        a, z, _, _ = W.paper_case(case, rng, m, n, ka, np.sqrt(ka))
         A, Zd = to_dev(a), to_dev_colmajor(z)
-        for name in ORACLE:
+        for name in names:
+            banner(f"stability m={m} case {case} kappa {ka:g} {name}")
             ref = oracle_run(name, a, z)
-            q, r, info = gpu_run(name, A, Zd)
-            what = f"case {case} kappa {ka:g} {name}"
+            q, r, info = gpu_run(name, A, Zd, n)
+            what = f"m {m} case {case} kappa {ka:g} {name}"
             if ref is None:
                 # the oracle broke down: the GPU reports it or also returns a useless factor
                 assert info != 0 or not np.all(np.isfinite(q)) or metrics.orth_loss(a, q) > 1e-6, what
@@ -114,18 +130,36 @@ def test_gpu_variants_follow_the_oracle(case):
             if info != 0:
                 # a breakdown only at the edge: the Gram's rounding near its smallest eigenvalue, or A
                 # itself near singular in FP64
-                assert theorem_bound(a, z, q0, r0) > 1e-3 or U * ka > 1e-3 or l0 > 1e-6, what
+                u_edge = 2.0 ** -16 if name == "mixed" else U
+                assert theorem_bound(a, z, q0, r0, u_edge) > 1e-3 or U * ka > 1e-3 or l0 > 1e-6, what
                 continue
             factor = 10 if l0 <= 1e-6 else 100   # rounding-dominated regime: wider band
             bar = factor * l0 + 1e-14
             if name in BOUND:
                 # unstable variants: any FP64 implementation lands within the theorem's expression
-                bar = max(bar, 10 * N * U * BOUND[name](kr))
+                bar = max(bar, 10 * n * U * BOUND[name](kr))
             assert metrics.orth_loss(a, q) <= bar, (what, metrics.orth_loss(a, q), l0)
             res0 = metrics.residual_f(z, q0, r0)
             assert metrics.residual_f(z, q, r) <= max(1e-12, 10 * res0), what
             compared += 1
-    assert compared >= 30
+    return compared
+
+
+@pytest.mark.parametrize("case", [1, 2, 3, 4, 5])
+def test_gpu_variants_follow_the_oracle(case):
+    banner(f"stability suite case {case}")
+    assert _run_suite(case, M, N, KAPPAS, 7, list(ORACLE)) >= 30
+
+
+@pytest.mark.parametrize("case", [1, 2, 3, 4, 5])
+def test_gpu_variants_follow_the_oracle_scaled_up(case):
+    """m = 2048, n = 64.  EQR-SYEV (a cyclic Jacobi eigensolver per call on the GPU) runs at the
+    smallest and largest kappa(A) only."""
+    banner(f"stability suite scaled up, case {case}")
+    names = [k for k in ORACLE if k != "eig_a"]
+    compared = _run_suite(case, M_SCALED, N_SCALED, KAPPAS_SCALED, 9, names)
+    compared += _run_suite(case, M_SCALED, N_SCALED, [KAPPAS_SCALED[0], KAPPAS_SCALED[-1]], 9, ["eig_a"])
+    assert compared >= 20
 
 
 def test_gpu_cholqr_loss_grows_like_kappa_z_squared_in_case2():
