@@ -95,7 +95,13 @@ typedef struct oqr_op {
  *             lo = bf16(x - hi)), products hi*hi + hi*lo + lo*hi on MFMA,
  *             FP32 accumulation inside a tile of K, FP64 across tiles.
  *   BF16X3  : three slices, the six products with slice indices i + j < 3.
- *   FP32    : reserved (OQR_E_UNSUPPORTED for single instances). */
+ *   FP32    : operands rounded to FP32 (nearest), products on FP32 MFMA,
+ *             FP32 accumulation inside a tile of K (at most 960 rows for
+ *             the dense product, 256 for the Gram), FP64 across tiles.
+ *             For the 7-point operator A Z is formed in FP64 first (the
+ *             unfused path) and the Gram runs in FP32.
+ * Every reduced-precision pass (BF16X2, BF16X3, FP32) starts with the shift
+ * of oqr_opts (unit roundoff u_p = 2^-24). */
 typedef enum { OQR_P_FP64 = 0, OQR_P_FP32 = 1, OQR_P_BF16X2 = 2, OQR_P_BF16X3 = 3 } oqr_prec;
 
 /* Gram-Schmidt variants for oqr_gs (Section 6 and the comments of Section 8). */

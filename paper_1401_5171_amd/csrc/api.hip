@@ -104,7 +104,8 @@ int64_t op_m(const oqr_op* A) { return (int64_t)A->nx * A->ny * A->nz; }
 
 int slices_of(int prec) { return prec == OQR_P_BF16X3 ? 3 : 2; }
 
-bool prec_ok(int p) { return p == OQR_P_FP64 || p == OQR_P_BF16X2 || p == OQR_P_BF16X3; }
+bool prec_ok(int p) { return p == OQR_P_FP64 || p == OQR_P_FP32 || p == OQR_P_BF16X2 || p == OQR_P_BF16X3; }
+bool split_prec(int p) { return p == OQR_P_BF16X2 || p == OQR_P_BF16X3; }
 
 int check_op(const oqr_op* A, int64_t m) {
   if (!A) return OQR_E_ARG;
@@ -205,8 +206,8 @@ size_t pass_ws(const oqr_op* A, int64_t m, int64_t n, const oqr_opts& o, bool tw
   w.R2 = c.take<double>((size_t)n * n);
   int maxs = 0;
   if (A->kind == OQR_OP_DENSE) {
-    if (o.pass1 != OQR_P_FP64) maxs = slices_of(o.pass1);
-    if (two && o.pass2 != OQR_P_FP64 && slices_of(o.pass2) > maxs) maxs = slices_of(o.pass2);
+    if (split_prec(o.pass1)) maxs = slices_of(o.pass1);
+    if (two && split_prec(o.pass2) && slices_of(o.pass2) > maxs) maxs = slices_of(o.pass2);
   }
   w.zs = c.take<unsigned short>(maxs ? split_z_elems(m, n, maxs) : 0);
   const size_t kp = A->kind == OQR_OP_DENSE ? gemm_kpart_bytes(m, n) : 0;
@@ -222,6 +223,12 @@ hipError_t gram_symm(const double* Z, int64_t ldz, int64_t m, int64_t n, const P
   return launch_gram_symm(Z, ldz, w.Ws, w.W, m, m, n, w.partial, w.G, s);
 }
 
+// Whether a pass on the 7-point operator forms A Z inside the Gram kernel (FP64 and split bfloat16 Grams,
+// n <= 128); the FP32 Gram runs unfused, on W = A Z.
+bool stencil_fused(const oqr_op* A, int64_t ldz, int64_t n, int prec) {
+  return A->kind == OQR_OP_STENCIL7 && prec != OQR_P_FP32 && stencil_gram_fits(A, ldz, n);
+}
+
 // One CHOLQR pass (Algorithm 1) on the device: W = A Z; G = Z^T W; R = chol(G [+ s I]); Q = Z R^{-1}.
 // For the 7-point operator with n <= 128 the first two steps run as one kernel that never stores W.
 // Dense A is symmetric: the product reads only its upper block triangle and G is assembled from the
@@ -231,8 +238,9 @@ int cholqr_pass(const oqr_op* A, const double* Z, int64_t ldz, int64_t m, int64_
                 int32_t* info, hipStream_t s) {
   if (A->kind == OQR_OP_DENSE) {
     const double* a = (const double*)A->a;
-    if (prec == OQR_P_FP64) {
-      OQR_TRACED(K_GEMM_F64, s, launch_symm_upper(a, A->lda, Z, ldz, w.W, m, m, n, w.kpart, s));
+    if (prec == OQR_P_FP64 || prec == OQR_P_FP32) {
+      OQR_TRACED(prec == OQR_P_FP64 ? K_GEMM_F64 : K_GEMM_SPLIT, s,
+                 launch_symm_upper(a, A->lda, Z, ldz, w.W, m, m, n, w.kpart, s, prec == OQR_P_FP32));
       OQR_TRACED(K_SYMM_DIAG, s,
                  launch_symm_finish(a, A->lda, Z, ldz, w.W, w.Ws, m, m, n, w.kpart, symm_layers(m, n, w.kpart), s));
     } else {
@@ -243,7 +251,7 @@ int cholqr_pass(const oqr_op* A, const double* Z, int64_t ldz, int64_t m, int64_
                  launch_symm_finish(a, A->lda, Z, ldz, w.W, w.Ws, m, m, n, w.kpart, symm_layers(m, n, w.kpart), s));
     }
     OQR_TRACED(K_GRAM, s, gram_symm(Z, ldz, m, n, w, s));
-  } else if (stencil_gram_fits(A, ldz, n)) {
+  } else if (stencil_fused(A, ldz, n, prec)) {
     if (prec == OQR_P_FP64)
       OQR_TRACED(K_GRAM, s, launch_stencil_gram(A, Z, ldz, n, w.partial, w.G, s));
     else
@@ -252,6 +260,8 @@ int cholqr_pass(const oqr_op* A, const double* Z, int64_t ldz, int64_t m, int64_
     OQR_TRACED(K_STENCIL, s, launch_sparse_apply(A, Z, ldz, w.W, w.ldw, n, s));
     if (prec == OQR_P_FP64)
       OQR_TRACED(K_GRAM, s, launch_gram_f64(Z, ldz, w.W, w.ldw, m, n, w.partial, w.G, s));
+    else if (prec == OQR_P_FP32)
+      OQR_TRACED(K_GRAM, s, launch_gram_fp32(Z, ldz, w.W, w.ldw, m, n, w.partial, w.G, s));
     else
       OQR_TRACED(K_GRAM, s, launch_gram_split(Z, ldz, w.W, w.ldw, m, n, slices_of(prec), w.partial, w.G, s));
   }
@@ -270,10 +280,7 @@ size_t pre_ws(const oqr_op* A, int64_t m, int64_t n, const oqr_opts& o) {
 
 int resolve_opts(const oqr_opts* in, oqr_opts* out) {
   *out = in ? *in : defaults();
-  if (!prec_ok(out->pass1) || !prec_ok(out->pass2)) {
-    if (out->pass1 == OQR_P_FP32 || out->pass2 == OQR_P_FP32) return OQR_E_UNSUPPORTED;
-    return OQR_E_ARG;
-  }
+  if (!prec_ok(out->pass1) || !prec_ok(out->pass2)) return OQR_E_ARG;
   if (!(out->shift_c >= 0.0) || !isfinite(out->shift_c)) return OQR_E_ARG;
   if (out->max_retries < 0 || out->max_retries > 16) return OQR_E_ARG;
   return OQR_OK;
@@ -440,7 +447,7 @@ int oqr_cholqr2(const oqr_op* A, const double* Z, int64_t ldz, int64_t m, int64_
   pass_ws(A, m, n, o, true, &w, ws);
   // pass 1: Z -> (Q1, R1);  pass 2: Q1 -> (Q, R2);  R = R2 R1.  Q1 is kept in Q (pass 2 in place), or, for
   // the stencil with the fused Gram, in the padded workspace W, whose A Q1 the second pass never stores.
-  const bool q1_in_w = A->kind == OQR_OP_STENCIL7 && stencil_gram_fits(A, w.ldw, n);
+  const bool q1_in_w = stencil_fused(A, w.ldw, n, o.pass2);
   double* q1 = q1_in_w ? w.W : Q;
   const int64_t ldq1 = q1_in_w ? w.ldw : ldq;
   if ((rc = cholqr_pass(A, Z, ldz, m, n, q1, ldq1, w.R1, n, o.pass1, o, w, w.shifts, info_dev, s))) return rc;

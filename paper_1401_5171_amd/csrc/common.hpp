@@ -19,6 +19,7 @@ typedef float f32x2 __attribute__((ext_vector_type(2)));
 // Lane layouts of the MFMA instructions used here (wave64; verified on gfx950):
 //  v_mfma_f64_16x16x4_f64   A[i][k]: lane l holds (i = l%16, k = l/16); B[k][j]: (k = l/16, j = l%16);
 //                           D[i][j]: lane l, element r holds (i = 4r + l/16, j = l%16).
+//  v_mfma_f32_16x16x4_f32   A and B as the FP64 instruction; D: lane l, element r holds (i = 4(l/16) + r, j = l%16).
 //  v_mfma_f32_16x16x32_bf16 A[i][k]: lane l holds i = l%16, k = 8(l/16)+e; B[k][j]: k = 8(l/16)+e, j = l%16;
 //                           D: lane l, element r holds (i = 4(l/16) + r, j = l%16).
 //  v_mfma_f32_32x32x16_bf16 A[i][k]: i = l%32, k = 8(l/32)+e; B[k][j]: k = 8(l/32)+e, j = l%32;
@@ -132,8 +133,10 @@ hipError_t launch_gemm_f64(const double* A, int64_t lda, const double* Z, int64_
 // cut into symm_layers parts whose partial products go to the layers of kpart (summed by
 // launch_symm_finish; with one layer the product goes to Woff directly).
 int symm_layers(int64_t m, int64_t n, const double* kpart);
+// f32: the FP32 operand pass (A and Z rounded to FP32, FP32 MFMA, FP32 sums over at most 960 rows of K
+// folded into FP64).
 hipError_t launch_symm_upper(const double* A, int64_t lda, const double* Z, int64_t ldz, double* Woff, int64_t ldw,
-                             int64_t m, int64_t n, double* kpart, hipStream_t s);
+                             int64_t m, int64_t n, double* kpart, hipStream_t s, bool f32 = false);
 // Woff of launch_symm_upper with A split on the fly into bfloat16 slices (Z pre-split, as for
 // launch_gemm_split); the diagonal blocks are then added in FP64 by launch_symm_finish.
 hipError_t launch_symm_split_upper(const double* A, int64_t lda, const unsigned short* zs, double* Woff, int64_t ldw,
@@ -170,6 +173,9 @@ hipError_t launch_gram_f64(const double* X, int64_t ldx, const double* Y, int64_
                            double* partial, double* G, hipStream_t s);
 hipError_t launch_gram_split(const double* X, int64_t ldx, const double* Y, int64_t ldy, int64_t m, int64_t n,
                              int slices, double* partial, double* G, hipStream_t s);
+// The same in FP32 operands: X, Y rounded to FP32, FP32 MFMA, FP32 sums over 256 rows, FP64 beyond.
+hipError_t launch_gram_fp32(const double* X, int64_t ldx, const double* Y, int64_t ldy, int64_t m, int64_t n,
+                            double* partial, double* G, hipStream_t s);
 
 // Shifted Cholesky of G (n x n, ld n, FP64, upper triangle read) into R (ldr), info on device.
 // Shift s = c * unit * max_i G_ii with c = c_first on the first attempt; on a failed pivot the

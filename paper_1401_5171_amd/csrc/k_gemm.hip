@@ -48,7 +48,12 @@ __device__ __forceinline__ bool upper_segments(int m, int p, int h, int H, int k
   return tb != ta;
 }
 
-template <int CB, int MODE>
+// F32: the FP32 operand pass.  A and Z are rounded to FP32 as they leave LDS and multiplied on
+// v_mfma_f32_16x16x4_f32 (the same lane layouts as the FP64 instruction), with FP32 sums over at most
+// F32_FOLD rows of K folded into the FP64 accumulators.
+constexpr int F32_FOLD = 960;
+
+template <int CB, int MODE, bool F32 = false>
 __global__ __launch_bounds__(NT, 2) void gemm_f64_kernel(const double* __restrict__ A, int64_t lda,
                                                           const double* __restrict__ Z, int64_t ldz,
                                                           double* __restrict__ W, int64_t ldw, int m, int n,
@@ -61,6 +66,9 @@ __global__ __launch_bounds__(NT, 2) void gemm_f64_kernel(const double* __restric
   const int j0 = blockIdx.y * BN;
   const int wc = wave * 16 * CB;
   W += blockIdx.z * wstride;
+  // row of accumulator element r within a 16 x 16 tile: the FP64 instruction's layout (4 r + l / 16), or
+  // the FP32 one's (4 (l / 16) + r); FP32 sums are folded element by element, so they keep theirs
+  auto drow = [](int r, int l) { return F32 ? 4 * (l >> 4) + r : 4 * r + (l >> 4); };
 
   // global -> register staging
   constexpr int AR = BM * BK64 / NT;            // 4
@@ -100,10 +108,30 @@ __global__ __launch_bounds__(NT, 2) void gemm_f64_kernel(const double* __restric
       for (int r = 0; r < BR; ++r) Bs[bk][bj + 16 * r] = rb[r];
     };
 
+    f32x4 acc32[F32 ? 4 : 1][F32 ? CB : 1];
+    auto fold32 = [&]() {
+      if constexpr (F32) {
+#pragma unroll
+        for (int a = 0; a < 4; ++a)
+#pragma unroll
+          for (int b = 0; b < CB; ++b) {
+#pragma unroll
+            for (int r = 0; r < 4; ++r) acc[a][b][r] += (double)acc32[a][b][r];
+            acc32[a][b] = f32x4{0.f, 0.f, 0.f, 0.f};
+          }
+      }
+    };
+    if constexpr (F32) {
+#pragma unroll
+      for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < CB; ++b) acc32[a][b] = f32x4{0.f, 0.f, 0.f, 0.f};
+    }
     __syncthreads();                   // the previous segment's last reads of As / Bs
     load(kb);
     store();
     __syncthreads();
+    int step = 0;
     for (int k0 = kb; k0 < ke; k0 += BK64) {
       load(k0 + BK64);                 // past the end: guarded loads return zeros
 #pragma unroll
@@ -114,15 +142,33 @@ __global__ __launch_bounds__(NT, 2) void gemm_f64_kernel(const double* __restric
         for (int a = 0; a < 4; ++a) af[a] = As[kr][a * 16 + (lane & 15)];
 #pragma unroll
         for (int b = 0; b < CB; ++b) bf[b] = Bs[kr][wc + b * 16 + (lane & 15)];
+        if constexpr (F32) {
+          float af32[4], bf32[CB];
 #pragma unroll
-        for (int a = 0; a < 4; ++a)
+          for (int a = 0; a < 4; ++a) af32[a] = (float)af[a];
 #pragma unroll
-          for (int b = 0; b < CB; ++b) acc[a][b] = mfma_f64(af[a], bf[b], acc[a][b]);
+          for (int b = 0; b < CB; ++b) bf32[b] = (float)bf[b];
+#pragma unroll
+          for (int a = 0; a < 4; ++a)
+#pragma unroll
+            for (int b = 0; b < CB; ++b)
+              acc32[a][b] = __builtin_amdgcn_mfma_f32_16x16x4f32(af32[a], bf32[b], acc32[a][b], 0, 0, 0);
+        } else {
+#pragma unroll
+          for (int a = 0; a < 4; ++a)
+#pragma unroll
+            for (int b = 0; b < CB; ++b) acc[a][b] = mfma_f64(af[a], bf[b], acc[a][b]);
+        }
+      }
+      if (F32 && ++step == F32_FOLD / BK64) {
+        fold32();
+        step = 0;
       }
       __syncthreads();
       store();
       __syncthreads();
     }
+    fold32();
     if (MODE == GEMM_DIAG) {
       // W = acc + Wadd: the addends of one row block are loaded together (branch-free buffer loads,
       // lanes outside the matrix masked with kOOB) before any is used, one round trip per row block
@@ -134,7 +180,7 @@ __global__ __launch_bounds__(NT, 2) void gemm_f64_kernel(const double* __restric
         for (int b = 0; b < CB; ++b)
 #pragma unroll
           for (int r = 0; r < 4; ++r) {
-            const int i = i0 + a * 16 + 4 * r + (lane >> 4);
+            const int i = i0 + a * 16 + drow(r, lane);
             const int j = j0 + wc + b * 16 + (lane & 15);
             add[b][r] = buf_f64(wb, ((uint32_t)((int64_t)j * ldadd + i) * 8u) | ((i < m && j < n) ? 0u : kOOB));
           }
@@ -142,7 +188,7 @@ __global__ __launch_bounds__(NT, 2) void gemm_f64_kernel(const double* __restric
         for (int b = 0; b < CB; ++b)
 #pragma unroll
           for (int r = 0; r < 4; ++r) {
-            const int i = i0 + a * 16 + 4 * r + (lane >> 4);
+            const int i = i0 + a * 16 + drow(r, lane);
             const int j = j0 + wc + b * 16 + (lane & 15);
             if (i < m && j < n) W[(int64_t)j * ldw + i] = acc[a][b][r] + add[b][r];
           }
@@ -154,7 +200,7 @@ __global__ __launch_bounds__(NT, 2) void gemm_f64_kernel(const double* __restric
         for (int b = 0; b < CB; ++b)
 #pragma unroll
           for (int r = 0; r < 4; ++r) {
-            const int i = i0 + a * 16 + 4 * r + (lane >> 4);
+            const int i = i0 + a * 16 + drow(r, lane);
             const int j = j0 + wc + b * 16 + (lane & 15);
             if (i < m && j < n) W[(int64_t)j * ldw + i] = acc[a][b][r];
           }
@@ -611,16 +657,21 @@ static hipError_t ksum(const double* P, int ks, int64_t m, int64_t n, double* W,
   return hipGetLastError();
 }
 
-#define OQR_GEMM_F64(cb, MODE_, grid, out, ldo, kchunk, stride, wadd, ldadd)                                     \
+#define OQR_GEMM_T(cb, MODE_, F32_, grid, out, ldo, kchunk, stride, wadd, ldadd)                                \
   do {                                                                                                          \
     const int M_ = (int)m, N_ = (int)n;                                                                         \
     if ((cb) == 1)                                                                                              \
-      gemm_f64_kernel<1, MODE_><<<(grid), NT, 0, s>>>(A, lda, Z, ldz, out, ldo, M_, N_, kchunk, stride, wadd, ldadd); \
+      gemm_f64_kernel<1, MODE_, F32_><<<(grid), NT, 0, s>>>(A, lda, Z, ldz, out, ldo, M_, N_, kchunk, stride, wadd, \
+                                                             ldadd);                                            \
     else if ((cb) == 2)                                                                                         \
-      gemm_f64_kernel<2, MODE_><<<(grid), NT, 0, s>>>(A, lda, Z, ldz, out, ldo, M_, N_, kchunk, stride, wadd, ldadd); \
+      gemm_f64_kernel<2, MODE_, F32_><<<(grid), NT, 0, s>>>(A, lda, Z, ldz, out, ldo, M_, N_, kchunk, stride, wadd, \
+                                                             ldadd);                                            \
     else                                                                                                        \
-      gemm_f64_kernel<4, MODE_><<<(grid), NT, 0, s>>>(A, lda, Z, ldz, out, ldo, M_, N_, kchunk, stride, wadd, ldadd); \
+      gemm_f64_kernel<4, MODE_, F32_><<<(grid), NT, 0, s>>>(A, lda, Z, ldz, out, ldo, M_, N_, kchunk, stride, wadd, \
+                                                             ldadd);                                            \
   } while (0)
+#define OQR_GEMM_F64(cb, MODE_, grid, out, ldo, kchunk, stride, wadd, ldadd) \
+  OQR_GEMM_T(cb, MODE_, false, grid, out, ldo, kchunk, stride, wadd, ldadd)
 
 hipError_t launch_gemm_f64(const double* A, int64_t lda, const double* Z, int64_t ldz, double* W, int64_t ldw,
                            int64_t m, int64_t n, double* kpart, hipStream_t s) {
@@ -639,13 +690,16 @@ hipError_t launch_gemm_f64(const double* A, int64_t lda, const double* Z, int64_
 int symm_layers(int64_t m, int64_t n, const double* kpart) { return kpart ? upper_parts(m, n) : 1; }
 
 hipError_t launch_symm_upper(const double* A, int64_t lda, const double* Z, int64_t ldz, double* Woff, int64_t ldw,
-                             int64_t m, int64_t n, double* kpart, hipStream_t s) {
+                             int64_t m, int64_t n, double* kpart, hipStream_t s, bool f32) {
   const int cb = col_blocks(n);
   const int R = ceil_div(m, BM), P = (R + 1) / 2, ycb = ceil_div(n, 64 * cb);
   const int H = symm_layers(m, n, kpart);
   double* out = H > 1 ? kpart : Woff;
   const int64_t ldo = H > 1 ? m : ldw, stride = H > 1 ? m * n : 0;
-  OQR_GEMM_F64(cb, GEMM_UPPER, dim3(P, ycb, H), out, ldo, 0, stride, nullptr, 0);
+  if (f32)
+    OQR_GEMM_T(cb, GEMM_UPPER, true, dim3(P, ycb, H), out, ldo, 0, stride, nullptr, 0);
+  else
+    OQR_GEMM_F64(cb, GEMM_UPPER, dim3(P, ycb, H), out, ldo, 0, stride, nullptr, 0);
   return hipGetLastError();
 }
 

@@ -47,7 +47,11 @@ constexpr int BK = 16;
 constexpr int PAD = 8;
 
 // SYM: G = X^T Y + X2^T X (the symmetric assembly Z^T Wsym + Woff^T Z with X = Z, Y = Wsym, X2 = Woff).
-template <bool SYM>
+// F32 (not with SYM): the FP32 operand Gram, X and Y rounded to FP32 as they leave LDS, products on
+// v_mfma_f32_16x16x4_f32, FP32 sums over KT32 rows folded into FP64 (the accumulators then follow the
+// FP32 instruction's row layout).
+constexpr int KT32 = 256;
+template <bool SYM, bool F32 = false>
 __global__ __launch_bounds__(NT) void gram_f64_kernel(const double* __restrict__ X, int64_t ldx,
                                                        const double* __restrict__ Y, int64_t ldy,
                                                        const double* __restrict__ X2, int64_t ldx2, int m, int n,
@@ -100,9 +104,22 @@ __global__ __launch_bounds__(NT) void gram_f64_kernel(const double* __restrict__
       }
     }
   };
+  static_assert(!(SYM && F32), "the FP32 Gram has no symmetric assembly");
+  f32x4 acc32[4];
+#pragma unroll
+  for (int b = 0; b < 4; ++b) acc32[b] = f32x4{0.f, 0.f, 0.f, 0.f};
+  auto fold32 = [&]() {
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+#pragma unroll
+      for (int r = 0; r < 4; ++r) acc[b][r] += (double)acc32[b][r];
+      acc32[b] = f32x4{0.f, 0.f, 0.f, 0.f};
+    }
+  };
   load(r0);
   store();
   __syncthreads();
+  int step = 0;
   for (int k0 = r0; k0 < r1; k0 += BK) {
     const bool more = k0 + BK < r1;
     load(k0 + BK);                        // past r1: zeros, never stored
@@ -110,13 +127,24 @@ __global__ __launch_bounds__(NT) void gram_f64_kernel(const double* __restrict__
     for (int kk = 0; kk < BK; kk += 4) {
       const int kr = kk + (lane >> 4);
       const double a = Xs[kr][wave * 16 + (lane & 15)];
+      if constexpr (F32) {
+        const float a32 = (float)a;
 #pragma unroll
-      for (int b = 0; b < 4; ++b) acc[b] = mfma_f64(a, Ys[kr][b * 16 + (lane & 15)], acc[b]);
+        for (int b = 0; b < 4; ++b)
+          acc32[b] = __builtin_amdgcn_mfma_f32_16x16x4f32(a32, (float)Ys[kr][b * 16 + (lane & 15)], acc32[b], 0, 0, 0);
+      } else {
+#pragma unroll
+        for (int b = 0; b < 4; ++b) acc[b] = mfma_f64(a, Ys[kr][b * 16 + (lane & 15)], acc[b]);
+      }
       if (SYM) {
         const double a2 = X2s[kr][wave * 16 + (lane & 15)];
 #pragma unroll
         for (int b = 0; b < 4; ++b) acc[b] = mfma_f64(a2, XJs[kr][b * 16 + (lane & 15)], acc[b]);
       }
+    }
+    if (F32 && ++step == KT32 / BK) {
+      fold32();
+      step = 0;
     }
     __syncthreads();
     if (more) {
@@ -124,12 +152,13 @@ __global__ __launch_bounds__(NT) void gram_f64_kernel(const double* __restrict__
       __syncthreads();
     }
   }
+  if (F32) fold32();
   double* P = partial + (int64_t)c * n * n;
 #pragma unroll
   for (int b = 0; b < 4; ++b)
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
-      const int i = I0 + wave * 16 + 4 * r + (lane >> 4);
+      const int i = I0 + wave * 16 + (F32 ? 4 * (lane >> 4) + r : 4 * r + (lane >> 4));
       const int j = J0 + b * 16 + (lane & 15);
       if (i < n && j < n) P[(int64_t)j * n + i] = acc[b][r];
     }
@@ -909,6 +938,16 @@ hipError_t launch_gram_f64(const double* X, int64_t ldx, const double* Y, int64_
 hipError_t launch_gram_symm(const double* Z, int64_t ldz, const double* Wsym, const double* Woff, int64_t ldw,
                             int64_t m, int64_t n, double* partial, double* G, hipStream_t s) {
   return gram_f64<true>(Z, ldz, Wsym, ldw, Woff, ldw, m, n, partial, G, s);
+}
+
+hipError_t launch_gram_fp32(const double* X, int64_t ldx, const double* Y, int64_t ldy, int64_t m, int64_t n,
+                            double* partial, double* G, hipStream_t s) {
+  GramPlan p = plan(m, n);
+  gram_f64_kernel<false, true><<<dim3(p.tiles, p.chunks), NT, 0, s>>>(X, ldx, Y, ldy, nullptr, 0, (int)m, (int)n,
+                                                                      p.nb, p.kc, partial);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  return reduce(partial, n, p.chunks, G, s);
 }
 
 hipError_t launch_gram_split(const double* X, int64_t ldx, const double* Y, int64_t ldy, int64_t m, int64_t n,
