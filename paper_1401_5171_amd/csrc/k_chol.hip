@@ -3,14 +3,14 @@
 // rule, the triangular product R = R2 R1 that combines two passes, and fills.
 //
 // Cholesky: one workgroup of 512 threads (8 waves), blocked left-looking with
-// 32x32 blocks, writing R in place.  For block row K:
-//   (a) wave w forms block (K, K+w) of G - sum_{P<K} R_PK^T R_PJ on FP64 MFMA,
-//       reading the finished rows of R (L2-resident) and keeping the result in
-//       LDS,
-//   (b) the diagonal block is factored by one wave in registers (lane j holds
-//       column j; pivots and pivot rows broadcast by readlane),
-//   (c) the rest of the block row is solved column by column,
-//       R_KJ = R_KK^{-T} (G_KJ - ...), and written to R.
+// 32x32 blocks and a one-row lookahead, writing R in place.  For block row K:
+//   (a) the diagonal block is factored by wave 0 in registers (lane j holds
+//       column j; pivots and pivot rows broadcast by readlane), while waves
+//       1..7 form the blocks (K+1, J) of G - sum_{P<K} R_P,K+1^T R_PJ on FP64
+//       MFMA, reading the finished rows of R (L2-resident),
+//   (b) the rest of block row K is solved column by column,
+//       R_KJ = R_KK^{-T} (G_KJ - ...), written to R and kept in LDS,
+//   (c) waves 1..7 subtract the term P = K from LDS: block row K+1 is ready.
 // A pivot that is not positive (or NaN) restarts the factorisation from G with
 // a larger diagonal shift; after the last retry the 1-based pivot index goes
 // to info (LAPACK potrf convention).
@@ -71,12 +71,20 @@ __device__ __noinline__ void diag_factor(double (*Dk)[CB + 1], double* rdiag, in
   }
 }
 
+// Left-looking with a one-block-row lookahead.  Block row K + 1 is
+//   G(K+1, J) - sum_{P <= K} R_{P,K+1}^T R_{P,J},
+// and only its last term needs block row K.  So while wave 0 factors the diagonal block of row K,
+// waves 1..7 accumulate the terms P < K of row K + 1 (one block each, R rows read from L2); after the
+// solve of row K (kept in LDS) they add the term P = K, and row K + 1 is ready.  The terms are added
+// in the same order (P ascending) as a plain left-looking sweep, so the factor does not depend on
+// the lookahead.
 __global__ __launch_bounds__(NTC) void chol_kernel(const double* __restrict__ G, int n, double* __restrict__ R,
                                                     int64_t ldr, double unit, double c_first, double c_retry,
                                                     int max_retries, int32_t* __restrict__ info,
                                                     double* __restrict__ shift_used) {
   __shared__ double Dk[1][CB][CB + 1];         // the diagonal block of block row K
-  __shared__ double P[CB][OQR_MAX_N + 2];     // block row K: P[p][j] = entry (k0 + p, j), j absolute column
+  __shared__ double P[CB][OQR_MAX_N + 2];     // block row K: P[p][j] = entry (k0 + p, j), j absolute column;
+                                              // after the solve of row K, row K of R
   __shared__ double red[NW];
   __shared__ double rdiag[CB];                // 1 / r_kk of the current diagonal block
   __shared__ double s_dmax;
@@ -102,102 +110,141 @@ __global__ __launch_bounds__(NTC) void chol_kernel(const double* __restrict__ G,
   const bufrsrc gbuf = make_buf(G, (int64_t)n * n * 8);
   const bufrsrc rbuf = make_buf(R, ((int64_t)(n - 1) * ldr + n) * 8);
 
+  // block (KR, J) of G + s I (upper triangle; identity beyond n) into acc.  Branch-free buffer loads,
+  // lanes outside the triangle masked with kOOB (they read 0), so that the 16 loads are in flight
+  // together.
+  auto load_g = [&](int KR, int J, double s, f64x4 (&acc)[2][2]) {
+    const int r0 = KR * CB, J0 = J * CB;
+#pragma unroll
+    for (int x = 0; x < 2; ++x)
+#pragma unroll
+      for (int y = 0; y < 2; ++y)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int i = r0 + 16 * x + 4 * r + li, j = J0 + 16 * y + lj;
+          const bool in = i < n && j < n && i <= j;
+          acc[x][y][r] = buf_f64(gbuf, ((uint32_t)(j * n + i) * 8u) | (in ? 0u : kOOB));
+        }
+#pragma unroll
+    for (int x = 0; x < 2; ++x)
+#pragma unroll
+      for (int y = 0; y < 2; ++y)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int i = r0 + 16 * x + 4 * r + li, j = J0 + 16 * y + lj;
+          if (i == j) acc[x][y][r] = (i < n) ? acc[x][y][r] + s : 1.0;
+        }
+  };
+  // acc -= sum over the finished block rows P < PEND of R_{P,KR}^T R_{P,J}, rows of R read from L2 in
+  // chunks of 32 (8 MFMA k steps), the next chunk loaded during the current one
+  auto update_l2 = [&](int KR, int J, int pend, f64x4 (&acc)[2][2]) {
+    const int k0 = KR * CB, J0 = J * CB, kend = pend * CB;
+    // byte offsets of this lane's entries of R in columns k0 + 16 x + lj (A operand) and
+    // J0 + 16 x + lj (B operand), rows li + 4 u of a chunk; columns beyond n read 0
+    uint32_t aoff[2], boff[2];
+#pragma unroll
+    for (int x = 0; x < 2; ++x) {
+      const int ca = k0 + 16 * x + lj, cb = J0 + 16 * x + lj;
+      aoff[x] = ((uint32_t)((int64_t)ca * ldr + li) * 8u) | (ca < n ? 0u : kOOB);
+      boff[x] = ((uint32_t)((int64_t)cb * ldr + li) * 8u) | (cb < n ? 0u : kOOB);
+    }
+    double a[8][2], b[8][2];
+    auto load_chunk = [&](int p0, double (&aa)[8][2], double (&bb)[8][2]) {
+#pragma unroll
+      for (int u = 0; u < 8; ++u)
+#pragma unroll
+        for (int x = 0; x < 2; ++x) {
+          aa[u][x] = buf_f64(rbuf, aoff[x] + (uint32_t)(p0 + 4 * u) * 8u);
+          bb[u][x] = buf_f64(rbuf, boff[x] + (uint32_t)(p0 + 4 * u) * 8u);
+        }
+    };
+    if (kend > 0) load_chunk(0, a, b);
+    for (int p0 = 0; p0 < kend; p0 += CB) {          // kend is a multiple of 32
+      double na[8][2], nbv[8][2];
+      if (p0 + CB < kend) load_chunk(p0 + CB, na, nbv);
+#pragma unroll
+      for (int u = 0; u < 8; ++u)
+#pragma unroll
+        for (int x = 0; x < 2; ++x)
+#pragma unroll
+          for (int y = 0; y < 2; ++y) acc[x][y] = mfma_f64(-a[u][x], b[u][y], acc[x][y]);
+      if (p0 + CB < kend) {
+#pragma unroll
+        for (int u = 0; u < 8; ++u)
+#pragma unroll
+          for (int x = 0; x < 2; ++x) {
+            a[u][x] = na[u][x];
+            b[u][x] = nbv[u][x];
+          }
+      }
+    }
+  };
+  // acc -= R_{K,KR}^T R_{K,J} from row K of R held in P (columns beyond n read 0, as from L2)
+  auto update_lds = [&](int KR, int J, f64x4 (&acc)[2][2]) {
+    const int k0 = KR * CB, J0 = J * CB;
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      double a[2], b[2];
+#pragma unroll
+      for (int x = 0; x < 2; ++x) {
+        const int ca = k0 + 16 * x + lj, cb = J0 + 16 * x + lj;
+        const double va = P[4 * u + li][ca], vb = P[4 * u + li][cb];
+        a[x] = ca < n ? va : 0.0;
+        b[x] = cb < n ? vb : 0.0;
+      }
+#pragma unroll
+      for (int x = 0; x < 2; ++x)
+#pragma unroll
+        for (int y = 0; y < 2; ++y) acc[x][y] = mfma_f64(-a[x], b[y], acc[x][y]);
+    }
+  };
+  auto store_block = [&](int KR, int J, const f64x4 (&acc)[2][2]) {
+    const int J0 = J * CB;
+#pragma unroll
+    for (int x = 0; x < 2; ++x)
+#pragma unroll
+      for (int y = 0; y < 2; ++y)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int i = 16 * x + 4 * r + li, j = 16 * y + lj;
+          if (J == KR) Dk[0][i][j] = acc[x][y][r];
+          else P[i][J0 + j] = acc[x][y][r];
+        }
+  };
+
   double c = c_first;
   for (int attempt = 0;; ++attempt) {
     const double s = c * unit * dmax;
     if (t == 0) s_fail = 0;
+    // block row 0: G itself
+    if (wave < nb) {
+      f64x4 acc[2][2];
+      load_g(0, wave, s, acc);
+      store_block(0, wave, acc);
+    }
     __syncthreads();
     for (int K = 0; K < nb; ++K) {
       const int k0 = K * CB;
-      // (a) block (K, J) for J = K + wave, minus the contributions of the finished rows
-      const int J = K + wave;
-      if (J < nb) {
-        const int J0 = J * CB;
-        // G's upper triangle (identity beyond n).  Branch-free buffer loads, lanes outside the triangle
-        // masked with kOOB (they read 0), so that the 16 loads are in flight together.
-        f64x4 acc[2][2];
-#pragma unroll
-        for (int x = 0; x < 2; ++x)
-#pragma unroll
-          for (int y = 0; y < 2; ++y)
-#pragma unroll
-            for (int r = 0; r < 4; ++r) {
-              const int i = k0 + 16 * x + 4 * r + li, j = J0 + 16 * y + lj;
-              const bool in = i < n && j < n && i <= j;
-              acc[x][y][r] = buf_f64(gbuf, ((uint32_t)(j * n + i) * 8u) | (in ? 0u : kOOB));
-            }
-#pragma unroll
-        for (int x = 0; x < 2; ++x)
-#pragma unroll
-          for (int y = 0; y < 2; ++y)
-#pragma unroll
-            for (int r = 0; r < 4; ++r) {
-              const int i = k0 + 16 * x + 4 * r + li, j = J0 + 16 * y + lj;
-              if (i == j) acc[x][y][r] = (i < n) ? acc[x][y][r] + s : 1.0;
-            }
-        // byte offsets of this lane's entries of R in columns k0 + 16 x + lj (A operand) and
-        // J0 + 16 x + lj (B operand), rows li + 4 u of a chunk; columns beyond n read 0
-        uint32_t aoff[2], boff[2];
-#pragma unroll
-        for (int x = 0; x < 2; ++x) {
-          const int ca = k0 + 16 * x + lj, cb = J0 + 16 * x + lj;
-          aoff[x] = ((uint32_t)((int64_t)ca * ldr + li) * 8u) | (ca < n ? 0u : kOOB);
-          boff[x] = ((uint32_t)((int64_t)cb * ldr + li) * 8u) | (cb < n ? 0u : kOOB);
-        }
-        // rows of R in chunks of 32 (8 MFMA k steps), the next chunk loaded during the current one
-        double a[8][2], b[8][2];
-        auto load_chunk = [&](int p0, double (&aa)[8][2], double (&bb)[8][2]) {
-#pragma unroll
-          for (int u = 0; u < 8; ++u)
-#pragma unroll
-            for (int x = 0; x < 2; ++x) {
-              aa[u][x] = buf_f64(rbuf, aoff[x] + (uint32_t)(p0 + 4 * u) * 8u);
-              bb[u][x] = buf_f64(rbuf, boff[x] + (uint32_t)(p0 + 4 * u) * 8u);
-            }
-        };
-        if (k0 > 0) load_chunk(0, a, b);
-        for (int p0 = 0; p0 < k0; p0 += CB) {          // k0 is a multiple of 32
-          double na[8][2], nbv[8][2];
-          if (p0 + CB < k0) load_chunk(p0 + CB, na, nbv);
-#pragma unroll
-          for (int u = 0; u < 8; ++u)
-#pragma unroll
-            for (int x = 0; x < 2; ++x)
-#pragma unroll
-              for (int y = 0; y < 2; ++y) acc[x][y] = mfma_f64(-a[u][x], b[u][y], acc[x][y]);
-          if (p0 + CB < k0) {
-#pragma unroll
-            for (int u = 0; u < 8; ++u)
-#pragma unroll
-              for (int x = 0; x < 2; ++x) {
-                a[u][x] = na[u][x];
-                b[u][x] = nbv[u][x];
-              }
-          }
-        }
-#pragma unroll
-        for (int x = 0; x < 2; ++x)
-#pragma unroll
-          for (int y = 0; y < 2; ++y)
-#pragma unroll
-            for (int r = 0; r < 4; ++r) {
-              const int i = 16 * x + 4 * r + li, j = 16 * y + lj;
-              if (J == K) Dk[0][i][j] = acc[x][y][r];
-              else P[i][J0 + j] = acc[x][y][r];
-            }
+      // (a) wave 0 factors the diagonal block of row K in registers; waves 1..7 start block
+      // (K + 1, K + w) of the next row with the terms of the rows before K
+      f64x4 nxt[2][2];
+      const int Jn = K + wave;                  // the next row's block of wave w (w >= 1)
+      const bool has_next = wave >= 1 && K + 1 < nb && Jn < nb;
+      if (wave == 0) {
+        diag_factor(Dk[0], rdiag, &s_fail, k0, lane);
+      } else if (has_next) {
+        load_g(K + 1, Jn, s, nxt);
+        update_l2(K + 1, Jn, K, nxt);
       }
       __syncthreads();
-      // (b) factor the diagonal block on wave 0, in registers
-      if (wave == 0) diag_factor(Dk[0], rdiag, &s_fail, k0, lane);
-      __syncthreads();
       if (s_fail) break;
-      // (c) write the diagonal block; solve the rest of the block row, one thread per column
+      // (b) write the diagonal block; solve the rest of block row K, four lanes per column (lane `sub`
+      // owns rows sub + 4e; pivots are broadcast within the quad); row K of R goes to R and stays in P
 #pragma unroll
       for (int e = 0; e < DPT; ++e) {
         const int di = (t + NTC * e) >> 5, dj = (t + NTC * e) & 31;
         if (k0 + di < n && k0 + dj < n) R[(int64_t)(k0 + dj) * ldr + k0 + di] = (di <= dj) ? Dk[0][di][dj] : 0.0;
       }
-      // four lanes per column: lane `sub` owns rows sub + 4e; pivots are broadcast within the quad
       {
         const int sub = t & 3;
         for (int cb = k0 + CB; cb < n; cb += NTC / 4) {
@@ -221,8 +268,10 @@ __global__ __launch_bounds__(NTC) void chol_kernel(const double* __restrict__ G,
           }
           if (ok) {
 #pragma unroll
-            for (int e = 0; e < 8; ++e)
+            for (int e = 0; e < 8; ++e) {
+              P[sub + 4 * e][jcol] = x[e];
               if (k0 + sub + 4 * e < n) R[(int64_t)jcol * ldr + k0 + sub + 4 * e] = x[e];
+            }
           }
         }
       }
@@ -230,6 +279,14 @@ __global__ __launch_bounds__(NTC) void chol_kernel(const double* __restrict__ G,
       for (int idx = t; idx < CB * n; idx += NTC) {
         const int j = k0 + idx % CB, i = k0 + CB + idx / CB;
         if (j < n && i < n) R[(int64_t)j * ldr + i] = 0.0;
+      }
+      __syncthreads();
+      // (c) waves 1..7 add the term of row K and leave block row K + 1 in Dk / P.  Each wave reads the
+      // columns of block K + 1 (never written here: that block goes to Dk) and of its own block, and
+      // writes only its own block after reading it.
+      if (has_next) {
+        update_lds(K + 1, Jn, nxt);
+        store_block(K + 1, Jn, nxt);
       }
       __syncthreads();
     }
