@@ -70,10 +70,13 @@ def parse():
                    choices=["dense32768", "dense8192", "stencil", "tridiag", "batch", "small500", "copycal"])
     p.add_argument("--batch-count", type=int, default=4096)
     p.add_argument("--batch-dtype", default="f64", choices=["f64", "f32"], help="storage type of the batch")
-    p.add_argument("--tile", type=int, default=-1, help="batched tile id (-1: time every id, keep the best)")
+    p.add_argument("--retune", action="store_true",
+                   help="batch: autotune the tile shapes on this batch instead of using the stored table")
     p.add_argument("--pass1", default=None, choices=["fp64", "bf16x2", "bf16x3"],
                    help="precision of pass 1 of the mixed schedule (default bf16x2: hi/lo split)")
     p.add_argument("--cpu-sample", type=int, default=8192, help="m' of the CPU oracle sample (0 = skip)")
+    p.add_argument("--no-others", action="store_true",
+                   help="default workload only: skip the stencil and batch summaries added to its line")
     return p.parse_args()
 
 
@@ -243,7 +246,7 @@ def cpu_baseline(A, z, n, ms, torch):
             "sample": sample, "seconds": round(dt, 3)}
 
 
-def run_batch(args, torch, oqr):
+def run_batch(args, torch, oqr, per_instance=True):
     """Batched FP64 CholQR2-A over the synthetic batch (see the module docstring)."""
     import numpy as np
     import workloads as W
@@ -276,15 +279,12 @@ def run_batch(args, torch, oqr):
         alg_flops += 2 * (n_ ** 3 / 3 + m_ * n_ * n_)
         alg_bytes += 2 * 3 * esize * m_ * n_
     log(f"batch: {len(sizes)} instances, sum A = {np.sum(ms * ms) * esize / 1e9:.1f} GB, {flops:.3e} flops")
-    bp = oqr.BatchPlan(As, Zs)
-    if args.tile < 0:
-        tile_ms = bp.autotune(reps=3)           # the library's tile configurations, fastest kept
-    else:
-        bp.tile = args.tile
-        tile_ms = {}
-    for tl, ms_ in tile_ms.items():
-        log(f"tile {tl}: {ms_:.3f} ms per batched launch")
-    best = bp.tile
+    bp = oqr.BatchPlan(As, Zs)             # the tuning table checked in beside the library
+    tune_report = None
+    if args.retune:
+        tune_report = bp.autotune(reps=3)
+        log(f"autotune: {json.dumps(tune_report)}")
+    tuning = bp.tuning.to_dict()
     for _ in range(args.warmup):
         bp.run()
     torch.cuda.synchronize()
@@ -304,7 +304,7 @@ def run_batch(args, torch, oqr):
         o, rr = oqr.check(a, z, q, r)
         worst_o, worst_r = max(worst_o, o), max(worst_r, rr)
     line_extra = {}
-    if dt == torch.float64:
+    if dt == torch.float64 and per_instance:
         # the same factorisations, one instance per call (each call launches its own kernels)
         plans = [oqr.Plan("cholqr2", As[k], sizes[k].n) for k in range(len(sizes))]
         outs = [(torch.empty(p.n, p.m, dtype=dt, device=dev).t(), torch.empty(p.n, p.n, dtype=dt, device=dev).t())
@@ -323,7 +323,7 @@ def run_batch(args, torch, oqr):
         log(f"per-instance launches: {per * 1e3:.2f} ms")
         del plans, outs
     kms = kt.avg_ms
-    kname = f"batch_kernel<{'double' if esize == 8 else 'float'}> (tile {best})"
+    kname = f"batch_kernel<{'double' if esize == 8 else 'float'}> (tuned tile shapes)"
     # the bound is the resource whose peak needs longer for the launch's algorithmic work
     if alg_bytes / PEAK["hbm"] >= alg_flops / PEAK["fp64"]:
         roof = {"bound": "hbm", "kernel": kname, "achieved": round(alg_bytes / (kms * 1e-3) / 1e9, 1),
@@ -344,12 +344,13 @@ def run_batch(args, torch, oqr):
                                f"n in {{8,16,32,64}}, kappa(A) in [1e2, 1e8], {args.batch_dtype} storage",
                    "count": len(sizes), "flops_per_step": flops, "flop_count": "sum of 2m^2n+2mn^2"},
         "orth_loss_fro_max_sampled": worst_o, "residual_fro_max_sampled": worst_r,
-        "tile_ms": {str(k): round(v, 4) for k, v in tile_ms.items()},
+        "tuning": tuning, "autotune": tune_report,
         "roofline": roof, "cpu_baseline": None,
     }
     line.update(line_extra)
     if args.cpu_sample:
         line["cpu_baseline"] = cpu_baseline_batch(As, Zs, sizes, budget_s=12.0)
+    del bp, As, Zs
     print(json.dumps(line), flush=True)
 
 
@@ -572,7 +573,53 @@ def main():
         line["cpu_baseline"] = cpu_baseline(A, z_host, n, min(args.cpu_sample, m), torch)
     else:
         line["cpu_baseline"] = None
+    if args.workload == "dense32768" and not args.no_others:
+        del A, Z, Q, R, mixed, fp64, fp64_1
+        torch.cuda.empty_cache()
+        line["other_workloads"] = {"stencil": summary_stencil(args, torch, oqr),
+                                   "batch_fp64": summary_batch(args, torch, oqr)}
     print(json.dumps(line), flush=True)
+
+
+def summary_stencil(args, torch, oqr):
+    """The stencil workload (7-point Laplacian + 1e-3 I on 128 x 128 x 64, n = 128, column-scaled Z
+    with kappa 1e4): both CholQR2-A schedules timed as the default workload's, with their schedule
+    rooflines and the fused FP64 Gram's average launch."""
+    A, Z, _, m, n, desc, flops, _, dom_flops = make_inputs("stencil", torch)
+    Q = torch.empty(n, m, dtype=torch.float64, device="cuda").t()
+    R = torch.empty(n, n, dtype=torch.float64, device="cuda").t()
+    out = {"workload": desc["workload"]}
+    for name, p1 in (("mixed", "bf16x2"), ("fp64", "fp64")):
+        plan = oqr.Plan("cholqr2", A, n, pass1=p1, pass2="fp64")
+        for _ in range(args.warmup):
+            plan.run(Z, Q, R)
+        t, kavg, _ = time_steps(plan, Z, Q, R, args.steps, torch, "gram")
+        orth_f, _ = oqr.check(A, Z, Q, R)
+        out[name] = {"ms_per_step": round(t * 1e3, 4), "value": round(flops / t / 1e9, 2),
+                     "orth_loss_fro": orth_f, "gram_avg_launch_ms": round(kavg, 4),
+                     "breakdown_ms": breakdown(plan, Z, Q, R, torch),
+                     "schedule_roofline": schedule_roofline("stencil", m, n, (p1, "fp64"), t * 1e3)}
+        log(f"stencil {name}: {t * 1e3:.3f} ms/step, orth_F={orth_f:.2e}")
+    out["unit"] = "GFLOP/s (2mn^2 per factorisation)"
+    return out
+
+
+def summary_batch(args, torch, oqr):
+    """The batch workload (4096 instances, FP64 storage) in one persistent launch: time per launch with
+    the autotuned configuration and the launch's fraction of the HBM and FP64-MFMA peaks (bytes and
+    flops the symmetric schedule executes)."""
+    import argparse as _ap
+    import contextlib
+    import io
+    sub = _ap.Namespace(**vars(args))
+    sub.batch_count, sub.batch_dtype, sub.retune, sub.cpu_sample = 4096, "f64", False, 0
+    buf = io.StringIO()
+    with contextlib.redirect_stdout(buf):
+        run_batch(sub, torch, oqr, per_instance=False)
+    rec = json.loads(buf.getvalue().strip().splitlines()[-1])
+    torch.cuda.empty_cache()
+    keep = ("value", "ms_per_step", "orth_loss_fro_max_sampled", "residual_fro_max_sampled", "tuning", "roofline")
+    return dict({"workload": rec["config"]["workload"]}, **{k: rec[k] for k in keep})
 
 
 if __name__ == "__main__":

@@ -265,6 +265,29 @@ enum { OQR_BATCH_BAD_ITEM = -1 };
 /* Workspace bytes for oqr_cholqr2_batched. */
 size_t oqr_batched_workspace_bytes(int64_t batch, int32_t max_m, int32_t max_n, int32_t dtype);
 
+/* Tuning of the batched launch.  Instances are classed by m (buckets
+ * m < 512, < 1024, < 2048, < 4096, < 8192, >= 8192) and by n (n <= 8, <= 16,
+ * <= 32, <= 64); each class runs the Gram phase with one tile shape:
+ *   shape 0: row blocks of 128 rows, K steps of 32   shape 1: 64 x 32
+ *   shape 2: 128 x 16                                shape 3: 64 x 16
+ * Shapes change the grouping of the FP64 sums (not the arithmetic), so
+ * results differ between shapes by rounding only.  wg_per_cu: 1..3
+ * persistent workgroups per compute unit; sort: 1 = take instances largest
+ * (m^2 n) first, 0 = in index order.  A table tuned on the caller's batch
+ * comes from the binding's autotuner (it times the shapes class by class). */
+#define OQR_BATCH_MBUCKETS 6
+#define OQR_BATCH_NCLASSES 4
+#define OQR_BATCH_SHAPES 4
+typedef struct oqr_batch_tuning {
+  int32_t wg_per_cu;
+  int32_t sort;
+  uint8_t shape[OQR_BATCH_MBUCKETS][OQR_BATCH_NCLASSES];
+} oqr_batch_tuning;
+
+/* Fills *tuning with the built-in configuration (2 workgroups per compute
+ * unit, sorted, shape 0 for every class), used when NULL is passed. */
+void oqr_batched_default_tuning(oqr_batch_tuning* tuning);
+
 /* Batched CholQR2-A over `batch` independent dense instances in one
  * persistent launch: workgroups take instances from a device work queue
  * (largest first), each instance runs both passes inside one workgroup with
@@ -277,17 +300,14 @@ size_t oqr_batched_workspace_bytes(int64_t batch, int32_t max_m, int32_t max_n, 
  * OQR_F32 (FP32 storage, widened to FP64 on load: every product, the Gram, the
  * Cholesky and the substitution are FP64; Q and R are rounded to FP32 on
  * store).  info_dev: `batch` int32, one per instance (values above).  Host
- * errors: OQR_E_ARG for batch, max_m, max_n, dtype, tile or options out of
+ * errors: OQR_E_ARG for batch, max_m, max_n, dtype, tuning or options out of
  * range; OQR_E_UNSUPPORTED for a precision other than FP64.  The call
  * allocates nothing and may be captured in a hipGraph.
- * tile: 0 = use the built-in tile table, else a tile id from
- * oqr_batched_tile_count() (autotuning). */
+ * tuning: host struct read during the call (NULL = oqr_batched_default_tuning). */
 int oqr_cholqr2_batched(int64_t batch, const oqr_batch_item* items_dev, int32_t dtype,
-                        int32_t max_m, int32_t max_n, const oqr_opts* opts, int32_t tile,
-                        void* ws, size_t ws_bytes, int32_t* info_dev, void* stream);
-
-/* Number of batched tile configurations (ids 1..count). */
-int oqr_batched_tile_count(void);
+                        int32_t max_m, int32_t max_n, const oqr_opts* opts,
+                        const oqr_batch_tuning* tuning, void* ws, size_t ws_bytes,
+                        int32_t* info_dev, void* stream);
 
 /* Timing aid: from oqr_trace_start(name) until oqr_trace_stop, every launch
  * of the named kernel ("gemm_f64", "gemm_split", "gram", "chol", "trsm",

@@ -33,7 +33,7 @@ MAX_N = 256
 
 EXPORTS = (
     "oqr_default_opts", "oqr_workspace_bytes", "oqr_cholqr", "oqr_cholqr2", "oqr_pre_cholqr", "oqr_chol_a", "oqr_eig_a",
-    "oqr_gs", "oqr_check", "oqr_batched_workspace_bytes", "oqr_cholqr2_batched", "oqr_batched_tile_count",
+    "oqr_gs", "oqr_check", "oqr_batched_workspace_bytes", "oqr_cholqr2_batched", "oqr_batched_default_tuning",
     "oqr_status_string", "oqr_version", "oqr_trace_start", "oqr_trace_stop", "oqr_gls", "oqr_gls_workspace_bytes",
     "oqr_cholqr2_noalloc", "oqr_noalloc_scratch_bytes",
 )
@@ -55,6 +55,58 @@ class _Op(ctypes.Structure):
 class _Opts(ctypes.Structure):
     _fields_ = [("pass1", ctypes.c_int32), ("pass2", ctypes.c_int32), ("shift_c", ctypes.c_double),
                 ("max_retries", ctypes.c_int32), ("gs_variant", ctypes.c_int32)]
+
+
+BATCH_MBUCKETS, BATCH_NCLASSES, BATCH_SHAPES = 6, 4, 4
+BATCH_SHAPE_NAMES = ("128x32", "64x32", "128x16", "64x16")       # rows per row block x K step
+TUNING_PATH = os.path.join(_HERE, "batch_tuning.json")
+
+
+class BatchTuning(ctypes.Structure):
+    _fields_ = [("wg_per_cu", ctypes.c_int32), ("sort", ctypes.c_int32),
+                ("shape", (ctypes.c_uint8 * BATCH_NCLASSES) * BATCH_MBUCKETS)]
+
+    def to_dict(self):
+        return {"wg_per_cu": int(self.wg_per_cu), "sort": int(self.sort),
+                "shape": [[int(self.shape[b][c]) for c in range(BATCH_NCLASSES)] for b in range(BATCH_MBUCKETS)]}
+
+    @classmethod
+    def from_dict(cls, d):
+        t = cls()
+        t.wg_per_cu, t.sort = int(d["wg_per_cu"]), int(d["sort"])
+        for b in range(BATCH_MBUCKETS):
+            for c in range(BATCH_NCLASSES):
+                t.shape[b][c] = int(d["shape"][b][c])
+        return t
+
+
+def batch_m_bucket(m: int) -> int:
+    """m bucket of the batched tuning table: m < 512, < 1024, < 2048, < 4096, < 8192, >= 8192."""
+    b, lim = 0, 512
+    while b < BATCH_MBUCKETS - 1 and m >= lim:
+        b, lim = b + 1, lim * 2
+    return b
+
+
+def batch_n_class(n: int) -> int:
+    """n class of the batched tuning table: n <= 8, <= 16, <= 32, <= 64."""
+    return 0 if n <= 8 else 1 if n <= 16 else 2 if n <= 32 else 3
+
+
+def default_batch_tuning() -> "BatchTuning":
+    t = BatchTuning()
+    lib().oqr_batched_default_tuning(ctypes.byref(t))
+    return t
+
+
+def stored_batch_tuning(dtype: str) -> Optional["BatchTuning"]:
+    """The tuning table checked in beside the library for storage `dtype` ("f64" or "f32"), or None."""
+    import json
+    if not os.path.exists(TUNING_PATH):
+        return None
+    with open(TUNING_PATH) as f:
+        d = json.load(f)
+    return BatchTuning.from_dict(d[dtype]) if dtype in d else None
 
 
 class BatchItem(ctypes.Structure):
@@ -92,9 +144,10 @@ def lib():
         L.oqr_check.restype = ctypes.c_int
         L.oqr_batched_workspace_bytes.argtypes = [i64, i32, i32, i32]
         L.oqr_batched_workspace_bytes.restype = sz
-        L.oqr_cholqr2_batched.argtypes = [i64, vp, i32, i32, i32, ctypes.POINTER(_Opts), i32, vp, sz, vp, vp]
+        L.oqr_cholqr2_batched.argtypes = [i64, vp, i32, i32, i32, ctypes.POINTER(_Opts), ctypes.POINTER(BatchTuning),
+                                          vp, sz, vp, vp]
         L.oqr_cholqr2_batched.restype = ctypes.c_int
-        L.oqr_batched_tile_count.restype = ctypes.c_int
+        L.oqr_batched_default_tuning.argtypes = [ctypes.POINTER(BatchTuning)]
         L.oqr_status_string.argtypes = [ctypes.c_int]
         L.oqr_status_string.restype = ctypes.c_char_p
         L.oqr_default_opts.argtypes = [ctypes.POINTER(_Opts)]
@@ -303,9 +356,12 @@ class BatchPlan:
     contiguous) and Z_i (m_i x n_i, column-major), storage float64 or float32, n_i <= 64.
 
     Outputs Q_i (column-major, same dtype) and R_i (n_i x n_i) are allocated here; `run()` enqueues
-    the launch on the current stream and allocates nothing, so it can be captured in a graph."""
+    the launch on the current stream and allocates nothing, so it can be captured in a graph.
+    `tuning`: a BatchTuning (tile shape per (m bucket, n class), workgroups per compute unit, order);
+    None takes the table checked in beside the library for this storage type, else the built-in one."""
 
-    def __init__(self, As, Zs, tile: int = 0, shift_c: float = 1.0, max_retries: int = 3, q_in_place=False):
+    def __init__(self, As, Zs, tuning: Optional[BatchTuning] = None, shift_c: float = 1.0, max_retries: int = 3,
+                 q_in_place=False):
         torch = _torch()
         if len(As) != len(Zs) or not As:
             raise ValueError("need as many A_i as Z_i, at least one")
@@ -331,43 +387,88 @@ class BatchPlan:
             it.lda, it.ldz, it.ldq, it.ldr = m, _ld(z), _ld(q), _ld(r)
             it.m, it.n = m, n
             max_m, max_n = max(max_m, m), max(max_n, n)
+        self._items_host = items
         raw = bytes(items)
         self.items = torch.frombuffer(bytearray(raw), dtype=torch.uint8).to(self.device)
-        self.batch, self.max_m, self.max_n, self.tile = len(As), max_m, max_n, int(tile)
+        self.batch, self.max_m, self.max_n = len(As), max_m, max_n
+        if tuning is None:
+            tuning = stored_batch_tuning("f64" if self.dtype == OQR_F64 else "f32") or default_batch_tuning()
+        self.tuning = tuning
         self.opts = make_opts(shift_c=shift_c, max_retries=max_retries)
         L = lib()
         nbytes = L.oqr_batched_workspace_bytes(self.batch, max_m, max_n, self.dtype)
         self.ws = torch.empty(max(int(nbytes), 256), dtype=torch.uint8, device=self.device)
         self.info = torch.zeros(self.batch, dtype=torch.int32, device=self.device)
 
-    def autotune(self, reps: int = 3) -> dict:
-        """Time every tile configuration of the library on this batch (`reps` launches each, HIP
-        events around the batched kernel), keep the fastest in `self.tile` and return
-        {tile id: average ms}.  Inputs are read only; outputs are overwritten."""
-        torch = _torch()
-        times = {}
-        for tl in range(1, batch_tile_count() + 1):
-            self.run(tile=tl)
-            torch.cuda.synchronize()
-            with KernelTimer("batch") as kt:
-                for _ in range(reps):
-                    self.run(tile=tl)
-                torch.cuda.synchronize()
-            times[tl] = kt.avg_ms
-        self.tile = min(times, key=times.get)
-        return times
-
-    def run(self, stream=None, tile=None):
+    def _launch(self, items, count, info, tuning, stream=None):
         torch = _torch()
         s = stream if stream is not None else torch.cuda.current_stream(self.device).cuda_stream
-        rc = lib().oqr_cholqr2_batched(self.batch, self.items.data_ptr(), self.dtype, self.max_m, self.max_n,
-                                       ctypes.byref(self.opts), self.tile if tile is None else int(tile),
-                                       self.ws.data_ptr(), self.ws.numel(), self.info.data_ptr(), s)
+        rc = lib().oqr_cholqr2_batched(count, items.data_ptr(), self.dtype, self.max_m, self.max_n,
+                                       ctypes.byref(self.opts), ctypes.byref(tuning), self.ws.data_ptr(),
+                                       self.ws.numel(), info.data_ptr(), s)
         _raise(rc, "oqr_cholqr2_batched")
 
+    def run(self, stream=None, tuning: Optional[BatchTuning] = None):
+        self._launch(self.items, self.batch, self.info, tuning or self.tuning, stream)
 
-def batch_tile_count() -> int:
-    return int(lib().oqr_batched_tile_count())
+    def _time(self, items, count, info, tuning, reps):
+        torch = _torch()
+        self._launch(items, count, info, tuning)
+        torch.cuda.synchronize()
+        with KernelTimer("batch") as kt:
+            for _ in range(reps):
+                self._launch(items, count, info, tuning)
+            torch.cuda.synchronize()
+        return kt.avg_ms
+
+    def autotune(self, reps: int = 3) -> dict:
+        """Choose the tuning on this batch: for every (m bucket, n class) that holds instances, launch
+        those instances alone with each tile shape (`reps` timed launches each, HIP events around the
+        batched kernel) and keep the fastest shape; then time the whole batch with 1, 2 and 3 workgroups
+        per compute unit (largest instances first) and keep the fastest.  Inputs are read only; outputs
+        are overwritten.  Sets and returns `self.tuning` with the timings in a dict."""
+        torch = _torch()
+        classes = {}
+        for k in range(self.batch):
+            it = self._items_host[k]
+            classes.setdefault((batch_m_bucket(it.m), batch_n_class(it.n)), []).append(k)
+        tu = BatchTuning.from_dict(self.tuning.to_dict())
+        report = {"classes": {}, "wg_per_cu": {}}
+        for (b, c), idx in sorted(classes.items()):
+            sub = (BatchItem * len(idx))(*[self._items_host[k] for k in idx])
+            sub_items = torch.frombuffer(bytearray(bytes(sub)), dtype=torch.uint8).to(self.device)
+            sub_info = torch.zeros(len(idx), dtype=torch.int32, device=self.device)
+            times = {}
+            for shp in range(BATCH_SHAPES):
+                trial = BatchTuning.from_dict(tu.to_dict())
+                trial.shape[b][c] = shp
+                times[shp] = self._time(sub_items, len(idx), sub_info, trial, reps)
+            best = min(times, key=times.get)
+            tu.shape[b][c] = best
+            report["classes"][f"m{b}_n{c}"] = {"count": len(idx), "ms": {BATCH_SHAPE_NAMES[k]: round(v, 4)
+                                                                      for k, v in times.items()},
+                                               "shape": BATCH_SHAPE_NAMES[best]}
+        for wg in (1, 2, 3):
+            trial = BatchTuning.from_dict(tu.to_dict())
+            trial.wg_per_cu, trial.sort = wg, 1
+            report["wg_per_cu"][wg] = round(self._time(self.items, self.batch, self.info, trial, reps), 4)
+        tu.wg_per_cu, tu.sort = min(report["wg_per_cu"], key=report["wg_per_cu"].get), 1
+        self.tuning = tu
+        report["tuning"] = tu.to_dict()
+        return report
+
+
+def save_batch_tuning(tuning: BatchTuning, dtype: str, path: str = TUNING_PATH) -> None:
+    """Store `tuning` for storage `dtype` ("f64" or "f32") in the JSON table at `path` (merged)."""
+    import json
+    d = {}
+    if os.path.exists(path):
+        with open(path) as f:
+            d = json.load(f)
+    d[dtype] = tuning.to_dict()
+    with open(path, "w") as f:
+        json.dump(d, f, indent=1)
+        f.write("\n")
 
 
 def _run(alg, A, Z, **opts):

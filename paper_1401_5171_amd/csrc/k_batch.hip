@@ -20,9 +20,15 @@ namespace {
 
 constexpr int NT = 256;
 constexpr int NB = 64;        // max n
-constexpr int BR = 128;       // rows of A per row block
-constexpr int BK = 32;        // K step of the A X product
+constexpr int BR = 128;       // largest row block (rows of A per block of W)
+constexpr int BK = 32;        // largest K step of the A X product
 constexpr int LD = NB + 1;
+
+// Tile shapes of the Gram phase, chosen per instance from the tuning table: rows per row block and
+// K step.  Shape id s: BR_OF[s] x BK_OF[s].
+constexpr int NSHAPES = OQR_BATCH_SHAPES;
+constexpr int BR_OF[NSHAPES] = {128, 64, 128, 64};
+constexpr int BK_OF[NSHAPES] = {32, 32, 16, 16};
 
 constexpr double U64 = 1.1102230246251565e-16;
 
@@ -58,7 +64,8 @@ template <> struct Raw<float> {
 };
 
 struct Tiles {
-  double As[BK][BR + 1];      // A tile: As[k][i] (odd stride: conflict-free MFMA operand reads)
+  double As[BK * (BR + 1)];   // A tile of the current shape: As[k (BR_ + 1) + i] (odd stride: conflict-free
+                              // MFMA operand reads)
   double Xs[BK][LD];          // X tile: Xs[k][j]
 };
 struct Fact {
@@ -85,14 +92,18 @@ struct Smem {
 // B layout, one K step per accumulator element).
 // Wave w owns the 16 columns cb = w % CLS of W and G and the row group rg = w / CLS of each row block
 // (RG = 4 / CLS groups of 16 * RBW rows).  On return, waves of row group 0 hold G(:, 16 cb ..) in g.
-template <class T, int CLS>
+template <class T, int CLS, int BR_, int BK_>
 __device__ __noinline__ void gram_phase(const T* A_, int64_t lda_, const T* X_, int64_t ldx_, int m_, int n_, Smem& S,
                                         f64x4 (&g_out)[4]) {
   const T* A = uni(A_);
   const T* X = uni(X_);
   const int64_t lda = uni(lda_), ldx = uni(ldx_);
   const int m = uni(m_), n = uni(n_);
-  constexpr int RG = 4 / CLS, RBW = BR / 16 / RG;
+  static_assert(BR_ % 64 == 0 && BR_ <= BR && BK_ <= BK && BK_ % 4 == 0, "tile shape");
+  constexpr int RG = 4 / CLS, RBW = BR_ / 16 / RG;
+  constexpr int ASTR = BR_ + 1;                // LDS stride of the A tile
+  constexpr int KSTR = NT / BR_;               // K rows loaded per pass of the workgroup
+  constexpr int XSTR = NT / BK_;               // X columns loaded per pass
   const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
   const int li = lane >> 4, lj = lane & 15;
   const int cb = wave % CLS, rg = wave / CLS;
@@ -102,25 +113,26 @@ __device__ __noinline__ void gram_phase(const T* A_, int64_t lda_, const T* X_, 
                                                // that they stay in registers
 #pragma unroll
   for (int b = 0; b < 4; ++b) g[b] = h[b] = f64x4{0, 0, 0, 0};
-  // tile loads: A 16 values per thread (row t % BR, k = t / BR + 2q), X 8 values (k = t % BK, col t / BK + 8q),
-  // unconditional buffer loads (elements outside the matrix read as 0), consumed only at the next LDS store
-  const int ai = t % BR, ak = uni(t / BR);     // ak is wave-uniform (BR > 64)
-  const int xk = t % BK, xj = t / BK;
+  // tile loads: A BR_ BK_ / NT values per thread (row t % BR_, k = t / BR_ + KSTR q), X BK_ NB / NT values
+  // (k = t % BK_, col t / BK_ + XSTR q), unconditional buffer loads (elements outside the matrix read as
+  // 0), consumed only at the next LDS store
+  const int ai = t % BR_, ak = uni(t / BR_);   // ak is wave-uniform (BR_ >= 64)
+  const int xk = t % BK_, xj = t / BK_;
   typedef typename Raw<T>::type RT;
   const bufrsrc abuf = make_buf(A, ((int64_t)(m - 1) * lda + m) * (int64_t)sizeof(T));
   const bufrsrc xbuf = make_buf(X, ((int64_t)(n - 1) * ldx + m) * (int64_t)sizeof(T));
-  RT ra[BR * BK / NT], rx[BK * NB / NT];
-  for (int r0 = 0; r0 < m; r0 += BR) {
+  RT ra[BR_ * BK_ / NT], rx[BK_ * NB / NT];
+  for (int r0 = 0; r0 < m; r0 += BR_) {
     auto load = [&](int k0) {
       const bool rok = r0 + ai < m;
 #pragma unroll
-      for (int q = 0; q < BR * BK / NT; ++q) {
-        const int k = k0 + ak + 2 * q;
+      for (int q = 0; q < BR_ * BK_ / NT; ++q) {
+        const int k = k0 + ak + KSTR * q;
         ra[q] = Raw<T>::load(abuf, (int64_t)k * lda + r0 + ai, rok && k < m);
       }
 #pragma unroll
-      for (int q = 0; q < BK * NB / NT; ++q) {
-        const int j = xj + 8 * q, k = k0 + xk;
+      for (int q = 0; q < BK_ * NB / NT; ++q) {
+        const int j = xj + XSTR * q, k = k0 + xk;
         rx[q] = Raw<T>::load(xbuf, (int64_t)j * ldx + k, j < n && k < m);
       }
     };
@@ -128,13 +140,13 @@ __device__ __noinline__ void gram_phase(const T* A_, int64_t lda_, const T* X_, 
 #pragma unroll
     for (int b = 0; b < RBW; ++b) w[b] = f64x4{0, 0, 0, 0};
     // dst += X_b^T W_b over this wave's rows.  X_b (the row block's rows of X) is staged through LDS
-    // in two halves of 64 rows, each one coalesced load (a wave per column, 64 rows) and one barrier,
+    // in halves of 64 rows, each one coalesced load (a wave per column, 64 rows) and one barrier,
     // so that the products wait for two memory round trips per call rather than one per 16-row block.
     // The tiles of the K loop are dead here (every K step ends with a barrier) and the halves overlay
     // them; the trailing barrier protects the half from the next K step's tile stores.
     auto accum = [&](f64x4 (&dst)[4]) {
 #pragma unroll
-      for (int hf = 0; hf < 2; ++hf) {
+      for (int hf = 0; hf < BR_ / 64; ++hf) {
         const int xi = t & 63, xw = uni(t >> 6);   // one column per wave
         RT xv[4 * CLS];
 #pragma unroll
@@ -161,33 +173,33 @@ __device__ __noinline__ void gram_phase(const T* A_, int64_t lda_, const T* X_, 
         __syncthreads();
       }
     };
-    const int dend = min(m, r0 + BR);          // end of the diagonal block
+    const int dend = min(m, r0 + BR_);         // end of the diagonal block
     auto kstep = [&](int k0) {
 #pragma unroll
-      for (int q = 0; q < BR * BK / NT; ++q) S.tl.As[ak + 2 * q][ai] = (double)ra[q];
+      for (int q = 0; q < BR_ * BK_ / NT; ++q) S.tl.As[(ak + KSTR * q) * ASTR + ai] = (double)ra[q];
 #pragma unroll
-      for (int q = 0; q < BK * NB / NT; ++q) S.tl.Xs[xk][xj + 8 * q] = (double)rx[q];
+      for (int q = 0; q < BK_ * NB / NT; ++q) S.tl.Xs[xk][xj + XSTR * q] = (double)rx[q];
       __syncthreads();
-      load(k0 + BK);                          // in flight during the MFMAs below (past the end: zeros)
+      load(k0 + BK_);                         // in flight during the MFMAs below (past the end: zeros)
       if (active) {
 #pragma unroll
-        for (int kk = 0; kk < BK; kk += 4) {
+        for (int kk = 0; kk < BK_; kk += 4) {
           const double b = S.tl.Xs[kk + li][16 * cb + lj];
 #pragma unroll
           for (int rb = 0; rb < RBW; ++rb)
-            w[rb] = mfma_f64(S.tl.As[kk + li][16 * RBW * rg + 16 * rb + lj], b, w[rb]);
+            w[rb] = mfma_f64(S.tl.As[(kk + li) * ASTR + 16 * RBW * rg + 16 * rb + lj], b, w[rb]);
           __builtin_amdgcn_sched_barrier(0);   // operand reads of one K sub-step only: no hoisting
         }
       }
       __syncthreads();
     };
     load(r0);
-    for (int k0 = r0; k0 < dend; k0 += BK) kstep(k0);
+    for (int k0 = r0; k0 < dend; k0 += BK_) kstep(k0);
     accum(g);                                  // D += X_b^T (A_b,diag X_b)
     if (dend < m) {
 #pragma unroll
       for (int b = 0; b < RBW; ++b) w[b] = f64x4{0, 0, 0, 0};
-      for (int k0 = dend; k0 < m; k0 += BK) kstep(k0);
+      for (int k0 = dend; k0 < m; k0 += BK_) kstep(k0);
       accum(h);                                // H += X_b^T (A_b,right X)
     }
   }
@@ -239,23 +251,36 @@ __device__ __noinline__ void gram_phase(const T* A_, int64_t lda_, const T* X_, 
 
 // One CHOLQR pass on instance (A, X) in place: X <- X R^{-1}, R into smem Gs (upper, zero lower).
 // Returns 0 or the failing pivot (1-based).
+template <class T, int CLS>
+__device__ __forceinline__ void gram_shape(int shape, const T* A, int64_t lda, const T* X, int64_t ldx, int m, int n,
+                                           Smem& S, f64x4 (&g)[4]) {
+  switch (shape) {
+    case 1: gram_phase<T, CLS, BR_OF[1], BK_OF[1]>(A, lda, X, ldx, m, n, S, g); break;
+    case 2: gram_phase<T, CLS, BR_OF[2], BK_OF[2]>(A, lda, X, ldx, m, n, S, g); break;
+    case 3: gram_phase<T, CLS, BR_OF[3], BK_OF[3]>(A, lda, X, ldx, m, n, S, g); break;
+    default: gram_phase<T, CLS, BR_OF[0], BK_OF[0]>(A, lda, X, ldx, m, n, S, g); break;
+  }
+}
+
 template <class T>
 __device__ __noinline__ int cholqr_pass_wg(const T* A, int64_t lda, const T* Xin, int64_t ldxin, T* X, int64_t ldx, int m,
-                              int n, double unit, double c_first, double c_retry, int max_retries, Smem& S) {
+                              int n, int shape, double unit, double c_first, double c_retry, int max_retries,
+                              Smem& S) {
   const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
   const int li = lane >> 4, lj = lane & 15;
   // ---- G = X^T A X ----------------------------------------------------------------------------
   f64x4 g[4];                                 // waves of row group 0: G(16 gi + .., 16 cb + ..)
   const int nbk = (n + 15) / 16;
+  shape = uni(shape);
   int cls;
   if (nbk <= 1) {
-    gram_phase<T, 1>(A, lda, Xin, ldxin, m, n, S, g);
+    gram_shape<T, 1>(shape, A, lda, Xin, ldxin, m, n, S, g);
     cls = 1;
   } else if (nbk == 2) {
-    gram_phase<T, 2>(A, lda, Xin, ldxin, m, n, S, g);
+    gram_shape<T, 2>(shape, A, lda, Xin, ldxin, m, n, S, g);
     cls = 2;
   } else {
-    gram_phase<T, 4>(A, lda, Xin, ldxin, m, n, S, g);
+    gram_shape<T, 4>(shape, A, lda, Xin, ldxin, m, n, S, g);
     cls = 4;
   }
   const bool owner = wave < cls && wave < nbk;   // waves holding a column block of G
@@ -396,11 +421,23 @@ __device__ __forceinline__ bool item_ok(const oqr_batch_item& it, int max_m) {
   return (m - 1) * it.lda + m <= lim && (n - 1) * it.ldz + m <= lim && (n - 1) * it.ldq + m <= lim;
 }
 
+// Tile shape of an instance: the tuning table's entry for its m bucket and n class.
+__host__ __device__ inline int m_bucket(int m) {
+  int b = 0;
+  for (int lim = 512; b < OQR_BATCH_MBUCKETS - 1 && m >= lim; lim <<= 1) ++b;
+  return b;
+}
+__host__ __device__ inline int n_class(int n) { return n <= 8 ? 0 : n <= 16 ? 1 : n <= 32 ? 2 : 3; }
+
+struct ShapeTable {
+  uint8_t s[OQR_BATCH_MBUCKETS][OQR_BATCH_NCLASSES];
+};
+
 template <class T>
 __global__ __launch_bounds__(NT, 2) void batch_kernel(const oqr_batch_item* __restrict__ items,
                                                     const int32_t* __restrict__ order, int batch, int max_m,
                                                     int32_t* __restrict__ counter, int32_t* __restrict__ info,
-                                                    double c_retry, int max_retries) {
+                                                    double c_retry, int max_retries, ShapeTable shapes) {
   __shared__ Smem S;
   const int t = threadIdx.x;
   for (;;) {
@@ -421,8 +458,9 @@ __global__ __launch_bounds__(NT, 2) void batch_kernel(const oqr_batch_item* __re
     T* Q = (T*)it.q;
     T* R = (T*)it.r;
     const int m = it.m, n = it.n;
+    const int shape = shapes.s[m_bucket(m)][n_class(n)];
     // pass 1 (Z -> Q), pass 2 (Q in place); both FP64 arithmetic
-    int f = cholqr_pass_wg<T>(A, it.lda, Z, it.ldz, Q, it.ldq, m, n, U64, 0.0, c_retry, max_retries, S);
+    int f = cholqr_pass_wg<T>(A, it.lda, Z, it.ldz, Q, it.ldq, m, n, shape, U64, 0.0, c_retry, max_retries, S);
     if (f) {
       if (t == 0) info[id] = f;
       __syncthreads();
@@ -434,7 +472,7 @@ __global__ __launch_bounds__(NT, 2) void batch_kernel(const oqr_batch_item* __re
       R[(int64_t)j * it.ldr + i] = (T)S.f.Gs[i][j];
     }
     __syncthreads();
-    f = cholqr_pass_wg<T>(A, it.lda, Q, it.ldq, Q, it.ldq, m, n, U64, 0.0, c_retry, max_retries, S);
+    f = cholqr_pass_wg<T>(A, it.lda, Q, it.ldq, Q, it.ldq, m, n, shape, U64, 0.0, c_retry, max_retries, S);
     if (f) {
       if (t == 0) info[id] = f;
       __syncthreads();
@@ -508,12 +546,16 @@ __global__ void identity_order_kernel(int batch, int32_t* order, int32_t* counte
   if (i == 0) counter[0] = 0;
 }
 
-struct TileCfg {
-  int wg_per_cu;
-  int sort;
-};
-const TileCfg kTiles[] = {{2, 1}, {1, 1}, {2, 1}, {3, 1}, {2, 0}};   // id 0 = default
-constexpr int kNumTiles = 4;                                          // ids 1..4
+// Built-in tuning (used when the caller passes none): two workgroups per compute unit, largest instances
+// first, the 128 x 32 shape for every class.
+oqr_batch_tuning builtin_tuning() {
+  oqr_batch_tuning tu;
+  tu.wg_per_cu = 2;
+  tu.sort = 1;
+  for (int b = 0; b < OQR_BATCH_MBUCKETS; ++b)
+    for (int c = 0; c < OQR_BATCH_NCLASSES; ++c) tu.shape[b][c] = 0;
+  return tu;
+}
 
 }  // namespace
 }  // namespace oqr
@@ -522,7 +564,9 @@ using namespace oqr;
 
 extern "C" {
 
-int oqr_batched_tile_count(void) { return kNumTiles; }
+void oqr_batched_default_tuning(oqr_batch_tuning* tuning) {
+  if (tuning) *tuning = builtin_tuning();
+}
 
 size_t oqr_batched_workspace_bytes(int64_t batch, int32_t max_m, int32_t max_n, int32_t dtype) {
   (void)max_m;
@@ -533,13 +577,20 @@ size_t oqr_batched_workspace_bytes(int64_t batch, int32_t max_m, int32_t max_n, 
 }
 
 int oqr_cholqr2_batched(int64_t batch, const oqr_batch_item* items_dev, int32_t dtype, int32_t max_m, int32_t max_n,
-                        const oqr_opts* opts, int32_t tile, void* ws, size_t ws_bytes, int32_t* info_dev,
-                        void* stream) {
+                        const oqr_opts* opts, const oqr_batch_tuning* tuning, void* ws, size_t ws_bytes,
+                        int32_t* info_dev, void* stream) {
   if (batch < 0 || batch > (1 << 30)) return OQR_E_ARG;
   if (batch == 0) return OQR_OK;
   if (!items_dev || !info_dev || max_m < 1 || max_n < 1 || max_n > NB || max_m < max_n) return OQR_E_ARG;
   if (dtype != OQR_F64 && dtype != OQR_F32) return OQR_E_ARG;
-  if (tile < 0 || tile > kNumTiles) return OQR_E_ARG;
+  const oqr_batch_tuning tu = tuning ? *tuning : builtin_tuning();
+  if (tu.wg_per_cu < 1 || tu.wg_per_cu > 3 || (tu.sort != 0 && tu.sort != 1)) return OQR_E_ARG;
+  ShapeTable shapes;
+  for (int b = 0; b < OQR_BATCH_MBUCKETS; ++b)
+    for (int c = 0; c < OQR_BATCH_NCLASSES; ++c) {
+      if (tu.shape[b][c] >= NSHAPES) return OQR_E_ARG;
+      shapes.s[b][c] = tu.shape[b][c];
+    }
   oqr_opts o;
   if (opts) o = *opts;
   else oqr_default_opts(&o);
@@ -550,23 +601,22 @@ int oqr_cholqr2_batched(int64_t batch, const oqr_batch_item* items_dev, int32_t 
   hipStream_t s = (hipStream_t)stream;
   int32_t* counter = (int32_t*)ws;
   int32_t* order = (int32_t*)((char*)ws + align256(sizeof(int32_t) * 64));
-  const TileCfg cfg = kTiles[tile];
-  if (cfg.sort && batch <= SORT_MAX)
+  if (tu.sort && batch <= SORT_MAX)
     order_kernel<<<1, 1024, 0, s>>>(items_dev, (int)batch, order, counter, info_dev);
   else
     identity_order_kernel<<<(unsigned)((batch + 255) / 256), 256, 0, s>>>((int)batch, order, counter, info_dev);
   if (hipGetLastError() != hipSuccess) return OQR_E_HIP;
   // compute-unit count, queried once per device (outside any graph capture: the first call)
   const int cus = device_cu_count();
-  int64_t grid = (int64_t)cus * cfg.wg_per_cu;
+  int64_t grid = (int64_t)cus * tu.wg_per_cu;
   if (grid > batch) grid = batch;
   trace_pre(K_BATCH, s);
   if (dtype == OQR_F64)
     batch_kernel<double><<<(unsigned)grid, NT, 0, s>>>(items_dev, order, (int)batch, max_m, counter, info_dev,
-                                                       o.shift_c, o.max_retries);
+                                                       o.shift_c, o.max_retries, shapes);
   else
     batch_kernel<float><<<(unsigned)grid, NT, 0, s>>>(items_dev, order, (int)batch, max_m, counter, info_dev,
-                                                      o.shift_c, o.max_retries);
+                                                      o.shift_c, o.max_retries, shapes);
   const hipError_t e = hipGetLastError();
   trace_post(K_BATCH, s);
   return e == hipSuccess ? OQR_OK : OQR_E_HIP;

@@ -61,18 +61,62 @@ def test_batch_fp64_matches_oracle():
     check_fp64(insts, plan)
 
 
-@pytest.mark.parametrize("tile", [1, 2, 3, 4])
-def test_batch_every_tile_gives_the_same_bits(tile):
+def _tuning(shape=None, wg=None, sort=None):
+    t = oqr.default_batch_tuning()
+    d = t.to_dict()
+    if shape is not None:
+        d["shape"] = [[shape] * oqr.BATCH_NCLASSES for _ in range(oqr.BATCH_MBUCKETS)]
+    if wg is not None:
+        d["wg_per_cu"] = wg
+    if sort is not None:
+        d["sort"] = sort
+    return oqr.BatchTuning.from_dict(d)
+
+
+@pytest.mark.parametrize("shape", [0, 1, 2, 3])
+def test_batch_every_tile_shape_matches_oracle(shape):
+    """Each Gram-phase tile shape (128 x 32, 64 x 32, 128 x 16, 64 x 16 rows x K step) on every
+    instance: results against CHOL-EQR, and two runs bit for bit equal (fixed order of the sums)."""
+    insts = make_batch(24, seed=8, extra_n=(1, 7, 33))
+    As, Zs = upload(insts, np.float64)
+    plan = oqr.BatchPlan(As, Zs, tuning=_tuning(shape=shape))
+    banner(f"batch tile shape {oqr.BATCH_SHAPE_NAMES[shape]}")
+    plan.run()
+    torch.cuda.synchronize()
+    check_fp64(insts, plan)
+    q1 = [q.clone() for q in plan.Qs]
+    plan.run()
+    torch.cuda.synchronize()
+    for k in range(len(insts)):
+        assert torch.equal(plan.Qs[k], q1[k])
+
+
+@pytest.mark.parametrize("wg,sort", [(1, 1), (3, 1), (2, 0)])
+def test_batch_launch_configuration_keeps_the_bits(wg, sort):
+    """Workgroups per compute unit and the order instances are taken in do not change any sum."""
     insts = make_batch(24, seed=8)
     As, Zs = upload(insts, np.float64)
-    ref = oqr.BatchPlan(As, Zs, tile=0)
+    ref = oqr.BatchPlan(As, Zs, tuning=_tuning(shape=1))
     ref.run()
-    plan = oqr.BatchPlan(As, Zs, tile=tile)
-    banner(f"batch tile {tile}")
+    plan = oqr.BatchPlan(As, Zs, tuning=_tuning(shape=1, wg=wg, sort=sort))
+    banner(f"batch wg_per_cu={wg} sort={sort}")
     plan.run()
     torch.cuda.synchronize()
     for k in range(len(insts)):
         assert torch.equal(plan.Qs[k], ref.Qs[k]) and torch.equal(plan.Rs[k], ref.Rs[k])
+
+
+def test_batch_bucket_table_selects_per_class():
+    """A table with a different shape per (m bucket, n class): every instance still matches the oracle."""
+    insts = make_batch(32, m_lo=200, m_hi=1100, seed=14)
+    As, Zs = upload(insts, np.float64)
+    d = oqr.default_batch_tuning().to_dict()
+    d["shape"] = [[(b + c) % oqr.BATCH_SHAPES for c in range(oqr.BATCH_NCLASSES)] for b in range(oqr.BATCH_MBUCKETS)]
+    plan = oqr.BatchPlan(As, Zs, tuning=oqr.BatchTuning.from_dict(d))
+    banner("batch mixed shape table")
+    plan.run()
+    torch.cuda.synchronize()
+    check_fp64(insts, plan)
 
 
 def test_batch_fp32_storage():
@@ -195,20 +239,38 @@ def test_graph_capture_replays_match_eager():
             assert torch.equal(plan.Qs[k], eager_q[k]) and torch.equal(plan.Rs[k], eager_r[k]), (rep, k)
 
 
-def test_autotune_picks_a_tile_and_keeps_the_bits():
-    """BatchPlan.autotune times every tile configuration on the caller's batch and keeps the fastest;
-    the outputs after tuning equal those of the default configuration bit for bit."""
+def test_autotune_picks_shapes_and_results_hold():
+    """BatchPlan.autotune times the four tile shapes on each (m bucket, n class) present and the
+    workgroups per compute unit, keeps the fastest; the tuned launch still matches the oracle and
+    repeats its bits."""
     insts = make_batch(24, seed=9)
     As, Zs = upload(insts, np.float64)
-    ref = oqr.BatchPlan(As, Zs, tile=0)
-    ref.run()
-    plan = oqr.BatchPlan(As, Zs)
+    plan = oqr.BatchPlan(As, Zs, tuning=oqr.default_batch_tuning())
     banner("batch autotune")
-    times = plan.autotune(reps=2)
-    assert sorted(times) == list(range(1, oqr.batch_tile_count() + 1))
-    assert all(t > 0 for t in times.values())
-    assert plan.tile == min(times, key=times.get)
+    rep = plan.autotune(reps=2)
+    classes = {(oqr.batch_m_bucket(z.shape[0]), oqr.batch_n_class(z.shape[1])) for _, z in insts}
+    assert len(rep["classes"]) == len(classes)
+    for (b, c) in classes:
+        e = rep["classes"][f"m{b}_n{c}"]
+        assert set(e["ms"]) == set(oqr.BATCH_SHAPE_NAMES) and all(v > 0 for v in e["ms"].values())
+        assert e["shape"] == min(e["ms"], key=e["ms"].get)
+        assert oqr.BATCH_SHAPE_NAMES[plan.tuning.shape[b][c]] == e["shape"]
+    assert plan.tuning.wg_per_cu == min(rep["wg_per_cu"], key=rep["wg_per_cu"].get)
+    plan.run()
+    torch.cuda.synchronize()
+    check_fp64(insts, plan)
+    q1 = [q.clone() for q in plan.Qs]
     plan.run()
     torch.cuda.synchronize()
     for k in range(len(insts)):
-        assert torch.equal(plan.Qs[k], ref.Qs[k]) and torch.equal(plan.Rs[k], ref.Rs[k])
+        assert torch.equal(plan.Qs[k], q1[k])
+
+
+def test_stored_tuning_table_is_valid():
+    """The tuning table checked in beside the library parses into the launch's limits."""
+    for dtype in ("f64", "f32"):
+        t = oqr.stored_batch_tuning(dtype)
+        assert t is not None, dtype
+        assert 1 <= t.wg_per_cu <= 3 and t.sort in (0, 1)
+        assert all(0 <= t.shape[b][c] < oqr.BATCH_SHAPES
+                   for b in range(oqr.BATCH_MBUCKETS) for c in range(oqr.BATCH_NCLASSES))
