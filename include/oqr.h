@@ -262,7 +262,9 @@ typedef struct oqr_batch_item {
  * on the device before anything of the instance is read or written. */
 enum { OQR_BATCH_BAD_ITEM = -1 };
 
-/* Workspace bytes for oqr_cholqr2_batched. */
+/* Workspace bytes for oqr_cholqr2_batched: a few int32 per instance plus the
+ * partial Grams of up to min(batch, 512) cooperative instances (8 parts of
+ * 32 KiB each), about 256 KiB per instance up to 128 MiB in all. */
 size_t oqr_batched_workspace_bytes(int64_t batch, int32_t max_m, int32_t max_n, int32_t dtype);
 
 /* Tuning of the batched launch.  Instances are classed by m (buckets
@@ -282,16 +284,25 @@ typedef struct oqr_batch_tuning {
   int32_t wg_per_cu;
   int32_t sort;
   uint8_t shape[OQR_BATCH_MBUCKETS][OQR_BATCH_NCLASSES];
+  /* Cooperative instances: with split_m > 0 (and sort = 1, batch <= 8192), up
+   * to 512 of the largest instances with m >= split_m run each pass as `parts`
+   * workgroups (1..8) over interleaved row blocks, their partial Grams summed
+   * in part order by one workgroup that then factors and solves; the other
+   * instances run in the persistent launch.  0 = no split. */
+  int32_t split_m;
+  int32_t parts;
 } oqr_batch_tuning;
 
 /* Fills *tuning with the built-in configuration (2 workgroups per compute
- * unit, sorted, shape 0 for every class), used when NULL is passed. */
+ * unit, sorted, shape 0 for every class, no split), used when NULL is passed. */
 void oqr_batched_default_tuning(oqr_batch_tuning* tuning);
 
 /* Batched CholQR2-A over `batch` independent dense instances in one
  * persistent launch: workgroups take instances from a device work queue
  * (largest first), each instance runs both passes inside one workgroup with
  * FP64 Gram accumulation, Cholesky (shift/retry as in opts) and substitution.
+ * Cooperative instances (tuning split_m > 0) run before it in four staged
+ * launches (Gram parts, then sum + Cholesky + substitution, for each pass).
  * items_dev: device array of `batch` items with 1 <= n_i <= max_n <= 64,
  * n_i <= m_i <= max_m, non-null pointers, lda >= m_i, ldz >= m_i, ldq >= m_i,
  * ldr >= n_i, and A_i, Z_i and Q_i each spanning at most 2^31 - 1 bytes

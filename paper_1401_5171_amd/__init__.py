@@ -64,11 +64,13 @@ TUNING_PATH = os.path.join(_HERE, "batch_tuning.json")
 
 class BatchTuning(ctypes.Structure):
     _fields_ = [("wg_per_cu", ctypes.c_int32), ("sort", ctypes.c_int32),
-                ("shape", (ctypes.c_uint8 * BATCH_NCLASSES) * BATCH_MBUCKETS)]
+                ("shape", (ctypes.c_uint8 * BATCH_NCLASSES) * BATCH_MBUCKETS),
+                ("split_m", ctypes.c_int32), ("parts", ctypes.c_int32)]
 
     def to_dict(self):
         return {"wg_per_cu": int(self.wg_per_cu), "sort": int(self.sort),
-                "shape": [[int(self.shape[b][c]) for c in range(BATCH_NCLASSES)] for b in range(BATCH_MBUCKETS)]}
+                "shape": [[int(self.shape[b][c]) for c in range(BATCH_NCLASSES)] for b in range(BATCH_MBUCKETS)],
+                "split_m": int(self.split_m), "parts": int(self.parts)}
 
     @classmethod
     def from_dict(cls, d):
@@ -77,6 +79,7 @@ class BatchTuning(ctypes.Structure):
         for b in range(BATCH_MBUCKETS):
             for c in range(BATCH_NCLASSES):
                 t.shape[b][c] = int(d["shape"][b][c])
+        t.split_m, t.parts = int(d.get("split_m", 0)), int(d.get("parts", 1))
         return t
 
 
@@ -424,8 +427,9 @@ class BatchPlan:
     def autotune(self, reps: int = 3) -> dict:
         """Choose the tuning on this batch: for every (m bucket, n class) that holds instances, launch
         those instances alone with each tile shape (`reps` timed launches each, HIP events around the
-        batched kernel) and keep the fastest shape; then time the whole batch with 1, 2 and 3 workgroups
-        per compute unit (largest instances first) and keep the fastest.  Inputs are read only; outputs
+        batched launch) and keep the fastest shape; then time the whole batch with 1, 2 and 3 workgroups
+        per compute unit (largest instances first), then with the largest instances split over several
+        workgroups (SPLIT_CANDIDATES: m threshold x parts, or none), keeping the fastest each time.  Inputs are read only; outputs
         are overwritten.  Sets and returns `self.tuning` with the timings in a dict."""
         torch = _torch()
         classes = {}
@@ -453,9 +457,21 @@ class BatchPlan:
             trial.wg_per_cu, trial.sort = wg, 1
             report["wg_per_cu"][wg] = round(self._time(self.items, self.batch, self.info, trial, reps), 4)
         tu.wg_per_cu, tu.sort = min(report["wg_per_cu"], key=report["wg_per_cu"].get), 1
+        # cooperative instances: the largest ones (m >= split_m) split over `parts` workgroups per pass
+        report["split"] = {}
+        for split_m, parts in self.SPLIT_CANDIDATES:
+            if split_m > self.max_m:
+                continue
+            trial = BatchTuning.from_dict(tu.to_dict())
+            trial.split_m, trial.parts = split_m, parts
+            report["split"][f"{split_m}x{parts}"] = round(self._time(self.items, self.batch, self.info, trial, reps), 4)
+        best = min(report["split"], key=report["split"].get)
+        tu.split_m, tu.parts = (int(v) for v in best.split("x"))
         self.tuning = tu
         report["tuning"] = tu.to_dict()
         return report
+
+    SPLIT_CANDIDATES = ((0, 1), (3584, 4), (3584, 8), (3072, 4), (3072, 8), (2048, 4), (2048, 8))
 
 
 def save_batch_tuning(tuning: BatchTuning, dtype: str, path: str = TUNING_PATH) -> None:

@@ -92,13 +92,17 @@ struct Smem {
 // B layout, one K step per accumulator element).
 // Wave w owns the 16 columns cb = w % CLS of W and G and the row group rg = w / CLS of each row block
 // (RG = 4 / CLS groups of 16 * RBW rows).  On return, waves of row group 0 hold G(:, 16 cb ..) in g.
-template <class T, int CLS, int BR_, int BK_>
-__device__ __noinline__ void gram_phase(const T* A_, int64_t lda_, const T* X_, int64_t ldx_, int m_, int n_, Smem& S,
-                                        f64x4 (&g_out)[4]) {
+// SITE (0 persistent kernel, 1 split kernels) gives each calling kernel its own copy of these out-of-line
+// functions: a copy shared with the split kernels gets a register allocation that spills several hundred
+// bytes per lane in the wide shapes and runs the persistent launch 1.6x slower.
+template <class T, int CLS, int BR_, int BK_, int SITE>
+__device__ __noinline__ void gram_phase(const T* A_, int64_t lda_, const T* X_, int64_t ldx_, int m_, int n_,
+                                        int rb_first_, int rb_step_, Smem& S, f64x4 (&g_out)[4]) {
   const T* A = uni(A_);
   const T* X = uni(X_);
   const int64_t lda = uni(lda_), ldx = uni(ldx_);
   const int m = uni(m_), n = uni(n_);
+  const int rb_first = uni(rb_first_), rb_step = uni(rb_step_);   // row blocks rb_first, + rb_step, ...
   static_assert(BR_ % 64 == 0 && BR_ <= BR && BK_ <= BK && BK_ % 4 == 0, "tile shape");
   constexpr int RG = 4 / CLS, RBW = BR_ / 16 / RG;
   constexpr int ASTR = BR_ + 1;                // LDS stride of the A tile
@@ -122,7 +126,7 @@ __device__ __noinline__ void gram_phase(const T* A_, int64_t lda_, const T* X_, 
   const bufrsrc abuf = make_buf(A, ((int64_t)(m - 1) * lda + m) * (int64_t)sizeof(T));
   const bufrsrc xbuf = make_buf(X, ((int64_t)(n - 1) * ldx + m) * (int64_t)sizeof(T));
   RT ra[BR_ * BK_ / NT], rx[BK_ * NB / NT];
-  for (int r0 = 0; r0 < m; r0 += BR_) {
+  for (int r0 = rb_first * BR_; r0 < m; r0 += rb_step * BR_) {
     auto load = [&](int k0) {
       const bool rok = r0 + ai < m;
 #pragma unroll
@@ -251,38 +255,46 @@ __device__ __noinline__ void gram_phase(const T* A_, int64_t lda_, const T* X_, 
 
 // One CHOLQR pass on instance (A, X) in place: X <- X R^{-1}, R into smem Gs (upper, zero lower).
 // Returns 0 or the failing pivot (1-based).
-template <class T, int CLS>
+template <class T, int CLS, int SITE>
 __device__ __forceinline__ void gram_shape(int shape, const T* A, int64_t lda, const T* X, int64_t ldx, int m, int n,
-                                           Smem& S, f64x4 (&g)[4]) {
+                                           int rb_first, int rb_step, Smem& S, f64x4 (&g)[4]) {
   switch (shape) {
-    case 1: gram_phase<T, CLS, BR_OF[1], BK_OF[1]>(A, lda, X, ldx, m, n, S, g); break;
-    case 2: gram_phase<T, CLS, BR_OF[2], BK_OF[2]>(A, lda, X, ldx, m, n, S, g); break;
-    case 3: gram_phase<T, CLS, BR_OF[3], BK_OF[3]>(A, lda, X, ldx, m, n, S, g); break;
-    default: gram_phase<T, CLS, BR_OF[0], BK_OF[0]>(A, lda, X, ldx, m, n, S, g); break;
+    case 1: gram_phase<T, CLS, BR_OF[1], BK_OF[1], SITE>(A, lda, X, ldx, m, n, rb_first, rb_step, S, g); break;
+    case 2: gram_phase<T, CLS, BR_OF[2], BK_OF[2], SITE>(A, lda, X, ldx, m, n, rb_first, rb_step, S, g); break;
+    case 3: gram_phase<T, CLS, BR_OF[3], BK_OF[3], SITE>(A, lda, X, ldx, m, n, rb_first, rb_step, S, g); break;
+    default: gram_phase<T, CLS, BR_OF[0], BK_OF[0], SITE>(A, lda, X, ldx, m, n, rb_first, rb_step, S, g); break;
   }
 }
 
-template <class T>
-__device__ __noinline__ int cholqr_pass_wg(const T* A, int64_t lda, const T* Xin, int64_t ldxin, T* X, int64_t ldx, int m,
-                              int n, int shape, double unit, double c_first, double c_retry, int max_retries,
-                              Smem& S) {
-  const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
-  const int li = lane >> 4, lj = lane & 15;
-  // ---- G = X^T A X ----------------------------------------------------------------------------
-  f64x4 g[4];                                 // waves of row group 0: G(16 gi + .., 16 cb + ..)
+// G (or the part of G from the row blocks rb_first, rb_first + rb_step, ...) of instance (A, X) into the
+// accumulators g of the waves of row group 0 (column block cb = wave < cls); returns cls.
+template <class T, int SITE>
+__device__ __forceinline__ int gram_wg(const T* A, int64_t lda, const T* X, int64_t ldx, int m, int n, int shape,
+                                       int rb_first, int rb_step, Smem& S, f64x4 (&g)[4]) {
   const int nbk = (n + 15) / 16;
   shape = uni(shape);
-  int cls;
   if (nbk <= 1) {
-    gram_shape<T, 1>(shape, A, lda, Xin, ldxin, m, n, S, g);
-    cls = 1;
-  } else if (nbk == 2) {
-    gram_shape<T, 2>(shape, A, lda, Xin, ldxin, m, n, S, g);
-    cls = 2;
-  } else {
-    gram_shape<T, 4>(shape, A, lda, Xin, ldxin, m, n, S, g);
-    cls = 4;
+    gram_shape<T, 1, SITE>(shape, A, lda, X, ldx, m, n, rb_first, rb_step, S, g);
+    return 1;
   }
+  if (nbk == 2) {
+    gram_shape<T, 2, SITE>(shape, A, lda, X, ldx, m, n, rb_first, rb_step, S, g);
+    return 2;
+  }
+  gram_shape<T, 4, SITE>(shape, A, lda, X, ldx, m, n, rb_first, rb_step, S, g);
+  return 4;
+}
+
+// The rest of one CHOLQR pass from G in the accumulators g (waves wave < cls of row group 0):
+// R = chol(G + s I) with the shift-and-retry rule, R into smem Gs (upper, zero lower), then
+// X <- Xin R^{-1} (X may alias Xin).  Returns 0 or the failing pivot (1-based).
+template <class T, int SITE>
+__device__ __noinline__ int finish_wg(const f64x4 (&g)[4], int cls, const T* Xin, int64_t ldxin, T* X, int64_t ldx,
+                                      int m, int n, double unit, double c_first, double c_retry, int max_retries,
+                                      Smem& S) {
+  const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+  const int li = lane >> 4, lj = lane & 15;
+  const int nbk = (n + 15) / 16;
   const bool owner = wave < cls && wave < nbk;   // waves holding a column block of G
   const int cb = wave;
   // ---- R = chol(G + s I), retries from the accumulators ------------------------------------------
@@ -408,9 +420,28 @@ __device__ __noinline__ int cholqr_pass_wg(const T* A, int64_t lda, const T* Xin
   return 0;
 }
 
+// One CHOLQR pass on instance (A, Xin) into X: X <- Xin R^{-1}, R into smem Gs (upper, zero lower).
+// Returns 0 or the failing pivot (1-based).
+template <class T>
+__device__ __noinline__ int cholqr_pass_wg(const T* A, int64_t lda, const T* Xin, int64_t ldxin, T* X, int64_t ldx, int m,
+                                           int n, int shape, double unit, double c_first, double c_retry,
+                                           int max_retries, Smem& S) {
+  f64x4 g[4];
+  const int cls = gram_wg<T, 0>(A, lda, Xin, ldxin, m, n, shape, 0, 1, S, g);
+  return finish_wg<T, 0>(g, cls, Xin, ldxin, X, ldx, m, n, unit, c_first, c_retry, max_retries, S);
+}
+
 // An item the kernel can run: the documented shape limits, leading dimensions that hold the matrices,
 // and every operand within the byte range of a buffer resource (the streaming loads take 32-bit
 // offsets).  Checked before anything of the item is read, so a malformed item only sets its info.
+__host__ __device__ inline bool item_ok_size(const oqr_batch_item& it, int max_m, int64_t esize) {
+  const int64_t m = it.m, n = it.n, lim = 0x7fffffff / esize;
+  if (n < 1 || n > NB || m < n || m > max_m) return false;
+  if (!it.a || !it.z || !it.q || !it.r) return false;
+  if (it.lda < m || it.ldz < m || it.ldq < m || it.ldr < n) return false;
+  if (it.lda > lim || it.ldz > lim || it.ldq > lim || it.ldr > lim) return false;
+  return (m - 1) * it.lda + m <= lim && (n - 1) * it.ldz + m <= lim && (n - 1) * it.ldq + m <= lim;
+}
 template <class T>
 __device__ __forceinline__ bool item_ok(const oqr_batch_item& it, int max_m) {
   const int64_t m = it.m, n = it.n, lim = 0x7fffffff / (int64_t)sizeof(T);
@@ -437,7 +468,8 @@ template <class T>
 __global__ __launch_bounds__(NT, 2) void batch_kernel(const oqr_batch_item* __restrict__ items,
                                                     const int32_t* __restrict__ order, int batch, int max_m,
                                                     int32_t* __restrict__ counter, int32_t* __restrict__ info,
-                                                    double c_retry, int max_retries, ShapeTable shapes) {
+                                                    double c_retry, int max_retries, ShapeTable shapes,
+                                                    const int32_t* __restrict__ big) {
   __shared__ Smem S;
   const int t = threadIdx.x;
   for (;;) {
@@ -447,6 +479,7 @@ __global__ __launch_bounds__(NT, 2) void batch_kernel(const oqr_batch_item* __re
     __syncthreads();
     if (slot >= batch) break;
     const int id = order[slot];
+    if (big && big[id]) continue;            // split over several workgroups by the staged launches
     const oqr_batch_item it = items[id];
     if (!item_ok<T>(it, max_m)) {
       if (t == 0) info[id] = OQR_BATCH_BAD_ITEM;
@@ -496,12 +529,115 @@ __global__ __launch_bounds__(NT, 2) void batch_kernel(const oqr_batch_item* __re
   }
 }
 
+// Split instances (cooperative workgroups): the largest instances, those with m >= split_m, run each
+// pass as `parts` workgroups over interleaved row blocks (part p takes row blocks p, p + parts, ...),
+// whose partial Grams go to the workspace, then one workgroup per instance sums the parts in order
+// and factors and solves.  Four launches (Gram parts and finish, twice) before the persistent kernel
+// takes the rest; nothing waits on another workgroup.  The order kernel lists the split instances in
+// large[0 .. ctl[1]) and flags them in big[].
+constexpr int MAX_PARTS = 8;
+constexpr int SPLIT_SLOTS = 512;
+constexpr int PART_DOUBLES = 4 * 4 * 4 * 64;    // waves of row group 0 x accumulators x elements x lanes
+
+template <class T>
+__global__ __launch_bounds__(NT, 2) void split_gram_kernel(const oqr_batch_item* __restrict__ items,
+                                                         const int32_t* __restrict__ large,
+                                                         const int32_t* __restrict__ ctl, int parts, int pass,
+                                                         const int32_t* __restrict__ info,
+                                                         double* __restrict__ partial, ShapeTable shapes) {
+  __shared__ Smem S;
+  const int p = blockIdx.x, k = blockIdx.y;
+  if (k >= ctl[1] || p >= parts) return;
+  const int id = large[k];
+  if (pass == 2 && info[id] != 0) return;
+  const oqr_batch_item it = items[id];
+  const int m = it.m, n = it.n;
+  const T* X = (const T*)(pass == 1 ? it.z : it.q);
+  const int64_t ldx = pass == 1 ? it.ldz : it.ldq;
+  f64x4 g[4];
+  const int cls = gram_wg<T, 1>((const T*)it.a, it.lda, X, ldx, m, n, shapes.s[m_bucket(m)][n_class(n)], p, parts, S, g);
+  const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+  double* P = partial + ((int64_t)k * MAX_PARTS + p) * PART_DOUBLES;
+  if (wave < cls) {
+#pragma unroll
+    for (int gi = 0; gi < 4; ++gi)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) P[((wave * 4 + gi) * 4 + r) * 64 + lane] = g[gi][r];
+  }
+}
+
+template <class T>
+__global__ __launch_bounds__(NT, 2) void split_finish_kernel(const oqr_batch_item* __restrict__ items,
+                                                           const int32_t* __restrict__ large,
+                                                           const int32_t* __restrict__ ctl, int parts, int pass,
+                                                           int32_t* __restrict__ info,
+                                                           const double* __restrict__ partial, double c_retry,
+                                                           int max_retries) {
+  __shared__ Smem S;
+  const int k = blockIdx.x;
+  if (k >= ctl[1]) return;
+  const int id = large[k];
+  if (pass == 2 && info[id] != 0) return;
+  const oqr_batch_item it = items[id];
+  const int m = it.m, n = it.n;
+  const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+  const int nbk = (n + 15) / 16, cls = nbk <= 1 ? 1 : (nbk == 2 ? 2 : 4);
+  // G = sum of the parts, in part order
+  f64x4 g[4];
+#pragma unroll
+  for (int gi = 0; gi < 4; ++gi) g[gi] = f64x4{0, 0, 0, 0};
+  if (wave < cls) {
+    for (int p = 0; p < parts; ++p) {
+      const double* P = partial + ((int64_t)k * MAX_PARTS + p) * PART_DOUBLES;
+#pragma unroll
+      for (int gi = 0; gi < 4; ++gi)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) g[gi][r] += P[((wave * 4 + gi) * 4 + r) * 64 + lane];
+    }
+  }
+  T* Q = (T*)it.q;
+  T* R = (T*)it.r;
+  const T* Xin = (const T*)(pass == 1 ? it.z : it.q);
+  const int64_t ldxin = pass == 1 ? it.ldz : it.ldq;
+  const int f = finish_wg<T, 1>(g, cls, Xin, ldxin, Q, it.ldq, m, n, U64, 0.0, c_retry, max_retries, S);
+  if (f) {
+    if (t == 0) info[id] = f;
+    return;
+  }
+  if (pass == 1) {
+    // R1 waits in the output R (upper n x n) across pass 2
+    for (int e = t; e < n * n; e += NT) {
+      const int i = e % n, j = e / n;
+      R[(int64_t)j * it.ldr + i] = (T)S.f.Gs[i][j];
+    }
+    return;
+  }
+  // R = R2 R1: R2 in Gs, R1 (back from R) into Ws
+  for (int e = t; e < NB * NB; e += NT) {
+    const int i = e % NB, j = e / NB;
+    S.f.Ws[i][j] = (i < n && j < n) ? (double)R[(int64_t)j * it.ldr + i] : 0.0;
+  }
+  __syncthreads();
+  for (int e = t; e < n * n; e += NT) {
+    const int i = e % n, j = e / n;
+    double sum = 0.0;
+    if (i <= j)
+      for (int kk = i; kk <= j; ++kk) sum += S.f.Gs[i][kk] * S.f.Ws[kk][j];
+    R[(int64_t)j * it.ldr + i] = (T)sum;
+  }
+}
+
 // order[] = instance indices sorted by decreasing cost m^2 n (one workgroup, bitonic sort in LDS).
 constexpr int SORT_MAX = 8192;
+// With split_m > 0 it also lists the split instances: the first `slots` items of the sorted order with
+// m >= split_m that pass the item check go to large[] (count in ctl[1]) and get big[id] = 1.
 __global__ __launch_bounds__(1024) void order_kernel(const oqr_batch_item* __restrict__ items, int batch,
                                                      int32_t* __restrict__ order, int32_t* __restrict__ counter,
-                                                     int32_t* __restrict__ info) {
+                                                     int32_t* __restrict__ info, int split_m, int slots,
+                                                     int max_m, int esize, int32_t* __restrict__ big,
+                                                     int32_t* __restrict__ large) {
   __shared__ unsigned long long key[SORT_MAX];
+  __shared__ int cnt[1024];
   const int t = threadIdx.x;
   int p2 = 1;
   while (p2 < batch) p2 <<= 1;
@@ -535,6 +671,49 @@ __global__ __launch_bounds__(1024) void order_kernel(const oqr_batch_item* __res
     info[i] = 0;
   }
   if (t == 0) counter[0] = 0;
+  if (split_m <= 0) {
+    if (t == 0) counter[1] = 0;
+    return;
+  }
+  // thread t examines sorted entries t CH .. t CH + CH - 1; an exclusive scan of the counts places them
+  constexpr int CH = SORT_MAX / 1024;
+  bool cand[CH];
+  int c = 0;
+#pragma unroll
+  for (int u = 0; u < CH; ++u) {
+    const int i = t * CH + u;
+    bool ok = false;
+    if (i < batch) {
+      const oqr_batch_item it = items[(int)(key[i] & (SORT_MAX - 1))];
+      ok = it.m >= split_m && item_ok_size(it, max_m, esize);
+    }
+    cand[u] = ok;
+    c += ok ? 1 : 0;
+  }
+  cnt[t] = c;
+  __syncthreads();
+  if (t == 0) {
+    int run = 0;
+    for (int q = 0; q < 1024; ++q) {
+      const int v = cnt[q];
+      cnt[q] = run;
+      run += v;
+    }
+    counter[1] = run < slots ? run : slots;
+  }
+  __syncthreads();
+  int pos = cnt[t];
+#pragma unroll
+  for (int u = 0; u < CH; ++u) {
+    const int i = t * CH + u;
+    if (i < batch) {
+      const int id = (int)(key[i] & (SORT_MAX - 1));
+      const bool take = cand[u] && pos < slots;
+      if (take) large[pos] = id;
+      big[id] = take ? 1 : 0;
+      pos += cand[u] ? 1 : 0;
+    }
+  }
 }
 
 __global__ void identity_order_kernel(int batch, int32_t* order, int32_t* counter, int32_t* info) {
@@ -554,7 +733,37 @@ oqr_batch_tuning builtin_tuning() {
   tu.sort = 1;
   for (int b = 0; b < OQR_BATCH_MBUCKETS; ++b)
     for (int c = 0; c < OQR_BATCH_NCLASSES; ++c) tu.shape[b][c] = 0;
+  tu.split_m = 0;
+  tu.parts = 1;
   return tu;
+}
+
+// Workspace: ctl (counter, split count) | order | big | large | partial Grams of the split instances.
+struct BatchWs {
+  int32_t* ctl;
+  int32_t* order;
+  int32_t* big;
+  int32_t* large;
+  double* partial;
+  size_t bytes;
+};
+BatchWs batch_ws(int64_t batch, void* base) {
+  const int64_t slots = batch < SPLIT_SLOTS ? batch : SPLIT_SLOTS;
+  char* p = (char*)base;
+  BatchWs w;
+  size_t off = 0;
+  w.ctl = (int32_t*)(p + off);
+  off += align256(sizeof(int32_t) * 64);
+  w.order = (int32_t*)(p + off);
+  off += align256(sizeof(int32_t) * (size_t)batch);
+  w.big = (int32_t*)(p + off);
+  off += align256(sizeof(int32_t) * (size_t)batch);
+  w.large = (int32_t*)(p + off);
+  off += align256(sizeof(int32_t) * (size_t)slots);
+  w.partial = (double*)(p + off);
+  off += align256(sizeof(double) * (size_t)slots * MAX_PARTS * PART_DOUBLES);
+  w.bytes = off;
+  return w;
 }
 
 }  // namespace
@@ -572,8 +781,8 @@ size_t oqr_batched_workspace_bytes(int64_t batch, int32_t max_m, int32_t max_n, 
   (void)max_m;
   (void)max_n;
   (void)dtype;
-  if (batch < 0) return 0;
-  return align256(sizeof(int32_t) * 64) + align256(sizeof(int32_t) * (size_t)(batch > 0 ? batch : 1));
+  if (batch < 0 || batch > (1 << 30)) return 0;
+  return batch_ws(batch > 0 ? batch : 1, nullptr).bytes;
 }
 
 int oqr_cholqr2_batched(int64_t batch, const oqr_batch_item* items_dev, int32_t dtype, int32_t max_m, int32_t max_n,
@@ -585,6 +794,7 @@ int oqr_cholqr2_batched(int64_t batch, const oqr_batch_item* items_dev, int32_t 
   if (dtype != OQR_F64 && dtype != OQR_F32) return OQR_E_ARG;
   const oqr_batch_tuning tu = tuning ? *tuning : builtin_tuning();
   if (tu.wg_per_cu < 1 || tu.wg_per_cu > 3 || (tu.sort != 0 && tu.sort != 1)) return OQR_E_ARG;
+  if (tu.split_m < 0 || tu.parts < 1 || tu.parts > MAX_PARTS) return OQR_E_ARG;
   ShapeTable shapes;
   for (int b = 0; b < OQR_BATCH_MBUCKETS; ++b)
     for (int c = 0; c < OQR_BATCH_NCLASSES; ++c) {
@@ -599,24 +809,45 @@ int oqr_cholqr2_batched(int64_t batch, const oqr_batch_item* items_dev, int32_t 
   const size_t need = oqr_batched_workspace_bytes(batch, max_m, max_n, dtype);
   if (!ws || ws_bytes < need || ((uintptr_t)ws & 255u)) return OQR_E_WORKSPACE;
   hipStream_t s = (hipStream_t)stream;
-  int32_t* counter = (int32_t*)ws;
-  int32_t* order = (int32_t*)((char*)ws + align256(sizeof(int32_t) * 64));
+  const BatchWs w = batch_ws(batch, ws);
+  const int slots = (int)(batch < SPLIT_SLOTS ? batch : SPLIT_SLOTS);
+  // split instances need the sorted order (they are the largest); a batch that cannot be sorted in one
+  // workgroup runs unsplit
+  const bool split = tu.split_m > 0 && tu.sort && batch <= SORT_MAX;
+  const int esize = dtype == OQR_F64 ? 8 : 4;
   if (tu.sort && batch <= SORT_MAX)
-    order_kernel<<<1, 1024, 0, s>>>(items_dev, (int)batch, order, counter, info_dev);
+    order_kernel<<<1, 1024, 0, s>>>(items_dev, (int)batch, w.order, w.ctl, info_dev, split ? tu.split_m : 0, slots,
+                                    max_m, esize, w.big, w.large);
   else
-    identity_order_kernel<<<(unsigned)((batch + 255) / 256), 256, 0, s>>>((int)batch, order, counter, info_dev);
+    identity_order_kernel<<<(unsigned)((batch + 255) / 256), 256, 0, s>>>((int)batch, w.order, w.ctl, info_dev);
   if (hipGetLastError() != hipSuccess) return OQR_E_HIP;
   // compute-unit count, queried once per device (outside any graph capture: the first call)
   const int cus = device_cu_count();
   int64_t grid = (int64_t)cus * tu.wg_per_cu;
   if (grid > batch) grid = batch;
   trace_pre(K_BATCH, s);
+  if (split) {
+    const dim3 pg(tu.parts, slots);
+    for (int pass = 1; pass <= 2; ++pass) {
+      if (dtype == OQR_F64) {
+        split_gram_kernel<double><<<pg, NT, 0, s>>>(items_dev, w.large, w.ctl, tu.parts, pass, info_dev, w.partial,
+                                                    shapes);
+        split_finish_kernel<double><<<slots, NT, 0, s>>>(items_dev, w.large, w.ctl, tu.parts, pass, info_dev,
+                                                         w.partial, o.shift_c, o.max_retries);
+      } else {
+        split_gram_kernel<float><<<pg, NT, 0, s>>>(items_dev, w.large, w.ctl, tu.parts, pass, info_dev, w.partial,
+                                                   shapes);
+        split_finish_kernel<float><<<slots, NT, 0, s>>>(items_dev, w.large, w.ctl, tu.parts, pass, info_dev,
+                                                        w.partial, o.shift_c, o.max_retries);
+      }
+    }
+  }
   if (dtype == OQR_F64)
-    batch_kernel<double><<<(unsigned)grid, NT, 0, s>>>(items_dev, order, (int)batch, max_m, counter, info_dev,
-                                                       o.shift_c, o.max_retries, shapes);
+    batch_kernel<double><<<(unsigned)grid, NT, 0, s>>>(items_dev, w.order, (int)batch, max_m, w.ctl, info_dev,
+                                                       o.shift_c, o.max_retries, shapes, split ? w.big : nullptr);
   else
-    batch_kernel<float><<<(unsigned)grid, NT, 0, s>>>(items_dev, order, (int)batch, max_m, counter, info_dev,
-                                                      o.shift_c, o.max_retries, shapes);
+    batch_kernel<float><<<(unsigned)grid, NT, 0, s>>>(items_dev, w.order, (int)batch, max_m, w.ctl, info_dev,
+                                                      o.shift_c, o.max_retries, shapes, split ? w.big : nullptr);
   const hipError_t e = hipGetLastError();
   trace_post(K_BATCH, s);
   return e == hipSuccess ? OQR_OK : OQR_E_HIP;

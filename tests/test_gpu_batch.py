@@ -106,6 +106,126 @@ def test_batch_launch_configuration_keeps_the_bits(wg, sort):
         assert torch.equal(plan.Qs[k], ref.Qs[k]) and torch.equal(plan.Rs[k], ref.Rs[k])
 
 
+def _split_tuning(split_m, parts, shape=None, wg=None):
+    d = _tuning(shape=shape, wg=wg).to_dict()
+    d["split_m"], d["parts"] = split_m, parts
+    return oqr.BatchTuning.from_dict(d)
+
+
+@pytest.mark.parametrize("parts", [1, 2, 3, 8])
+def test_batch_split_instances_match_oracle(parts):
+    """Cooperative instances: those with m >= 700 run each pass as `parts` Gram parts over interleaved
+    row blocks (partial Grams summed in part order) taken by any workgroup of the persistent launch;
+    every instance matches CHOL-EQR, ragged n included; two runs, and a run with one workgroup per
+    compute unit (other workgroups take the parts), repeat the bits."""
+    insts = make_batch(20, m_lo=100, m_hi=1500, seed=15, extra_n=(64, 1, 33, 17))
+    assert sum(z.shape[0] >= 700 for _, z in insts) >= 4
+    As, Zs = upload(insts, np.float64)
+    plan = oqr.BatchPlan(As, Zs, tuning=_split_tuning(700, parts))
+    banner(f"batch split m>=700 parts={parts}")
+    plan.run()
+    torch.cuda.synchronize()
+    check_fp64(insts, plan)
+    q1 = [q.clone() for q in plan.Qs]
+    r1 = [r.clone() for r in plan.Rs]
+    plan.run()
+    torch.cuda.synchronize()
+    for k in range(len(insts)):
+        assert torch.equal(plan.Qs[k], q1[k])
+    one = oqr.BatchPlan(As, Zs, tuning=_split_tuning(700, parts, wg=1))
+    one.run()
+    torch.cuda.synchronize()
+    for k in range(len(insts)):
+        assert torch.equal(one.Qs[k], q1[k]) and torch.equal(one.Rs[k], r1[k]), k
+
+
+def test_batch_split_most_instances():
+    """Nearly every instance split (8 parts each): many pass-2 parts published while others are still
+    in pass 1; results against the oracle."""
+    insts = make_batch(40, m_lo=300, m_hi=900, seed=19, extra_n=(64, 40))
+    As, Zs = upload(insts, np.float64)
+    plan = oqr.BatchPlan(As, Zs, tuning=_split_tuning(300, 8))
+    banner("batch split 40 instances x 8 parts")
+    plan.run()
+    torch.cuda.synchronize()
+    check_fp64(insts, plan)
+
+
+def test_batch_split_fp32_storage_and_shapes():
+    """The split path with FP32 storage and a non-default tile shape, against the oracle on the rounded
+    inputs."""
+    insts = make_batch(16, m_lo=100, m_hi=1200, seed=16, k=(1e2, 1e4))
+    As, Zs = upload(insts, np.float32)
+    plan = oqr.BatchPlan(As, Zs, tuning=_split_tuning(600, 4, shape=3))
+    banner("batch split fp32")
+    plan.run()
+    torch.cuda.synchronize()
+    assert np.all(to_host(plan.info) == 0)
+    for k, (a, z) in enumerate(insts):
+        a32 = a.astype(np.float32).astype(np.float64)
+        z32 = z.astype(np.float32).astype(np.float64)
+        q, r = to_host(plan.Qs[k]).astype(np.float64), to_host(plan.Rs[k]).astype(np.float64)
+        q0, r0 = reference.chol_eqr(a32, z32)
+        aq2 = metrics.diagnostics(a32, z32, q0, r0)["a_q2"]
+        assert metrics.orth_loss(a32, q) <= max(1e-6, 10 * U32 * aq2), k
+        assert metrics.residual_f(z32, q, r) <= 1e-6, k
+
+
+def test_batch_split_failing_instance_reports_and_stops():
+    """A split instance whose Gram is not positive definite reports its pivot in info after the first
+    pass and takes no second pass; the other instances, split or not, are solved."""
+    insts = make_batch(10, m_lo=100, m_hi=1000, seed=17)
+    m, n = 900, 5
+    d = np.ones(m)
+    d[1] = -1.0
+    bad_a = np.diag(d)
+    bad_z = np.zeros((m, n), order="F")
+    for j in range(n):
+        bad_z[j, j] = 1.0
+    insts[2] = (bad_a, bad_z)
+    As, Zs = upload(insts, np.float64)
+    plan = oqr.BatchPlan(As, Zs, tuning=_split_tuning(500, 3))
+    banner("batch split with a failing instance")
+    plan.run()
+    torch.cuda.synchronize()
+    info = to_host(plan.info)
+    assert info[2] == variants.chol_info(bad_z.T @ bad_a @ bad_z)[1] == 2
+    good = [k for k in range(len(insts)) if k != 2]
+    assert np.all(info[good] == 0)
+    for k in good:
+        a, z = insts[k]
+        assert metrics.residual_f(z, to_host(plan.Qs[k]), to_host(plan.Rs[k])) <= 1e-12
+
+
+def test_batch_split_graph_replays_match_eager():
+    insts = make_batch(12, m_lo=200, m_hi=1500, seed=18)
+    As, Zs = upload(insts, np.float64)
+    plan = oqr.BatchPlan(As, Zs, tuning=_split_tuning(800, 4))
+    plan.run()
+    torch.cuda.synchronize()
+    eager_q = [q.clone() for q in plan.Qs]
+    eager_r = [r.clone() for r in plan.Rs]
+    g = torch.cuda.CUDAGraph()
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        plan.run()
+    torch.cuda.current_stream().wait_stream(s)
+    torch.cuda.synchronize()
+    with torch.cuda.graph(g, stream=s):
+        plan.run()
+    banner("batch split graph replays")
+    for rep in range(3):
+        for q in plan.Qs:
+            q.zero_()
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        assert int(plan.info.sum().item()) == 0
+        for k in range(len(insts)):
+            assert torch.equal(plan.Qs[k], eager_q[k]) and torch.equal(plan.Rs[k], eager_r[k]), (rep, k)
+
+
 def test_batch_bucket_table_selects_per_class():
     """A table with a different shape per (m bucket, n class): every instance still matches the oracle."""
     insts = make_batch(32, m_lo=200, m_hi=1100, seed=14)
