@@ -18,7 +18,8 @@ Bars (the error models of Sections 2-6):
   the Gram-based CHOLQR-A and CGS-A, whose computed Gram carries an error of u ||G||).
 * CHOL-EQR: R and Q within 100 n u kappa(A)^{1/2} kappa(R) of the oracle's.
 * EQR-SYEV: within 100 n u kappa(A) kappa(R) of the oracle's EQR-SYEV (the eigenvector error grows
-  with kappa(A), Section 5), at half the row count (m = 4096, the same spectrum and Z recipe,
+  with kappa(A), Section 5); its residual is the one that is not constant (Section 7: proportional to
+  kappa(A)^{1/2}, even for random matrices), so its bar is 100 u kappa(A)^{1/2}; at half the row count (m = 4096, the same spectrum and Z recipe,
   kappa(Z) = 1e4): the library's cyclic Jacobi eigensolver (a comparison baseline, one launch pair per
   rotation round) takes about 35 s per call at m = 4096 and more than three minutes at m = 8192,
   beyond a test's time.  The eigendecomposition does not depend on Z; everything after it (the
@@ -72,8 +73,8 @@ def _gpu(alg, A, z, **kw):
     return to_host(q), to_host(r)
 
 
-def _common(a, z, q, r):
-    assert metrics.residual_f(z, q, r) <= 1e-12
+def _common(a, z, q, r, res_bar=1e-12):
+    assert metrics.residual_f(z, q, r) <= res_bar
     assert np.all(np.tril(r, -1) == 0) and np.all(np.diag(r) > 0)
 
 
@@ -164,7 +165,7 @@ def test_config2_eig_a_half_size():
     q, r = _gpu("eig_a", to_dev(a), z)
     banner("config2 eig_a m=4096 kz=1e4: CPU run of the same algorithm")
     q0, r0 = reference.eqr_syev(a, z)
-    _common(a, z, q, r)
+    _common(a, z, q, r, res_bar=max(1e-12, 100 * U * np.sqrt(KAPPA_A)))
     assert metrics.orth_loss(a, q) <= 10 * metrics.orth_loss(a, q0) + 1e-13
     tol = 100 * N * U * KAPPA_A * np.linalg.cond(r0)
     assert metrics.r_forward_error(r, r0) <= tol
