@@ -5,7 +5,8 @@ NumPy, so that a GPU variant can be compared with the same algorithm's own FP64
 behaviour (unstable variants are judged against themselves and against their
 theorem's bound, not against the acceptance oracle).
 
-* cholqr      Algorithm 1 (Section 2): B = A Z, C = Z^T B, R = chol(C), Q = Z R^{-1}.
+* cholqr      Algorithm 1 (Section 2): B = A Z, C = Z^T B, R = chol(C), Q = Z R^{-1};
+              for dense symmetric A, C may be formed from A's upper triangle (split_gram).
 * cholqr2     Algorithm 1 applied twice, R = R2 R1 (the second pass plays the
               role of PRE-CHOLQR's R = U S, Algorithm 2, Section 3).
 * pre_cholqr  Algorithm 2 (Section 3): [Y,S] = qr(Z), [Q,U] = CHOLQR(A,Y), R = U S.
@@ -56,19 +57,31 @@ def trsm_right_upper(z: np.ndarray, r: np.ndarray) -> np.ndarray:
     return scipy.linalg.solve_triangular(r, z.T, trans="T", lower=False, check_finite=False).T
 
 
+def split_gram(a: np.ndarray, z: np.ndarray) -> np.ndarray:
+    """Z^T A Z for a dense symmetric A read in its upper triangle only: with T = triu(A, 1) + diag(A)/2,
+    A = T + T^T exactly, so Z^T A Z = Z^T (T Z) + (T Z)^T Z, symmetric by construction."""
+    t = np.triu(a, 1) + 0.5 * np.diag(np.diag(a))
+    w = t @ z
+    return z.T @ w + w.T @ z
+
+
 def cholqr(a, z: np.ndarray, shift: float = 0.0, return_info: bool = False, gram: str = "sym"):
     """CHOLQR (Algorithm 1).  C = Z^T (A Z) is symmetric only in exact arithmetic:
     gram="sym" factors (C + C^T)/2; gram="upper" factors the symmetric matrix
     built from the upper triangle of C, which is what the listing's chol(C) reads
-    (MATLAB's chol uses the upper triangle only).  `shift` is added to the
-    diagonal before the factorisation."""
-    b = _apply(a, z)
-    c = z.T @ b
+    (MATLAB's chol uses the upper triangle only); gram="split" (dense A) forms C from
+    A's upper triangle as Z^T (T Z) + (T Z)^T Z (split_gram).  `shift` is added to
+    the diagonal before the factorisation."""
+    if gram == "split":
+        c = split_gram(np.asarray(a), z)
+    else:
+        b = _apply(a, z)
+        c = z.T @ b
     if gram == "sym":
         c = 0.5 * (c + c.T)
     elif gram == "upper":
         c = np.triu(c) + np.triu(c, 1).T
-    else:
+    elif gram != "split":
         raise ValueError(gram)
     if shift:
         c = c + shift * np.eye(c.shape[0])

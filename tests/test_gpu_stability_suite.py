@@ -35,14 +35,17 @@ KAPPAS = [1e1, 1e3, 1e5, 1e7, 1e9, 1e11, 1e13, 1e15]
 M_SCALED, N_SCALED = 2048, 64
 KAPPAS_SCALED = [1e1, 1e4, 1e7, 1e10, 1e13]
 
-# The Cholesky-based variants are compared under the GPU's Gram convention: the factorisation
-# reads the upper triangle of C = Z^T (A Z), as the listing's chol(C) does.  In Case 1 (Z in the span
-# of A's smallest eigenvalues) symmetrising C instead changes CHOLQR-A's loss by up to ~500x
-# (2.9e-8 against 1e-5..3e-5 at kappa(A) = 1e7 for every summation order of A Z).
+# The Cholesky-based variants are compared under the GPU's Gram convention for a dense symmetric A:
+# the FP64 pass reads A's upper triangle only and forms C = Z^T (T Z) + (T Z)^T Z with
+# T = triu(A, 1) + diag(A)/2 (`variants.split_gram`), symmetric by construction.  The convention
+# matters in Case 1 (Z in the span of A's smallest eigenvalues): there the readings of chol(C) differ
+# by large factors (symmetrising C = Z^T (A Z) instead of reading its upper triangle changes CHOLQR-A's
+# loss by up to ~500x, 2.9e-8 against 1e-5..3e-5 at kappa(A) = 1e7), and the split assembly sits
+# 4-9x above the upper-triangle reading in an FP64 NumPy run at m = 80.
 ORACLE = {
-    "cholqr": lambda a, z: variants.cholqr(a, z, gram="upper"),
-    "cholqr2": lambda a, z: variants.cholqr2(a, z, gram="upper"),
-    "pre_cholqr": lambda a, z: variants.pre_cholqr(a, z, gram="upper"),
+    "cholqr": lambda a, z: variants.cholqr(a, z, gram="split"),
+    "cholqr2": lambda a, z: variants.cholqr2(a, z, gram="split"),
+    "pre_cholqr": lambda a, z: variants.pre_cholqr(a, z, gram="split"),
     "chol_a": lambda a, z: reference.chol_eqr(a, z),
     "eig_a": lambda a, z: reference.eqr_syev(a, z),
     "cgs": lambda a, z: variants.cgs(a, z),

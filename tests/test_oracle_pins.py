@@ -183,6 +183,43 @@ def test_gram_conventions_agree_when_the_gram_is_exact():
         variants.cholqr(a, z, gram="lower")
 
 
+def _exact_zt_a_z(a, z):
+    """Z^T A Z by brute-force integer sums (inputs hold small integers)."""
+    ai, zi = a.astype(np.int64), z.astype(np.int64)
+    m, n = zi.shape
+    return np.array([[sum(int(zi[k, i]) * int(ai[k, l]) * int(zi[l, j]) for k in range(m) for l in range(m))
+                      for j in range(n)] for i in range(n)], dtype=np.float64)
+
+
+def test_split_gram_is_z_t_a_z_exactly_on_integers():
+    """A = T + T^T with T = triu(A, 1) + diag(A)/2: on small integers every product and sum is exact,
+    so the split assembly equals the integer Z^T A Z, and a T that keeps the whole diagonal (a
+    plausible slip) does not."""
+    rng = np.random.default_rng(11)
+    b = rng.integers(-3, 4, size=(10, 10)).astype(np.float64)
+    a = b.T @ b + 5 * np.eye(10)
+    z = rng.integers(-2, 3, size=(10, 3)).astype(np.float64)
+    exact_c = _exact_zt_a_z(a, z)
+    assert np.array_equal(variants.split_gram(a, z), exact_c)
+    t_bad = np.triu(a)                                 # planted slip: whole diagonal in T
+    w = t_bad @ z
+    assert not np.array_equal(z.T @ w + w.T @ z, exact_c)
+
+
+def test_split_gram_is_exactly_symmetric_and_factors_within_theorem_bound():
+    """The split assembly is symmetric by construction (M + M^T, bit for bit), and one CHOLQR pass on it
+    lands within u kappa(R)^2 of the 50-digit factor, like the other readings of chol(C)."""
+    a, z = tiny(1, 14, 4, ka=1e3, kz=1e2)
+    c = variants.split_gram(a, z)
+    assert np.array_equal(c, c.T)
+    qe, re = exact.exact_oblique_qr(a, z)
+    kap = np.linalg.cond(re)
+    r1 = variants.cholqr(a, z, gram="split")[1]
+    assert metrics.r_forward_error(r1, re) <= 50 * 14 * 4 * U * kap ** 2
+    r2 = variants.cholqr2(a, z, gram="split")[1]
+    assert metrics.r_forward_error(r2, re) <= 50 * 14 * 4 * U * kap
+
+
 # ---- the tridiagonal operator (Section 8's sparse workload) ----------------------------------
 
 def test_tridiag_apply_matches_assembled_matrix():
