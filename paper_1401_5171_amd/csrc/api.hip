@@ -238,9 +238,14 @@ int cholqr_pass(const oqr_op* A, const double* Z, int64_t ldz, int64_t m, int64_
                 int32_t* info, hipStream_t s) {
   if (A->kind == OQR_OP_DENSE) {
     const double* a = (const double*)A->a;
-    if (prec == OQR_P_FP64 || prec == OQR_P_FP32) {
-      OQR_TRACED(prec == OQR_P_FP64 ? K_GEMM_F64 : K_GEMM_SPLIT, s,
-                 launch_symm_upper(a, A->lda, Z, ldz, w.W, m, m, n, w.kpart, s, prec == OQR_P_FP32));
+    if (prec == OQR_P_FP64) {
+      // W' = (U + D/2) Z, then G = Z^T W' + W'^T Z: the diagonal blocks ride in the product
+      OQR_TRACED(K_GEMM_F64, s, launch_symm_half(a, A->lda, Z, ldz, w.W, m, m, n, w.kpart, s));
+      if (symm_layers(m, n, w.kpart) > 1)
+        OQR_TRACED(K_SYMM_DIAG, s, launch_layer_sum(w.kpart, symm_layers(m, n, w.kpart), m, n, w.W, m, s));
+      OQR_TRACED(K_GRAM, s, launch_gram_symm(Z, ldz, w.W, w.W, m, m, n, w.partial, w.G, s));
+    } else if (prec == OQR_P_FP32) {
+      OQR_TRACED(K_GEMM_SPLIT, s, launch_symm_upper(a, A->lda, Z, ldz, w.W, m, m, n, w.kpart, s, true));
       OQR_TRACED(K_SYMM_DIAG, s,
                  launch_symm_finish(a, A->lda, Z, ldz, w.W, w.Ws, m, m, n, w.kpart, symm_layers(m, n, w.kpart), s));
     } else {
@@ -250,7 +255,7 @@ int cholqr_pass(const oqr_op* A, const double* Z, int64_t ldz, int64_t m, int64_
       OQR_TRACED(K_SYMM_DIAG, s,
                  launch_symm_finish(a, A->lda, Z, ldz, w.W, w.Ws, m, m, n, w.kpart, symm_layers(m, n, w.kpart), s));
     }
-    OQR_TRACED(K_GRAM, s, gram_symm(Z, ldz, m, n, w, s));
+    if (prec != OQR_P_FP64) OQR_TRACED(K_GRAM, s, gram_symm(Z, ldz, m, n, w, s));
   } else if (stencil_fused(A, ldz, n, prec)) {
     if (prec == OQR_P_FP64)
       OQR_TRACED(K_GRAM, s, launch_stencil_gram(A, Z, ldz, n, w.partial, w.G, s));

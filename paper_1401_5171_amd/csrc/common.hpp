@@ -141,6 +141,13 @@ hipError_t launch_symm_upper(const double* A, int64_t lda, const double* Z, int6
 // launch_gemm_split); the diagonal blocks are then added in FP64 by launch_symm_finish.
 hipError_t launch_symm_split_upper(const double* A, int64_t lda, const unsigned short* zs, double* Woff, int64_t ldw,
                                    int64_t m, int64_t n, int slices, double* kpart, hipStream_t s);
+// W' = (U + D/2) Z for symmetric A (U the strictly upper block triangle, D the diagonal blocks with
+// their lower triangles dropped), FP64: Z^T A Z = Z^T W' + W'^T Z.  With more than one layer the
+// partial products go to kpart and launch_layer_sum adds them into W.
+hipError_t launch_symm_half(const double* A, int64_t lda, const double* Z, int64_t ldz, double* W, int64_t ldw,
+                            int64_t m, int64_t n, double* kpart, hipStream_t s);
+hipError_t launch_layer_sum(const double* kpart, int layers, int64_t m, int64_t n, double* W, int64_t ldw,
+                            hipStream_t s);
 hipError_t launch_symm_finish(const double* A, int64_t lda, const double* Z, int64_t ldz, double* Woff, double* Wsym,
                               int64_t ldw, int64_t m, int64_t n, const double* kpart, int layers, hipStream_t s);
 // W = A * Z with A split on the fly into `slices` bfloat16 slices and Z pre-split (zs: slices x n

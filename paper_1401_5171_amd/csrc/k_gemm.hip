@@ -27,19 +27,26 @@ constexpr int APAD = 16, BPAD = 14;
 // tiles t and R - 1 - t form pair blockIdx.x (their lengths sum to m - BM), the pair's K steps are cut
 // into gridDim.z equal parts, and part blockIdx.z goes to layer blockIdx.z of the output (both tiles of
 // the pair are written in every layer, zeros where the part has no steps).  GEMM_DIAG: row tile
-// blockIdx.x, K in its own diagonal block [BM t, BM (t + 1)); the result is added to Wadd.
-enum GemmMode { GEMM_FULL = 0, GEMM_UPPER = 1, GEMM_DIAG = 2 };
+// blockIdx.x, K in its own diagonal block [BM t, BM (t + 1)); the result is added to Wadd.  GEMM_SYMH: as
+// GEMM_UPPER, but row tile t starts at its own diagonal block, whose entries below the diagonal count as
+// zero and whose diagonal counts half: the product is W' = (U + D/2) Z with U the strictly upper part of
+// A and D the lower-triangle-free diagonal blocks, so that A = (U + D/2) + (U + D/2)^T and
+// Z^T A Z = Z^T W' + W'^T Z.
+enum GemmMode { GEMM_FULL = 0, GEMM_UPPER = 1, GEMM_DIAG = 2, GEMM_SYMH = 3 };
 
 struct Seg {
   int tile, k0, k1;
 };
 
 // The row-tile segments of workgroup (pair p, part h) in GEMM_UPPER, K steps of ks: a in tile p and,
-// unless the pair is one tile (returns false), b in tile R - 1 - p.
-__device__ __forceinline__ bool upper_segments(int m, int p, int h, int H, int ks, Seg& a, Seg& b) {
+// unless the pair is one tile (returns false), b in tile R - 1 - p.  With diag, a tile's K range starts
+// at its own diagonal block.
+__device__ __forceinline__ bool upper_segments(int m, int p, int h, int H, int ks, Seg& a, Seg& b,
+                                               bool diag = false) {
   const int R = (m + BM - 1) / BM;
   const int ta = p, tb = R - 1 - p;
-  const int sa = min(m, BM * (ta + 1)), sb = min(m, BM * (tb + 1));
+  const int d = diag ? 0 : 1;
+  const int sa = min(m, BM * (ta + d)), sb = min(m, BM * (tb + d));
   const int na = (m - sa + ks - 1) / ks, nb = (tb != ta) ? (m - sb + ks - 1) / ks : 0;
   const int T = na + nb;
   const int s0 = (int)((int64_t)T * h / H), s1 = (int)((int64_t)T * (h + 1) / H);
@@ -88,6 +95,7 @@ __global__ __launch_bounds__(NT, 2) void gemm_f64_kernel(const double* __restric
 #pragma unroll
       for (int b = 0; b < CB; ++b) acc[a][b] = f64x4{0, 0, 0, 0};
     double ra[AR], rb[BR];
+    int ka = kb;                       // K step held in ra
     uint32_t aoff[AR];
 #pragma unroll
     for (int r = 0; r < AR; ++r) aoff[r] = (i0 + ai < m) ? (uint32_t)(((int64_t)(ak + 4 * r) * lda + ai) * 8) : kOOB;
@@ -96,12 +104,21 @@ __global__ __launch_bounds__(NT, 2) void gemm_f64_kernel(const double* __restric
       const bufrsrc abuf = make_buf(A + (int64_t)min(k0, ke) * lda + i0, (int64_t)(ke - min(k0, ke)) * lda * 8);
       const bufrsrc zbuf = make_buf(Z + (int64_t)j0 * ldz + k0, (int64_t)(n - j0) * ldz * 8);
       const bool kin = k0 + bk < ke;
+      ka = k0;
 #pragma unroll
       for (int r = 0; r < AR; ++r) ra[r] = buf_f64(abuf, aoff[r]);
 #pragma unroll
       for (int r = 0; r < BR; ++r) rb[r] = buf_f64(zbuf, kin ? boff[r] : kOOB);
     };
     auto store = [&]() {
+      if (MODE == GEMM_SYMH && ka < i0 + BM) {
+        // the diagonal block (uniform test): below the diagonal 0, on it half
+#pragma unroll
+        for (int r = 0; r < AR; ++r) {
+          const int d = ka + ak + 4 * r - (i0 + ai);
+          ra[r] = d < 0 ? 0.0 : (d == 0 ? 0.5 * ra[r] : ra[r]);
+        }
+      }
 #pragma unroll
       for (int r = 0; r < AR; ++r) As[ak + 4 * r][ai] = ra[r];
 #pragma unroll
@@ -207,9 +224,9 @@ __global__ __launch_bounds__(NT, 2) void gemm_f64_kernel(const double* __restric
     }
   };
 
-  if (MODE == GEMM_UPPER) {
+  if (MODE == GEMM_UPPER || MODE == GEMM_SYMH) {
     Seg sa, sb;
-    const bool two = upper_segments(m, blockIdx.x, blockIdx.z, gridDim.z, BK64, sa, sb);
+    const bool two = upper_segments(m, blockIdx.x, blockIdx.z, gridDim.z, BK64, sa, sb, MODE == GEMM_SYMH);
     segment(sa.tile * BM, sa.k0, sa.k1);
     if (two) segment(sb.tile * BM, sb.k0, sb.k1);
   } else if (MODE == GEMM_DIAG) {
@@ -701,6 +718,22 @@ hipError_t launch_symm_upper(const double* A, int64_t lda, const double* Z, int6
   else
     OQR_GEMM_F64(cb, GEMM_UPPER, dim3(P, ycb, H), out, ldo, 0, stride, nullptr, 0);
   return hipGetLastError();
+}
+
+hipError_t launch_symm_half(const double* A, int64_t lda, const double* Z, int64_t ldz, double* W, int64_t ldw,
+                            int64_t m, int64_t n, double* kpart, hipStream_t s) {
+  const int cb = col_blocks(n);
+  const int R = ceil_div(m, BM), P = (R + 1) / 2, ycb = ceil_div(n, 64 * cb);
+  const int H = symm_layers(m, n, kpart);
+  double* out = H > 1 ? kpart : W;
+  const int64_t ldo = H > 1 ? m : ldw, stride = H > 1 ? m * n : 0;
+  OQR_GEMM_F64(cb, GEMM_SYMH, dim3(P, ycb, H), out, ldo, 0, stride, nullptr, 0);
+  return hipGetLastError();
+}
+
+hipError_t launch_layer_sum(const double* kpart, int layers, int64_t m, int64_t n, double* W, int64_t ldw,
+                            hipStream_t s) {
+  return layers > 1 ? ksum(kpart, layers, m, n, W, ldw, s) : hipSuccess;
 }
 
 hipError_t launch_symm_finish(const double* A, int64_t lda, const double* Z, int64_t ldz, double* Woff, double* Wsym,
