@@ -8,10 +8,10 @@
 //       the pivot is applied as a product with 1/r_kk (computed once per
 //       workgroup), which perturbs r_kk by one more rounding and keeps the
 //       componentwise backward error bound.
-// A workgroup owns BMR rows x all n columns, staged once in LDS (Z is read
-// from HBM once and Q written once, column-coalesced, at the end); BMR = 64
-// for n <= 128 and 32 above, so that two workgroups fit in one CU's LDS.  Q may
+// A workgroup owns BMR = 64 rows x all n <= 128 columns, staged once in LDS (Z is
+// read from HBM once and Q written once, column-coalesced, at the end).  Q may
 // alias Z: the whole row block of Z is in LDS before any of its Q is written.
+// For 128 < n <= 256, trsm_wide_kernel (32-row blocks, right-looking updates).
 #include "common.hpp"
 
 namespace oqr {
@@ -168,6 +168,157 @@ __global__ __launch_bounds__(NT, 2) void trsm_kernel(const double* Z, int64_t ld
     const int i = t % BMR, jq = t / BMR;
     if (i0 + i < m) {
       for (int j = jq; j < n; j += STRIDE) Q[(int64_t)j * ldq + i0 + i] = Qs[j * LDQ + i];
+    }
+  }
+}
+
+// Right-looking variant for 128 < n <= 256 (32-row blocks, two workgroups per CU): after the
+// substitution of column block J, every column right of it is updated at once,
+//   Z_{>J} -= Q_J R_{J,>J}            FP64 MFMA, one K step of 32 per update,
+// so that a wave owns up to four 16-column tiles of both 16-row blocks (eight independent chains,
+// each pair sharing its R fragments) instead of one chain over all earlier columns.  The R fragments
+// of the update (row block J of R, columns right of it) are requested before the substitution and
+// arrive while it runs, and the next diagonal block of R one block ahead.  The substitution itself
+// is the one of trsm_kernel (4 lanes per row, FP64, pivots as products with 1/r_kk).
+constexpr int WNMAX = 256, WBMR = 32, WLDQ = WBMR + 1;
+constexpr int WCT = 4;                       // column tiles per wave (up to 14 right of block 0)
+__global__ __launch_bounds__(NT, 2) void trsm_wide_kernel(const double* Z, int64_t ldz, const double* __restrict__ R,
+                                                          int64_t ldr, double* Q, int64_t ldq, int m, int n,
+                                                          const int32_t* __restrict__ info) {
+  __shared__ double Qs[WNMAX * WLDQ];        // Qs[j * WLDQ + i]: row i of the block, column j
+  __shared__ __attribute__((aligned(16))) double RZ[JB][JB];
+  __shared__ double rinv[JB];
+  if (info[0] != 0) return;
+  const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+  const int i0 = blockIdx.x * WBMR;
+  const int nblk = (n + JB - 1) / JB;
+  const int nct = (n + 15) / 16;             // 16-column tiles of Q
+  const bufrsrc rb_ = make_buf(R, ((int64_t)(n - 1) * ldr + n) * 8);
+
+  // load the Z row block (column-major: 32 contiguous rows per column)
+  {
+    constexpr int STRIDE = NT / WBMR;
+    const int i = t % WBMR, jq = t / WBMR;
+    const bool ok = i0 + i < m;
+#pragma unroll
+    for (int jb = 0; jb < WNMAX; jb += 16 * STRIDE) {
+      double v[16];
+#pragma unroll
+      for (int u = 0; u < 16; ++u) {
+        const int j = jb + jq + STRIDE * u;
+        v[u] = sel_load(Z, (int64_t)j * ldz + i0 + i, ok && j < n);
+      }
+#pragma unroll
+      for (int u = 0; u < 16; ++u) Qs[(jb + jq + STRIDE * u) * WLDQ + i] = v[u];
+    }
+  }
+
+  const int li = lane >> 4, lj = lane & 15;
+  const int row = t >> 2, sub = t & 3;       // substitution: 4 lanes per row
+  // R_JJ entries of this thread (strictly upper part per column owner; zero elsewhere) and, for t < 32,
+  // the pivot r_kk: requested one block ahead (branch-free buffer loads, masked entries read zero)
+  double rzp[JB * JB / NT], rdp = 1.0;
+  auto fetch_diag = [&](int J) {
+    const int j0 = J * JB;
+#pragma unroll
+    for (int w = 0; w < JB * JB / NT; ++w) {
+      const int idx = t + NT * w, c = idx / JB, q = idx % JB, sb = q >> 3, e = q & 7;
+      const int col = sb + 4 * e, gr = j0 + c, gc = j0 + col;
+      const uint32_t msk = (col > c && gc < n) ? 0u : kOOB;
+      rzp[w] = buf_f64(rb_, (uint32_t)((int64_t)gc * ldr + gr) * 8u | msk);
+    }
+    const int g = j0 + (t & (JB - 1));
+    rdp = buf_f64(rb_, (uint32_t)((int64_t)g * ldr + g) * 8u | (g < n ? 0u : kOOB));
+  };
+  fetch_diag(0);
+  for (int J = 0; J < nblk; ++J) {
+    const int j0 = J * JB;
+    // R_JJ into LDS (RZ, rinv); the previous block's update (the last reader of RZ is the previous
+    // substitution) ended with a barrier
+#pragma unroll
+    for (int w = 0; w < JB * JB / NT; ++w) {
+      const int idx = t + NT * w;
+      RZ[idx / JB][idx % JB] = rzp[w];
+    }
+    if (t < JB) rinv[t] = (j0 + t < n) ? 1.0 / rdp : 1.0;
+    if (J + 1 < nblk) fetch_diag(J + 1);     // in flight during this block's substitution and update
+    // R fragments of this block's update: the wave's column tiles are ct0 + wave + 4 v; lane (li, lj)
+    // holds R(j0 + 4 s + li, 16 ct + lj), s = 0..7.  Columns past n, or tiles past the last, read zero.
+    const int ct0 = (j0 + JB) / 16;
+    double bf[WCT][8];
+#pragma unroll
+    for (int v = 0; v < WCT; ++v) {
+      const int ct = ct0 + wave + 4 * v, col = 16 * ct + lj;
+      const uint32_t base = (uint32_t)((int64_t)col * ldr + j0 + li) * 8u;
+      const uint32_t msk = (ct < nct && col < n) ? 0u : kOOB;
+#pragma unroll
+      for (int s2 = 0; s2 < 8; ++s2) bf[v][s2] = buf_f64(rb_, (base + 32u * s2) | msk);
+    }
+    __syncthreads();
+    // substitution on the 32 columns of block J: lane `sub` of a row owns columns sub + 4e
+    if (row < WBMR) {
+      double x[8];
+#pragma unroll
+      for (int e = 0; e < 8; ++e) x[e] = Qs[(j0 + sub + 4 * e) * WLDQ + row];
+      double rzc[8], rzn[8], ric = rinv[0], rin = 1.0;
+#pragma unroll
+      for (int e = 0; e < 8; ++e) rzc[e] = RZ[0][sub * 8 + e];
+#pragma unroll
+      for (int c = 0; c < JB; ++c) {
+        if (c + 1 < JB) {
+#pragma unroll
+          for (int e = 0; e < 8; ++e) rzn[e] = RZ[c + 1][sub * 8 + e];
+          rin = rinv[c + 1];
+        }
+        const int owner = c & 3, ec = c >> 2;
+        const double q = quad_bcast(x[ec] * ric, owner);
+#pragma unroll
+        for (int e = 0; e < 8; ++e)
+          if (4 * e + 3 > c) x[e] = __builtin_fma(-q, rzc[e], x[e]);
+        x[ec] = (sub == owner) ? q : x[ec];
+#pragma unroll
+        for (int e = 0; e < 8; ++e) rzc[e] = rzn[e];
+        ric = rin;
+      }
+#pragma unroll
+      for (int e = 0; e < 8; ++e) Qs[(j0 + sub + 4 * e) * WLDQ + row] = x[e];
+    }
+    __syncthreads();
+    // right-looking update of the columns right of block J: independent 16 x 16 tiles, K = 32
+    if (j0 + JB < n) {
+      double a[2][8];                        // -Q(16 rb + lj, j0 + 4 s + li) for both row blocks
+#pragma unroll
+      for (int rb = 0; rb < 2; ++rb)
+#pragma unroll
+        for (int s2 = 0; s2 < 8; ++s2) a[rb][s2] = -Qs[(j0 + 4 * s2 + li) * WLDQ + 16 * rb + lj];
+#pragma unroll
+      for (int v = 0; v < WCT; ++v) {
+        const int ct = ct0 + wave + 4 * v;
+        if (ct < nct) {                      // wave-uniform
+          f64x4 acc[2];
+#pragma unroll
+          for (int rb = 0; rb < 2; ++rb)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) acc[rb][r] = Qs[(16 * ct + lj) * WLDQ + 16 * rb + 4 * r + li];
+#pragma unroll
+          for (int s2 = 0; s2 < 8; ++s2)
+#pragma unroll
+            for (int rb = 0; rb < 2; ++rb) acc[rb] = mfma_f64(a[rb][s2], bf[v][s2], acc[rb]);
+#pragma unroll
+          for (int rb = 0; rb < 2; ++rb)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) Qs[(16 * ct + lj) * WLDQ + 16 * rb + 4 * r + li] = acc[rb][r];
+        }
+      }
+    }
+    __syncthreads();
+  }
+  // store Q: column-major, 32 contiguous rows per column
+  {
+    constexpr int STRIDE = NT / WBMR;
+    const int i = t % WBMR, jq = t / WBMR;
+    if (i0 + i < m) {
+      for (int j = jq; j < n; j += STRIDE) Q[(int64_t)j * ldq + i0 + i] = Qs[j * WLDQ + i];
     }
   }
 }
@@ -510,7 +661,7 @@ hipError_t launch_trsm(const double* Z, int64_t ldz, const double* R, int64_t ld
   else if (n <= 128)
     trsm_kernel<128, 64><<<ceil_div(m, 64), NT, 0, s>>>(Z, ldz, R, ldr, Q, ldq, (int)m, (int)n, info);
   else
-    trsm_kernel<256, 32><<<ceil_div(m, 32), NT, 0, s>>>(Z, ldz, R, ldr, Q, ldq, (int)m, (int)n, info);
+    trsm_wide_kernel<<<ceil_div(m, WBMR), NT, 0, s>>>(Z, ldz, R, ldr, Q, ldq, (int)m, (int)n, info);
   return hipGetLastError();
 }
 
