@@ -239,11 +239,17 @@ int cholqr_pass(const oqr_op* A, const double* Z, int64_t ldz, int64_t m, int64_
   if (A->kind == OQR_OP_DENSE) {
     const double* a = (const double*)A->a;
     if (prec == OQR_P_FP64) {
-      // W' = (U + D/2) Z, then G = Z^T W' + W'^T Z: the diagonal blocks ride in the product
+      // W' = (U + D/2) Z, then G = Z^T W' + W'^T Z: the diagonal blocks ride in the product; for
+      // 128 < n <= 256 the Gram adds the product's layers as it loads them
+      const int H = symm_layers(m, n, w.kpart);
       OQR_TRACED(K_GEMM_F64, s, launch_symm_half(a, A->lda, Z, ldz, w.W, m, m, n, w.kpart, s));
-      if (symm_layers(m, n, w.kpart) > 1)
-        OQR_TRACED(K_SYMM_DIAG, s, launch_layer_sum(w.kpart, symm_layers(m, n, w.kpart), m, n, w.W, m, s));
-      OQR_TRACED(K_GRAM, s, launch_gram_symm(Z, ldz, w.W, w.W, m, m, n, w.partial, w.G, s));
+      if (n > 128) {
+        OQR_TRACED(K_GRAM, s, launch_gram_symm_layers(Z, ldz, H > 1 ? w.kpart : w.W, m, (int64_t)m * n, H, m, n,
+                                                      w.partial, w.G, s));
+      } else {
+        if (H > 1) OQR_TRACED(K_SYMM_DIAG, s, launch_layer_sum(w.kpart, H, m, n, w.W, m, s));
+        OQR_TRACED(K_GRAM, s, launch_gram_symm(Z, ldz, w.W, w.W, m, m, n, w.partial, w.G, s));
+      }
     } else if (prec == OQR_P_FP32) {
       OQR_TRACED(K_GEMM_SPLIT, s, launch_symm_upper(a, A->lda, Z, ldz, w.W, m, m, n, w.kpart, s, true));
       OQR_TRACED(K_SYMM_DIAG, s,

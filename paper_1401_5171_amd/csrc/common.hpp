@@ -164,6 +164,10 @@ hipError_t launch_sparse_apply(const oqr_op* op, const double* Z, int64_t ldz, d
 
 // Gram: partial[c] = (X^T Y) restricted to row chunk c, upper 64x64 tiles; then G = sum_c partial[c].
 size_t gram_partial_bytes(int64_t m, int64_t n);
+// G = Z^T W + W^T Z (upper triangle, both triangles written) for 128 < n <= 256, W the sum of `layers`
+// m x n layers W + h wstride (leading dimension ldw), added in layer order as they are loaded.
+hipError_t launch_gram_symm_layers(const double* Z, int64_t ldz, const double* W, int64_t ldw, int64_t wstride,
+                                  int layers, int64_t m, int64_t n, double* partial, double* G, hipStream_t s);
 // G = Z^T Wsym + Woff^T Z (upper triangle; both products accumulated in the same tiles, one pass).
 hipError_t launch_gram_symm(const double* Z, int64_t ldz, const double* Wsym, const double* Woff, int64_t ldw,
                             int64_t m, int64_t n, double* partial, double* G, hipStream_t s);

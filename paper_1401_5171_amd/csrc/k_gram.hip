@@ -385,6 +385,111 @@ __global__ __launch_bounds__(NT, 2) void gram_full_f64_kernel(const double* __re
         }
 }
 
+// ---- all upper tiles per workgroup, 128 < n <= 256, symmetric assembly from layers --------------
+// G = Z^T W + W^T Z (upper triangle) with W = sum_h Y_h, the H partial layers of the product summed as
+// they are loaded (in layer order, as the layer sum would): the FP64 dense pass's W' = T Z needs no
+// separate sum.  Eight waves, one workgroup per CU; a workgroup owns a chunk of rows and the ten upper
+// 64 x 64 tiles, so Z and W are read once: waves 0-3 take tiles (0,0) (0,1) (0,2) (0,3) (1,1), waves
+// 4-7 tiles (1,2) (1,3) (2,2) (2,3) (3,3); wave w owns rows 16 (w & 3) .. of block I of its tiles.
+constexpr int NTW = 512, NBW = 4, WTILE = 5;
+constexpr int WT_I[2][WTILE] = {{0, 0, 0, 0, 1}, {1, 1, 2, 2, 3}};
+constexpr int WT_J[2][WTILE] = {{0, 1, 2, 3, 1}, {2, 3, 2, 3, 3}};
+
+FullPlan wide_plan(int64_t m) {
+  FullPlan p;
+  const int cus = device_cu_count();
+  int64_t kc = (m + cus - 1) / cus;
+  if (kc < BK) kc = BK;
+  kc = (kc + BK - 1) / BK * BK;
+  p.kc = (int)kc;
+  p.chunks = ceil_div(m, kc);
+  return p;
+}
+
+template <int G>
+__device__ __forceinline__ void wide_tiles(const double (&Xs)[NBW][BK][TB + 1], const double (&Ys)[NBW][BK][TB + 1],
+                                           int kr, int rw, int lj, f64x4 (&acc)[WTILE][4]) {
+#pragma unroll
+  for (int u = 0; u < WTILE; ++u) {
+    const int I = WT_I[G][u], J = WT_J[G][u];
+    const double a = Xs[I][kr][rw + lj], a2 = Ys[I][kr][rw + lj];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      acc[u][q] = mfma_f64(a, Ys[J][kr][q * 16 + lj], acc[u][q]);
+      acc[u][q] = mfma_f64(a2, Xs[J][kr][q * 16 + lj], acc[u][q]);
+    }
+  }
+}
+
+__global__ __launch_bounds__(NTW, 1) void gram_wide_symm_kernel(const double* __restrict__ X, int64_t ldx,
+                                                                 const double* __restrict__ Y, int64_t ldy,
+                                                                 int64_t ystride, int layers, int m, int n, int kc,
+                                                                 double* __restrict__ partial) {
+  __shared__ double Xs[NBW][BK][TB + 1];
+  __shared__ double Ys[NBW][BK][TB + 1];
+  const int c = blockIdx.x;
+  const int r0 = c * kc, r1 = min(m, r0 + kc);
+  const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+  const int li = lane >> 4, lj = lane & 15;
+  const int grp = wave >> 2, rw = 16 * (wave & 3);
+  // thread: row k = t % BK of the step, columns lc + 32 q (q = 0..7); columns past n lie beyond the
+  // size bound of the resource and read zero, rows past r1 are masked
+  const int lk = t % BK, lc = t / BK;
+  const bufrsrc xb = make_buf(X + r0, ((int64_t)(n - 1) * ldx + (m - r0)) * 8);
+  double rx[8], ry[8];
+  auto load = [&](int k0) {
+    const int k = k0 + lk;
+    const uint32_t mk = k < r1 ? 0u : kOOB;
+#pragma unroll
+    for (int q = 0; q < 8; ++q) rx[q] = buf_f64(xb, ((uint32_t)((int64_t)(lc + 32 * q) * ldx + (k - r0)) * 8u) | mk);
+#pragma unroll
+    for (int q = 0; q < 8; ++q) ry[q] = 0.0;
+    for (int h = 0; h < layers; ++h) {
+      const bufrsrc yb = make_buf(Y + h * ystride + r0, ((int64_t)(n - 1) * ldy + (m - r0)) * 8);
+      double v[8];
+#pragma unroll
+      for (int q = 0; q < 8; ++q) v[q] = buf_f64(yb, ((uint32_t)((int64_t)(lc + 32 * q) * ldy + (k - r0)) * 8u) | mk);
+#pragma unroll
+      for (int q = 0; q < 8; ++q) ry[q] += v[q];
+    }
+  };
+  f64x4 acc[WTILE][4];
+#pragma unroll
+  for (int u = 0; u < WTILE; ++u)
+#pragma unroll
+    for (int q = 0; q < 4; ++q) acc[u][q] = f64x4{0, 0, 0, 0};
+  load(r0);
+  for (int k0 = r0; k0 < r1; k0 += BK) {
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      const int col = lc + 32 * q;
+      Xs[col >> 6][lk][col & 63] = rx[q];
+      Ys[col >> 6][lk][col & 63] = ry[q];
+    }
+    __syncthreads();
+    load(k0 + BK);                            // past r1: masked, zeros
+#pragma unroll
+    for (int kk = 0; kk < BK; kk += 4) {
+      if (grp == 0) wide_tiles<0>(Xs, Ys, kk + li, rw, lj, acc);
+      else wide_tiles<1>(Xs, Ys, kk + li, rw, lj, acc);
+    }
+    __syncthreads();
+  }
+  double* P = partial + (int64_t)c * n * n;
+#pragma unroll
+  for (int u = 0; u < WTILE; ++u) {
+    const int I = grp ? WT_I[1][u] : WT_I[0][u], J = grp ? WT_J[1][u] : WT_J[0][u];
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int i = I * TB + rw + 4 * r + li;
+        const int j = J * TB + q * 16 + lj;
+        if (i < n && j < n) P[(int64_t)j * n + i] = acc[u][q][r];
+      }
+  }
+}
+
 template <int S, int NBT>
 __global__ __launch_bounds__(NT, 2) void gram_full_split_kernel(const double* __restrict__ X, int64_t ldx,
                                                                const double* __restrict__ Y, int64_t ldy, int m,
@@ -895,6 +1000,10 @@ StencilPlan stencil_plan(int64_t sxy, int64_t nz) {
 size_t gram_partial_bytes(int64_t m, int64_t n) {
   GramPlan p = plan(m, n);
   size_t b = (size_t)p.chunks * n * n * sizeof(double);
+  if (n > 2 * TB && n <= NBW * TB) {
+    const size_t bw = (size_t)wide_plan(m).chunks * n * n * sizeof(double);
+    if (bw > b) b = bw;
+  }
   if (n <= 2 * TB) {
     const FullPlan f = full_plan(m, BK), g = full_plan(m, BKS);
     const size_t bf = (size_t)(f.chunks > g.chunks ? f.chunks : g.chunks) * n * n * sizeof(double);
@@ -938,6 +1047,16 @@ hipError_t launch_gram_f64(const double* X, int64_t ldx, const double* Y, int64_
 hipError_t launch_gram_symm(const double* Z, int64_t ldz, const double* Wsym, const double* Woff, int64_t ldw,
                             int64_t m, int64_t n, double* partial, double* G, hipStream_t s) {
   return gram_f64<true>(Z, ldz, Wsym, ldw, Woff, ldw, m, n, partial, G, s);
+}
+
+hipError_t launch_gram_symm_layers(const double* Z, int64_t ldz, const double* W, int64_t ldw, int64_t wstride,
+                                  int layers, int64_t m, int64_t n, double* partial, double* G, hipStream_t s) {
+  if (n <= 2 * TB || n > NBW * TB || layers < 1) return hipErrorInvalidValue;
+  const FullPlan f = wide_plan(m);
+  gram_wide_symm_kernel<<<f.chunks, NTW, 0, s>>>(Z, ldz, W, ldw, wstride, layers, (int)m, (int)n, f.kc, partial);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  return reduce(partial, n, f.chunks, G, s);
 }
 
 hipError_t launch_gram_fp32(const double* X, int64_t ldx, const double* Y, int64_t ldy, int64_t m, int64_t n,
