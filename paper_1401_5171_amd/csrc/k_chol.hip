@@ -83,6 +83,7 @@ __global__ __launch_bounds__(NTC) void chol_kernel(const double* __restrict__ G,
                                                     int max_retries, int32_t* __restrict__ info,
                                                     double* __restrict__ shift_used) {
   __shared__ double Dk[1][CB][CB + 1];         // the diagonal block of block row K
+  __shared__ double Dz[CB][CB + 1];            // its factor's strictly upper part, zero elsewhere
   __shared__ double P[CB][OQR_MAX_N + 2];     // block row K: P[p][j] = entry (k0 + p, j), j absolute column;
                                               // after the solve of row K, row K of R
   __shared__ double red[NW];
@@ -243,8 +244,10 @@ __global__ __launch_bounds__(NTC) void chol_kernel(const double* __restrict__ G,
 #pragma unroll
       for (int e = 0; e < DPT; ++e) {
         const int di = (t + NTC * e) >> 5, dj = (t + NTC * e) & 31;
+        Dz[di][dj] = (di < dj) ? Dk[0][di][dj] : 0.0;
         if (k0 + di < n && k0 + dj < n) R[(int64_t)(k0 + dj) * ldr + k0 + di] = (di <= dj) ? Dk[0][di][dj] : 0.0;
       }
+      __syncthreads();
       {
         const int sub = t & 3;
         for (int cb = k0 + CB; cb < n; cb += NTC / 4) {
@@ -259,11 +262,10 @@ __global__ __launch_bounds__(NTC) void chol_kernel(const double* __restrict__ G,
             // branch-free: every lane scales, the owner's value is broadcast
             const double q = quad_bcast(x[ep] * rdiag[p], owner);
             if (sub == owner) x[ep] = q;
+            // entries at or left of the pivot meet a zero of Dz: x - 0 q = x, no select
 #pragma unroll
-            for (int e = 0; e < 8; ++e) {
-              const double upd = x[e] - Dk[0][p][sub + 4 * e] * q;
-              x[e] = (sub + 4 * e > p) ? upd : x[e];
-            }
+            for (int e = 0; e < 8; ++e)
+              if (4 * e + 3 > p) x[e] = x[e] - Dz[p][sub + 4 * e] * q;
             __builtin_amdgcn_sched_barrier(0);   // keep the LDS reads of one pivot row together
           }
           if (ok) {
