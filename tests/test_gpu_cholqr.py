@@ -80,9 +80,11 @@ def test_config2_shape_kappa_sweep(kz):
 
 
 @pytest.mark.parametrize("m,n", [(1, 1), (7, 3), (65, 65), (130, 1), (1000, 37), (777, 100), (1531, 129), (600, 256),
-                                 (3000, 50), (5003, 130)])
+                                 (3000, 50), (5003, 130), (257, 129), (2049, 200), (3333, 161), (4133, 255)])
 def test_ragged_shapes(m, n):
-    """Sizes that leave partial tiles in every kernel (and m = n, n = 1)."""
+    """Sizes that leave partial tiles in every kernel (and m = n, n = 1); for 128 < n <= 256 the
+    right-looking substitution (partial 16-column tiles, a last block narrower than 32) and the
+    all-tiles Gram that adds the product's layers as it loads them."""
     ka = 1e3 if m > 1 else 1.0
     a, z = dense_case(90, m, n, ka, 10.0)
     banner(f"ragged m={m} n={n}")
@@ -93,14 +95,15 @@ def test_ragged_shapes(m, n):
     assert metrics.r_forward_error(r, r0) <= 10 * n * U * np.linalg.cond(r0) + 1e-15
 
 
-def test_in_place_q_aliases_z():
-    a, z = dense_case(91, 700, 24, 1e4, 1e3)
+@pytest.mark.parametrize("m,n", [(700, 24), (1100, 200)])
+def test_in_place_q_aliases_z(m, n):
+    a, z = dense_case(91, m, n, 1e4, 1e3)
     A = to_dev(a)
     Z = to_dev_colmajor(z)
-    plan = oqr.Plan("cholqr2", A, 24)
+    plan = oqr.Plan("cholqr2", A, n)
     import torch
-    R = torch.empty(24, 24, dtype=torch.float64, device="cuda").t()
-    banner("in place")
+    R = torch.empty(n, n, dtype=torch.float64, device="cuda").t()
+    banner(f"in place m={m} n={n}")
     plan.run(Z, Z, R)
     assert int(plan.info.item()) == 0
     q, r = to_host(Z), to_host(R)
