@@ -718,12 +718,26 @@ __global__ __launch_bounds__(NT, 2) void stencil_gram_kernel(const double* __res
       yp[q] = buf_f64(zb[q], op);
     }
   };
-  constexpr int NTILE = NBT * (NBT + 1) / 2;
-  f64x4 acc[NTILE][4];
+  // Diagonal tiles (I, I): only their 16 x 16 blocks on or above the diagonal are needed (10 of 16);
+  // those NBT x 10 blocks are dealt to the waves in turn (block wave + 4 v), so that no wave computes
+  // a block the reduction never reads.  Off-diagonal tiles: wave w owns their rows 16 w .. 16 w + 15.
+  // Every output element accumulates over the same K in the same order either way.
+  constexpr int ND = 10 * NBT, DV = (ND + 3) / 4, NOFF = NBT * (NBT - 1) / 2;
+  f64x4 accd[DV];
+  f64x4 acco[NOFF > 0 ? NOFF : 1][4];
 #pragma unroll
-  for (int u = 0; u < NTILE; ++u)
+  for (int v = 0; v < DV; ++v) accd[v] = f64x4{0, 0, 0, 0};
 #pragma unroll
-    for (int q = 0; q < 4; ++q) acc[u][q] = f64x4{0, 0, 0, 0};
+  for (int u = 0; u < (NOFF > 0 ? NOFF : 1); ++u)
+#pragma unroll
+    for (int q = 0; q < 4; ++q) acco[u][q] = f64x4{0, 0, 0, 0};
+  // block d of the diagonal tiles: tile d / 10, then (row block, column block) in row order
+  auto dblock = [](int d, int& I, int& rb, int& qb) {
+    I = d / 10;
+    const int r = d % 10;
+    rb = r < 4 ? 0 : (r < 7 ? 1 : (r < 9 ? 2 : 3));
+    qb = r < 4 ? r : (r < 7 ? r - 3 : (r < 9 ? r - 5 : 3));
+  };
   // plane z: cm, c0, cp hold the centres of z - 1, z, z + 1; cm is refilled with plane z + 2
   auto step = [&](int z, double (&cm)[NQ], double (&c0)[NQ], double (&cp)[NQ]) {
 #pragma unroll
@@ -742,14 +756,23 @@ __global__ __launch_bounds__(NT, 2) void stencil_gram_kernel(const double* __res
 #pragma unroll
     for (int kk = 0; kk < SP; kk += 4) {
       const int kr = kk + li;
+#pragma unroll
+      for (int v = 0; v < DV; ++v) {
+        const int d = wave + 4 * v;
+        if (d < ND) {                          // wave-uniform
+          int I, rb, qb;
+          dblock(d, I, rb, qb);
+          accd[v] = mfma_f64(Xs[I][kr][rb * 16 + lj], Ys[I][kr][qb * 16 + lj], accd[v]);
+        }
+      }
       int u = 0;
 #pragma unroll
       for (int I = 0; I < NBT; ++I) {
         const double a = Xs[I][kr][wave * 16 + lj];
 #pragma unroll
-        for (int J = I; J < NBT; ++J, ++u)
+        for (int J = I + 1; J < NBT; ++J, ++u)
 #pragma unroll
-          for (int q = 0; q < 4; ++q) acc[u][q] = mfma_f64(a, Ys[J][kr][q * 16 + lj], acc[u][q]);
+          for (int q = 0; q < 4; ++q) acco[u][q] = mfma_f64(a, Ys[J][kr][q * 16 + lj], acco[u][q]);
       }
     }
     __syncthreads();
@@ -767,18 +790,32 @@ __global__ __launch_bounds__(NT, 2) void stencil_gram_kernel(const double* __res
     }
   }
   double* P = partial + (int64_t)blockIdx.x * n * n;
+#pragma unroll
+  for (int v = 0; v < DV; ++v) {
+    const int d = wave + 4 * v;
+    if (d < ND) {
+      int I, rb, qb;
+      dblock(d, I, rb, qb);
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int i = I * TB + rb * 16 + 4 * r + li;
+        const int j = I * TB + qb * 16 + lj;
+        if (i < n && j < n) P[(int64_t)j * n + i] = accd[v][r];
+      }
+    }
+  }
   int u = 0;
 #pragma unroll
   for (int I = 0; I < NBT; ++I)
 #pragma unroll
-    for (int J = I; J < NBT; ++J, ++u)
+    for (int J = I + 1; J < NBT; ++J, ++u)
 #pragma unroll
       for (int q = 0; q < 4; ++q)
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
           const int i = I * TB + wave * 16 + 4 * r + li;
           const int j = J * TB + q * 16 + lj;
-          if (i < n && j < n) P[(int64_t)j * n + i] = acc[u][q][r];
+          if (i < n && j < n) P[(int64_t)j * n + i] = acco[u][q][r];
         }
 }
 
