@@ -450,16 +450,20 @@ __global__ __launch_bounds__(NT, 1) void trsm_persist_kernel(const double* Z, in
 // per CU; every thread carries two rows (t / 4 and t / 4 + 64) through the substitution, so two
 // independent chains share each pivot's R row, and every wave updates four 16-row blocks of one
 // 16-column half on MFMA (four accumulator chains, half the R fragments of a wave in registers).
-// The diagonal blocks of R are kept packed (strictly upper rows only) so that the 128-row tile fits
-// in LDS; the R fragments take the registers a next-tile prefetch would need, so a tile's Z is loaded
-// at its start.  Every row sees the same operations in the same order as in trsm_persist_kernel
-// instantiated for 128 columns (the 64-row layout this one replaces), so the results are identical.
+// Row c of a diagonal block of R is kept from column 4 floor(c / 4) on (the first column a lane of the
+// quad can hold at step c), with zeros in columns <= c, so that the 128-row tile fits in LDS and the
+// update of step c needs no per-lane select: a settled column meets a zero and keeps its value.  The
+// pivot is scaled by 1 / R(c, c) where it is broadcast, and each lane's own columns once the block is
+// done, which gives the same product.  The R fragments take the registers a next-tile prefetch would
+// need, so a tile's Z is loaded at its start.  Every entry is formed by the same operations in the same
+// order as in trsm_persist_kernel instantiated for 128 columns, so the results are identical (but for
+// the sign of an exact zero).
 constexpr int NM2 = 128, BM2 = 128, LDQ2 = BM2 + 1, NBLK2 = NM2 / JB;
-constexpr int RZP = JB * (JB - 1) / 2;          // packed strictly upper entries of one diagonal block
-constexpr int RZO = 1;                            // entry 0 is padding: lane reads of columns <= c (unused)
-                                                  // then stay in the array with no clamp
 
-__host__ __device__ constexpr int rz_row(int c) { return c * (JB - 1) - c * (c - 1) / 2; }   // row c start
+__host__ __device__ constexpr int rz_row(int c) {        // start of row c: groups of four rows of 32 - 4 g
+  return 128 * (c >> 2) - 8 * (c >> 2) * ((c >> 2) - 1) + (c & 3) * (JB - 4 * (c >> 2));
+}
+constexpr int RZP = rz_row(JB);                          // entries of one diagonal block (576)
 
 __global__ __launch_bounds__(NT, 1) void trsm_persist2_kernel(const double* Z, int64_t ldz,
                                                               const double* __restrict__ R, int64_t ldr,
@@ -467,7 +471,7 @@ __global__ __launch_bounds__(NT, 1) void trsm_persist2_kernel(const double* Z, i
                                                               const int32_t* __restrict__ info) {
   constexpr int NF = 8 * NBLK2 * (NBLK2 - 1) / 2;
   __shared__ double Qs[NM2 * LDQ2];               // Qs[j * LDQ2 + i]: row i of the tile, column j
-  __shared__ double RZ[NBLK2][RZO + RZP];         // R(j0 + c, j0 + col), col > c, packed by rows
+  __shared__ double RZ[NBLK2][RZP];               // R(j0 + c, j0 + col), col >= 4 floor(c / 4), by rows
   __shared__ double rinv[NBLK2][JB];
   if (info[0] != 0) return;
   const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
@@ -477,10 +481,9 @@ __global__ __launch_bounds__(NT, 1) void trsm_persist2_kernel(const double* Z, i
     const int J = idx / RZP, k = idx % RZP;
     int c = 0;
     while (k >= rz_row(c + 1)) ++c;
-    const int col = c + 1 + (k - rz_row(c)), gr = J * JB + c, gc = J * JB + col;
-    RZ[J][RZO + k] = (gc < n) ? R[(int64_t)gc * ldr + gr] : 0.0;
+    const int col = 4 * (c >> 2) + (k - rz_row(c)), gr = J * JB + c, gc = J * JB + col;
+    RZ[J][k] = (col > c && gc < n) ? R[(int64_t)gc * ldr + gr] : 0.0;
   }
-  if (t < NBLK2) RZ[t][0] = 0.0;
   for (int idx = t; idx < NBLK2 * JB; idx += NT)
     rinv[idx / JB][idx % JB] = (idx < n) ? 1.0 / R[(int64_t)idx * ldr + idx] : 1.0;
   // MFMA update: wave w owns column half hw = w & 1 of every block and the four 16-row blocks
@@ -548,14 +551,14 @@ __global__ __launch_bounds__(NT, 1) void trsm_persist2_kernel(const double* Z, i
           x0[e] = Qs[(j0 + sub + 4 * e) * LDQ2 + row];
           x1[e] = Qs[(j0 + sub + 4 * e) * LDQ2 + row + 64];
         }
-        // R row c of the block for this lane's columns sub + 4e (> c), staged one step ahead; for
-        // columns <= c the index falls on other entries of the array (>= 0 with the padding entry),
-        // whose values are never used
+        // R row c of the block for this lane's columns sub + 4e, staged one step ahead (columns of
+        // groups below c / 4 are settled for every lane and neither read nor updated)
         double rzc[8], rzn[8], ric = rinv[J][0], rin = 1.0;
-        const double* rzl = &RZ[J][RZO + sub - 1];
+        const double* rzl = &RZ[J][sub];
         auto stage = [&](double (&v)[8], int c) {
 #pragma unroll
-          for (int e = 0; e < 8; ++e) v[e] = rzl[rz_row(c) + 4 * e - c];
+          for (int e = 0; e < 8; ++e)
+            if (4 * e + 3 > c) v[e] = rzl[rz_row(c) + 4 * (e - (c >> 2))];
         };
         stage(rzc, 0);
 #pragma unroll
@@ -570,12 +573,9 @@ __global__ __launch_bounds__(NT, 1) void trsm_persist2_kernel(const double* Z, i
 #pragma unroll
           for (int e = 0; e < 8; ++e)
             if (4 * e + 3 > c) {
-              const bool live = sub + 4 * e > c;
-              x0[e] = live ? __builtin_fma(-q0, rzc[e], x0[e]) : x0[e];
-              x1[e] = live ? __builtin_fma(-q1, rzc[e], x1[e]) : x1[e];
+              x0[e] = __builtin_fma(-q0, rzc[e], x0[e]);
+              x1[e] = __builtin_fma(-q1, rzc[e], x1[e]);
             }
-          x0[ec] = (sub == owner) ? q0 : x0[ec];
-          x1[ec] = (sub == owner) ? q1 : x1[ec];
 #pragma unroll
           for (int e = 0; e < 8; ++e) rzc[e] = rzn[e];
           ric = rin;
@@ -583,8 +583,9 @@ __global__ __launch_bounds__(NT, 1) void trsm_persist2_kernel(const double* Z, i
         }
 #pragma unroll
         for (int e = 0; e < 8; ++e) {
-          Qs[(j0 + sub + 4 * e) * LDQ2 + row] = x0[e];
-          Qs[(j0 + sub + 4 * e) * LDQ2 + row + 64] = x1[e];
+          const double ri = rinv[J][sub + 4 * e];
+          Qs[(j0 + sub + 4 * e) * LDQ2 + row] = x0[e] * ri;
+          Qs[(j0 + sub + 4 * e) * LDQ2 + row + 64] = x1[e] * ri;
         }
       }
       __syncthreads();
