@@ -36,13 +36,20 @@ enum GemmMode { GEMM_FULL = 0, GEMM_UPPER = 1, GEMM_DIAG = 2, GEMM_SYMH = 3 };
 
 struct Seg {
   int tile, k0, k1;
+  bool desc;           // K steps taken from the top of [k0, k1) down
 };
 
 // The row-tile segments of workgroup (pair p, part h) in GEMM_UPPER, K steps of ks: a in tile p and,
 // unless the pair is one tile (returns false), b in tile R - 1 - p.  With diag, a tile's K range starts
-// at its own diagonal block.
+// at its own diagonal block.  A pair's steps form one list, cut into H equal parts (part h takes entries
+// [T h / H, T (h + 1) / H)): tile p's steps, then tile R - 1 - p's, each from its start up; or, with
+// sync, tile p's from the top of K down and then tile R - 1 - p's from its start up.  With sync the
+// list has the same length for every pair (for m a multiple of BM) and its s-th entry lies at the same
+// K for every pair (the top step less ks s while in tile p, then BM + ks (s - na)), so the workgroups
+// of one part walk K together and each K tile of Z is fetched into L2 once rather than once per
+// workgroup.
 __device__ __forceinline__ bool upper_segments(int m, int p, int h, int H, int ks, Seg& a, Seg& b,
-                                               bool diag = false) {
+                                               bool diag = false, bool sync = false) {
   const int R = (m + BM - 1) / BM;
   const int ta = p, tb = R - 1 - p;
   const int d = diag ? 0 : 1;
@@ -50,9 +57,19 @@ __device__ __forceinline__ bool upper_segments(int m, int p, int h, int H, int k
   const int na = (m - sa + ks - 1) / ks, nb = (tb != ta) ? (m - sb + ks - 1) / ks : 0;
   const int T = na + nb;
   const int s0 = (int)((int64_t)T * h / H), s1 = (int)((int64_t)T * (h + 1) / H);
-  a = {ta, min(m, sa + ks * min(s0, na)), min(m, sa + ks * min(s1, na))};
-  b = {tb, min(m, sb + ks * max(s0 - na, 0)), min(m, sb + ks * max(s1 - na, 0))};
+  if (sync)   // entries [s0, min(s1, na)) are tile p's steps na - 1 - s (downward)
+    a = {ta, min(m, sa + ks * (na - min(s1, na))), min(m, sa + ks * (na - min(s0, na))), true};
+  else
+    a = {ta, min(m, sa + ks * min(s0, na)), min(m, sa + ks * min(s1, na)), false};
+  b = {tb, min(m, sb + ks * max(s0 - na, 0)), min(m, sb + ks * max(s1 - na, 0)), false};
   return tb != ta;
+}
+
+// Start of step s of a K range [kb, ke) cut into steps of ks from kb, taken from the top down if desc;
+// past the last step, ke (loads there read nothing and return zeros).
+__device__ __forceinline__ int kpos(int kb, int ke, int ks, int s, bool desc) {
+  const int ns = (ke - kb + ks - 1) / ks;
+  return s >= ns ? ke : (desc ? kb + ks * (ns - 1 - s) : kb + ks * s);
 }
 
 // F32: the FP32 operand pass.  A and Z are rounded to FP32 as they leave LDS and multiplied on
@@ -227,7 +244,7 @@ __global__ __launch_bounds__(NT, 2) void gemm_f64_kernel(const double* __restric
   if (MODE == GEMM_UPPER || MODE == GEMM_SYMH) {
     Seg sa, sb;
     const bool two = upper_segments(m, blockIdx.x, blockIdx.z, gridDim.z, BK64, sa, sb, MODE == GEMM_SYMH);
-    segment(sa.tile * BM, sa.k0, sa.k1);
+    segment(sa.tile * BM, sa.k0, sa.k1);           // ascending (no sync): sa.desc is false
     if (two) segment(sb.tile * BM, sb.k0, sb.k1);
   } else if (MODE == GEMM_DIAG) {
     const int i0 = blockIdx.x * BM;
@@ -263,6 +280,7 @@ __global__ __launch_bounds__(NT, 1) void gemm_split_kernel(const double* __restr
   const int64_t slice_stride = mp * n;
   // the current segment: rows [i0, i0 + BM), K [kb, ke) (kb a multiple of BKS)
   int i0 = 0, kb = 0, ke = 0;
+  bool kdesc = false;          // K steps taken from the top down
   W += blockIdx.z * wstride;
 
   f32x4 acc[4][CB];
@@ -271,8 +289,8 @@ __global__ __launch_bounds__(NT, 1) void gemm_split_kernel(const double* __restr
   const int ai = t % BM, ak = t / BM;
   uint32_t aoff[8];
   double ra0[8], ra1[8], ra2[8];
-  auto load_a = [&](double (&ra)[8], int k0) {
-    k0 += kb;
+  auto load_a = [&](double (&ra)[8], int st) {      // A tile of K step st
+    const int k0 = kpos(kb, ke, BKS, st, kdesc);
     const bufrsrc abuf = make_buf(A + (int64_t)min(k0, ke) * lda + i0, (int64_t)(ke - min(k0, ke)) * lda * 8);
 #pragma unroll
     for (int e = 0; e < 8; ++e) ra[e] = buf_f64(abuf, aoff[e]);
@@ -305,9 +323,9 @@ __global__ __launch_bounds__(NT, 1) void gemm_split_kernel(const double* __restr
     zoff[b] = (j < n) ? (uint32_t)(((int64_t)j * mp + 8 * (lane >> 4)) * 2) : kOOB;
   }
   uint4 bf0[S][CB], bf1[S][CB], bf2[S][CB];
-  auto load_b = [&](int k0, uint4 (&dst)[S][CB]) {
-    // rows k0 .. k0 + 31 of every slice; past the slice (or the padded end) the buffer is empty
-    k0 += kb;
+  auto load_b = [&](int st, uint4 (&dst)[S][CB]) {
+    // rows k0 .. k0 + 31 of every slice (K step st); past the slice (or the padded end) the buffer is empty
+    const int k0 = kpos(kb, ke, BKS, st, kdesc);
     const bool live = k0 < ke || (ke == m && k0 < mp);
     const bufrsrc zbuf = make_buf(zs + min((int64_t)k0, mp), live ? (int64_t)(S * slice_stride - k0) * 2 : 0);
 #pragma unroll
@@ -324,10 +342,10 @@ __global__ __launch_bounds__(NT, 1) void gemm_split_kernel(const double* __restr
   // before A: memory counters retire in order, so the wait for B(st+1) at the next step must not
   // also wait for the HBM loads of A issued after it.
   auto step = [&](int st, const double (&ra_store)[8], double (&ra_fill)[8], const uint4 (&bu)[S][CB],
-                  uint4 (&bfill)[S][CB]) {
+                  uint4 (&bfill)[S][CB]) __attribute__((always_inline)) {
     const int cur = st & 1;
-    load_b((st + 2) * BKS, bfill);
-    load_a(ra_fill, (st + 3) * BKS);
+    load_b(st + 2, bfill);
+    load_a(ra_fill, st + 3);
     const int kq = 8 * (lane >> 4);
     bf16x8 af[S][4];
 #pragma unroll
@@ -379,10 +397,10 @@ __global__ __launch_bounds__(NT, 1) void gemm_split_kernel(const double* __restr
   for (int e = 0; e < 8; ++e) aoff[e] = (i0 + ai < m) ? (uint32_t)(((int64_t)(ak * 8 + e) * lda + ai) * 8) : kOOB;
   const int nsteps = ((ke - kb + BKS - 1) / BKS + 5) / 6 * 6;
   load_b(0, bf0);
-  load_b(BKS, bf1);
+  load_b(1, bf1);
   load_a(ra0, 0);
-  load_a(ra1, BKS);
-  load_a(ra2, 2 * BKS);
+  load_a(ra1, 1);
+  load_a(ra2, 2);
   store_a(ra0, 0);
   __syncthreads();
   for (int st = 0; st < nsteps; st += 6) {
@@ -414,12 +432,12 @@ __global__ __launch_bounds__(NT, 1) void gemm_split_kernel(const double* __restr
 
   if (MODE == GEMM_UPPER) {
     Seg sa, sb;
-    const bool two = upper_segments(m, blockIdx.x, blockIdx.z, gridDim.z, BKS, sa, sb);
-    i0 = sa.tile * BM, kb = sa.k0, ke = sa.k1;
+    const bool two = upper_segments(m, blockIdx.x, blockIdx.z, gridDim.z, BKS, sa, sb, false, true);
+    i0 = sa.tile * BM, kb = sa.k0, ke = sa.k1, kdesc = sa.desc;
     segment();
     if (two) {
       __syncthreads();                  // the last reads of As
-      i0 = sb.tile * BM, kb = sb.k0, ke = sb.k1;
+      i0 = sb.tile * BM, kb = sb.k0, ke = sb.k1, kdesc = sb.desc;
       segment();
     }
   } else {
@@ -449,6 +467,7 @@ __global__ __launch_bounds__(NT2, 1) void gemm_split2_kernel(const double* __res
   constexpr int64_t TILE = (int64_t)S * BN2 * BKS;   // bf16 elements of one K step of the tiled slices
   // the current segment: rows [i0, i0 + BM), K [kb, ke) (kb a multiple of BKS)
   int i0 = 0, kb = 0, ke = 0;
+  bool kdesc = false;          // K steps taken from the top down
   W += blockIdx.z * wstride;
 
   f32x4 acc[4][2];
@@ -543,21 +562,21 @@ __global__ __launch_bounds__(NT2, 1) void gemm_split2_kernel(const double* __res
     // K steps padded to a multiple of 6 (2 A buffers x 3 B stages); steps past the end read empty
     // buffers and add zeros
     const int nsteps = ((ke - kb + BKS - 1) / BKS + 5) / 6 * 6;
-    load_a(kb, ra0);
-    load_b(kb, bq0);
-    load_b(kb + BKS, bq1);
-    load_b(kb + 2 * BKS, bq2);
+    load_a(kpos(kb, ke, BKS, 0, kdesc), ra0);
+    load_b(kpos(kb, ke, BKS, 0, kdesc), bq0);
+    load_b(kpos(kb, ke, BKS, 1, kdesc), bq1);
+    load_b(kpos(kb, ke, BKS, 2, kdesc), bq2);
     store_a(0, ra0);
     __syncthreads();
-    load_a(kb + BKS, ra0);
-    load_a(kb + 2 * BKS, ra1);
+    load_a(kpos(kb, ke, BKS, 1, kdesc), ra0);
+    load_a(kpos(kb, ke, BKS, 2, kdesc), ra1);
     // step st: MFMAs on A buffer st & 1 and B stage st % 3; A(st + 1) into the other buffer; A and B of
     // step st + 3 requested
 #define OQR_SPLIT2_STEP(st, RA, BQ)       \
   compute(st, BQ);                        \
   store_a(((st) + 1) & 1, RA);            \
-  load_a(kb + ((st) + 3) * BKS, RA);      \
-  load_b(kb + ((st) + 3) * BKS, BQ);      \
+  load_a(kpos(kb, ke, BKS, (st) + 3, kdesc), RA); \
+  load_b(kpos(kb, ke, BKS, (st) + 3, kdesc), BQ); \
   __syncthreads();
     for (int st = 0; st < nsteps; st += 6) {
       OQR_SPLIT2_STEP(st + 0, ra0, bq0)
@@ -583,12 +602,12 @@ __global__ __launch_bounds__(NT2, 1) void gemm_split2_kernel(const double* __res
 
   if (MODE == GEMM_UPPER) {
     Seg sa, sb;
-    const bool two = upper_segments(m, blockIdx.x, blockIdx.z, gridDim.z, BKS, sa, sb);
-    i0 = sa.tile * BM, kb = sa.k0, ke = sa.k1;
+    const bool two = upper_segments(m, blockIdx.x, blockIdx.z, gridDim.z, BKS, sa, sb, false, true);
+    i0 = sa.tile * BM, kb = sa.k0, ke = sa.k1, kdesc = sa.desc;
     segment();
     if (two) {
       __syncthreads();                  // the last reads of As
-      i0 = sb.tile * BM, kb = sb.k0, ke = sb.k1;
+      i0 = sb.tile * BM, kb = sb.k0, ke = sb.k1, kdesc = sb.desc;
       segment();
     }
   } else {
