@@ -43,7 +43,7 @@ PEAK = {"fp64": 78.6e12, "bf16": 2.5e15, "hbm": 8.0e12}
 # on; workloads without an entry report null.
 TRAFFIC = {
     ("dense32768", "gemm_f64"): (8529916.3 * 2.0 + 131084.7 * 1.0) * 1024,
-    ("stencil", "gram"): (872679.1 * 2.0 + 98305.0 * 1.0) * 1024,
+    ("stencil", "gram"): (1001810.9 * 2.0 + 73731.6 * 1.0) * 1024,
 }
 
 
