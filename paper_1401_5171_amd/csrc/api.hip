@@ -183,6 +183,7 @@ struct PassWs {
   double* R2;         // n x n (second pass)
   unsigned short* zs; // bf16 slices of Z (dense reduced precision)
   double* kpart;      // split-K partial products of the dense GEMMs (may be empty)
+  int kpart_layers;   // m x n layers in kpart
   double* shifts;     // [2] shift used per pass
 };
 
@@ -210,8 +211,11 @@ size_t pass_ws(const oqr_op* A, int64_t m, int64_t n, const oqr_opts& o, bool tw
     if (two && split_prec(o.pass2) && slices_of(o.pass2) > maxs) maxs = slices_of(o.pass2);
   }
   w.zs = c.take<unsigned short>(maxs ? split_z_elems(m, n, maxs) : 0);
-  const size_t kp = A->kind == OQR_OP_DENSE ? gemm_kpart_bytes(m, n) : 0;
+  // a reduced-precision dense pass with 128 < n <= 256 puts D' Z in a layer after the product's parts
+  const bool reduced = o.pass1 != OQR_P_FP64 || (two && o.pass2 != OQR_P_FP64);
+  const size_t kp = A->kind == OQR_OP_DENSE ? gemm_kpart_bytes(m, n, reduced && n > 128 && n <= 256) : 0;
   w.kpart = kp ? c.take<double>(kp / sizeof(double)) : nullptr;
+  w.kpart_layers = (m > 0 && n > 0) ? (int)(kp / ((size_t)m * n * sizeof(double))) : 0;
   w.shifts = c.take<double>(2);
   if (out) *out = w;
   return c.off;
@@ -250,18 +254,30 @@ int cholqr_pass(const oqr_op* A, const double* Z, int64_t ldz, int64_t m, int64_
         if (H > 1) OQR_TRACED(K_SYMM_DIAG, s, launch_layer_sum(w.kpart, H, m, n, w.W, m, s));
         OQR_TRACED(K_GRAM, s, launch_gram_symm(Z, ldz, w.W, w.W, m, m, n, w.partial, w.G, s));
       }
-    } else if (prec == OQR_P_FP32) {
-      OQR_TRACED(K_GEMM_SPLIT, s, launch_symm_upper(a, A->lda, Z, ldz, w.W, m, m, n, w.kpart, s, true));
-      OQR_TRACED(K_SYMM_DIAG, s,
-                 launch_symm_finish(a, A->lda, Z, ldz, w.W, w.Ws, m, m, n, w.kpart, symm_layers(m, n, w.kpart), s));
     } else {
-      OQR_TRACED(K_SPLIT_Z, s, launch_split_z(Z, ldz, w.zs, m, n, slices_of(prec), s));
-      OQR_TRACED(K_GEMM_SPLIT, s,
-                 launch_symm_split_upper(a, A->lda, w.zs, w.W, m, m, n, slices_of(prec), w.kpart, s));
-      OQR_TRACED(K_SYMM_DIAG, s,
-                 launch_symm_finish(a, A->lda, Z, ldz, w.W, w.Ws, m, m, n, w.kpart, symm_layers(m, n, w.kpart), s));
+      // reduced precision: U Z in the pass's precision, the diagonal blocks in FP64.  For 128 < n <= 256
+      // with the product in layers, D' Z goes to the next layer and the Gram adds them all as it loads
+      // them: G = Z^T W' + W'^T Z as in the FP64 pass.  Otherwise Wsym = Woff + D Z and
+      // G = Z^T Wsym + Woff^T Z.
+      const int H = symm_layers(m, n, w.kpart);
+      const bool layered = n > 128 && n <= 256 && H > 1 && w.kpart_layers > H;
+      if (prec == OQR_P_FP32) {
+        OQR_TRACED(K_GEMM_SPLIT, s, launch_symm_upper(a, A->lda, Z, ldz, w.W, m, m, n, w.kpart, s, true));
+      } else {
+        OQR_TRACED(K_SPLIT_Z, s, launch_split_z(Z, ldz, w.zs, m, n, slices_of(prec), s));
+        OQR_TRACED(K_GEMM_SPLIT, s,
+                   launch_symm_split_upper(a, A->lda, w.zs, w.W, m, m, n, slices_of(prec), w.kpart, s));
+      }
+      if (layered) {
+        const int64_t mn = (int64_t)m * n;
+        OQR_TRACED(K_SYMM_DIAG, s, launch_symm_diag_half(a, A->lda, Z, ldz, w.kpart + H * mn, m, m, n, s));
+        OQR_TRACED(K_GRAM, s, launch_gram_symm_layers(Z, ldz, w.kpart, m, mn, H + 1, m, n, w.partial, w.G, s));
+      } else {
+        OQR_TRACED(K_SYMM_DIAG, s,
+                   launch_symm_finish(a, A->lda, Z, ldz, w.W, w.Ws, m, m, n, w.kpart, H, s));
+        OQR_TRACED(K_GRAM, s, gram_symm(Z, ldz, m, n, w, s));
+      }
     }
-    if (prec != OQR_P_FP64) OQR_TRACED(K_GRAM, s, gram_symm(Z, ldz, m, n, w, s));
   } else if (stencil_fused(A, ldz, n, prec)) {
     if (prec == OQR_P_FP64)
       OQR_TRACED(K_GRAM, s, launch_stencil_gram(A, Z, ldz, n, w.partial, w.G, s));

@@ -123,8 +123,9 @@ int device_cu_count();
 
 // W (m x n, ldw) = A (m x m, lda) * Z (m x n, ldz), FP64 MFMA.  When the tile grid is too small for
 // the device, K is split over workgroups into FP64 partial products in kpart (gemm_kpart_bytes; null
-// disables the split) that are then summed in a fixed order.
-size_t gemm_kpart_bytes(int64_t m, int64_t n);
+// disables the split) that are then summed in a fixed order.  diag_layer: one more layer than the
+// symmetric product's parts, for the diagonal blocks of a reduced-precision pass (launch_symm_diag_half).
+size_t gemm_kpart_bytes(int64_t m, int64_t n, bool diag_layer = false);
 hipError_t launch_gemm_f64(const double* A, int64_t lda, const double* Z, int64_t ldz, double* W, int64_t ldw,
                            int64_t m, int64_t n, double* kpart, hipStream_t s);
 // A symmetric, only its upper block triangle read (blocks of 64 rows): Woff = (strictly upper block
@@ -148,6 +149,11 @@ hipError_t launch_symm_half(const double* A, int64_t lda, const double* Z, int64
                             int64_t m, int64_t n, double* kpart, hipStream_t s);
 hipError_t launch_layer_sum(const double* kpart, int layers, int64_t m, int64_t n, double* W, int64_t ldw,
                             hipStream_t s);
+// W = D' Z, FP64, D' the diagonal blocks of A with their lower triangles dropped and their diagonal
+// halved; with the layers of launch_symm_upper / launch_symm_split_upper (U Z) it sums to W' of
+// launch_symm_half, so that a reduced-precision pass can form Z^T A Z = Z^T W' + W'^T Z.
+hipError_t launch_symm_diag_half(const double* A, int64_t lda, const double* Z, int64_t ldz, double* W, int64_t ldw,
+                                 int64_t m, int64_t n, hipStream_t s);
 hipError_t launch_symm_finish(const double* A, int64_t lda, const double* Z, int64_t ldz, double* Woff, double* Wsym,
                               int64_t ldw, int64_t m, int64_t n, const double* kpart, int layers, hipStream_t s);
 // W = A * Z with A split on the fly into `slices` bfloat16 slices and Z pre-split (zs: slices x n

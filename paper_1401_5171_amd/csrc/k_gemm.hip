@@ -31,8 +31,10 @@ constexpr int APAD = 16, BPAD = 14;
 // GEMM_UPPER, but row tile t starts at its own diagonal block, whose entries below the diagonal count as
 // zero and whose diagonal counts half: the product is W' = (U + D/2) Z with U the strictly upper part of
 // A and D the lower-triangle-free diagonal blocks, so that A = (U + D/2) + (U + D/2)^T and
-// Z^T A Z = Z^T W' + W'^T Z.
-enum GemmMode { GEMM_FULL = 0, GEMM_UPPER = 1, GEMM_DIAG = 2, GEMM_SYMH = 3 };
+// Z^T A Z = Z^T W' + W'^T Z.  GEMM_DIAGH: row tile blockIdx.x over its own diagonal block only, with
+// the masking of GEMM_SYMH (D' Z, D' = the upper triangles of the diagonal blocks with the diagonal
+// halved), written as it is: added to U Z (GEMM_UPPER, any precision) it gives W'.
+enum GemmMode { GEMM_FULL = 0, GEMM_UPPER = 1, GEMM_DIAG = 2, GEMM_SYMH = 3, GEMM_DIAGH = 4 };
 
 struct Seg {
   int tile, k0, k1;
@@ -128,7 +130,7 @@ __global__ __launch_bounds__(NT, 2) void gemm_f64_kernel(const double* __restric
       for (int r = 0; r < BR; ++r) rb[r] = buf_f64(zbuf, kin ? boff[r] : kOOB);
     };
     auto store = [&]() {
-      if (MODE == GEMM_SYMH && ka < i0 + BM) {
+      if ((MODE == GEMM_SYMH || MODE == GEMM_DIAGH) && ka < i0 + BM) {
         // the diagonal block (uniform test): below the diagonal 0, on it half
 #pragma unroll
         for (int r = 0; r < AR; ++r) {
@@ -246,7 +248,7 @@ __global__ __launch_bounds__(NT, 2) void gemm_f64_kernel(const double* __restric
     const bool two = upper_segments(m, blockIdx.x, blockIdx.z, gridDim.z, BK64, sa, sb, MODE == GEMM_SYMH);
     segment(sa.tile * BM, sa.k0, sa.k1);           // ascending (no sync): sa.desc is false
     if (two) segment(sb.tile * BM, sb.k0, sb.k1);
-  } else if (MODE == GEMM_DIAG) {
+  } else if (MODE == GEMM_DIAG || MODE == GEMM_DIAGH) {
     const int i0 = blockIdx.x * BM;
     segment(i0, i0, min(m, i0 + BM));
   } else {
@@ -679,11 +681,11 @@ static int upper_parts(int64_t m, int64_t n) {
   return (int)H;
 }
 
-size_t gemm_kpart_bytes(int64_t m, int64_t n) {
+size_t gemm_kpart_bytes(int64_t m, int64_t n, bool diag_layer) {
   const KSplit k = ksplit(m, n);
   int layers = k.ks > 1 ? k.ks : 0;
   const int h = upper_parts(m, n);
-  if (h > 1 && h > layers) layers = h;
+  if (h > 1 && h + (diag_layer ? 1 : 0) > layers) layers = h + (diag_layer ? 1 : 0);
   return (size_t)layers * m * n * sizeof(double);
 }
 
@@ -747,6 +749,13 @@ hipError_t launch_symm_half(const double* A, int64_t lda, const double* Z, int64
   double* out = H > 1 ? kpart : W;
   const int64_t ldo = H > 1 ? m : ldw, stride = H > 1 ? m * n : 0;
   OQR_GEMM_F64(cb, GEMM_SYMH, dim3(P, ycb, H), out, ldo, 0, stride, nullptr, 0);
+  return hipGetLastError();
+}
+
+hipError_t launch_symm_diag_half(const double* A, int64_t lda, const double* Z, int64_t ldz, double* W, int64_t ldw,
+                                 int64_t m, int64_t n, hipStream_t s) {
+  const int cb = col_blocks(n);
+  OQR_GEMM_F64(cb, GEMM_DIAGH, dim3(ceil_div(m, BM), ceil_div(n, 64 * cb), 1), W, ldw, 0, 0, nullptr, 0);
   return hipGetLastError();
 }
 
