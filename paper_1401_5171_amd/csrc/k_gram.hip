@@ -389,11 +389,16 @@ __global__ __launch_bounds__(NT, 2) void gram_full_f64_kernel(const double* __re
 // G = Z^T W + W^T Z (upper triangle) with W = sum_h Y_h, the H partial layers of the product summed as
 // they are loaded (in layer order, as the layer sum would): the FP64 dense pass's W' = T Z needs no
 // separate sum.  Eight waves, one workgroup per CU; a workgroup owns a chunk of rows and the ten upper
-// 64 x 64 tiles, so Z and W are read once: waves 0-3 take tiles (0,0) (0,1) (0,2) (0,3) (1,1), waves
-// 4-7 tiles (1,2) (1,3) (2,2) (2,3) (3,3); wave w owns rows 16 (w & 3) .. of block I of its tiles.
-constexpr int NTW = 512, NBW = 4, WTILE = 5;
-constexpr int WT_I[2][WTILE] = {{0, 0, 0, 0, 1}, {1, 1, 2, 2, 3}};
-constexpr int WT_J[2][WTILE] = {{0, 1, 2, 3, 1}, {2, 3, 2, 3, 3}};
+// 64 x 64 tiles, so Z and W are read once: waves 0-3 take tiles (0,1) (0,2) (0,3) and the diagonal
+// tiles (0,0) (1,1), waves 4-7 tiles (1,2) (1,3) (2,3) and (2,2) (3,3).  Wave w (b = w & 3) owns rows
+// 16 b .. 16 b + 15 of block I of its off-diagonal tiles and of its first diagonal tile, and rows
+// 16 (3 - b) .. of its second; in a diagonal tile only the 16 x 16 blocks on or above the diagonal are
+// formed, so every wave forms 4 - b + b + 1 = 5 of them.  Every entry sums the same products in the
+// same order as when whole diagonal tiles were formed.
+constexpr int NTW = 512, NBW = 4, WOFF = 3;
+constexpr int WO_I[2][WOFF] = {{0, 0, 0}, {1, 1, 2}};
+constexpr int WO_J[2][WOFF] = {{1, 2, 3}, {2, 3, 3}};
+constexpr int WD_T[2][2] = {{0, 1}, {2, 3}};
 
 FullPlan wide_plan(int64_t m) {
   FullPlan p;
@@ -408,16 +413,27 @@ FullPlan wide_plan(int64_t m) {
 
 template <int G>
 __device__ __forceinline__ void wide_tiles(const double (&Xs)[NBW][BK][TB + 1], const double (&Ys)[NBW][BK][TB + 1],
-                                           int kr, int rw, int lj, f64x4 (&acc)[WTILE][4]) {
+                                           int kr, int wb, int lj, f64x4 (&acc)[WOFF][4], f64x4 (&accd)[2][4]) {
 #pragma unroll
-  for (int u = 0; u < WTILE; ++u) {
-    const int I = WT_I[G][u], J = WT_J[G][u];
-    const double a = Xs[I][kr][rw + lj], a2 = Ys[I][kr][rw + lj];
+  for (int u = 0; u < WOFF; ++u) {
+    const int I = WO_I[G][u], J = WO_J[G][u];
+    const double a = Xs[I][kr][16 * wb + lj], a2 = Ys[I][kr][16 * wb + lj];
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
       acc[u][q] = mfma_f64(a, Ys[J][kr][q * 16 + lj], acc[u][q]);
       acc[u][q] = mfma_f64(a2, Xs[J][kr][q * 16 + lj], acc[u][q]);
     }
+  }
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    const int I = WD_T[G][h], b = h ? 3 - wb : wb;   // wb is wave-uniform (scalar): the tests branch
+    const double a = Xs[I][kr][16 * b + lj], a2 = Ys[I][kr][16 * b + lj];
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+      if (q >= b) {
+        accd[h][q] = mfma_f64(a, Ys[I][kr][q * 16 + lj], accd[h][q]);
+        accd[h][q] = mfma_f64(a2, Xs[I][kr][q * 16 + lj], accd[h][q]);
+      }
   }
 }
 
@@ -431,7 +447,7 @@ __global__ __launch_bounds__(NTW, 1) void gram_wide_symm_kernel(const double* __
   const int r0 = c * kc, r1 = min(m, r0 + kc);
   const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
   const int li = lane >> 4, lj = lane & 15;
-  const int grp = wave >> 2, rw = 16 * (wave & 3);
+  const int grp = wave >> 2, wb = __builtin_amdgcn_readfirstlane(wave & 3);
   // thread: row k = t % BK of the step, columns lc + 32 q (q = 0..7); columns past n lie beyond the
   // size bound of the resource and read zero, rows past r1 are masked
   const int lk = t % BK, lc = t / BK;
@@ -453,11 +469,13 @@ __global__ __launch_bounds__(NTW, 1) void gram_wide_symm_kernel(const double* __
       for (int q = 0; q < 8; ++q) ry[q] += v[q];
     }
   };
-  f64x4 acc[WTILE][4];
+  f64x4 acc[WOFF][4], accd[2][4];
 #pragma unroll
-  for (int u = 0; u < WTILE; ++u)
+  for (int q = 0; q < 4; ++q) {
 #pragma unroll
-    for (int q = 0; q < 4; ++q) acc[u][q] = f64x4{0, 0, 0, 0};
+    for (int u = 0; u < WOFF; ++u) acc[u][q] = f64x4{0, 0, 0, 0};
+    accd[0][q] = accd[1][q] = f64x4{0, 0, 0, 0};
+  }
   load(r0);
   for (int k0 = r0; k0 < r1; k0 += BK) {
 #pragma unroll
@@ -470,22 +488,36 @@ __global__ __launch_bounds__(NTW, 1) void gram_wide_symm_kernel(const double* __
     load(k0 + BK);                            // past r1: masked, zeros
 #pragma unroll
     for (int kk = 0; kk < BK; kk += 4) {
-      if (grp == 0) wide_tiles<0>(Xs, Ys, kk + li, rw, lj, acc);
-      else wide_tiles<1>(Xs, Ys, kk + li, rw, lj, acc);
+      if (grp == 0) wide_tiles<0>(Xs, Ys, kk + li, wb, lj, acc, accd);
+      else wide_tiles<1>(Xs, Ys, kk + li, wb, lj, acc, accd);
     }
     __syncthreads();
   }
   double* P = partial + (int64_t)c * n * n;
 #pragma unroll
-  for (int u = 0; u < WTILE; ++u) {
-    const int I = grp ? WT_I[1][u] : WT_I[0][u], J = grp ? WT_J[1][u] : WT_J[0][u];
+  for (int u = 0; u < WOFF; ++u) {
+    const int I = grp ? WO_I[1][u] : WO_I[0][u], J = grp ? WO_J[1][u] : WO_J[0][u];
 #pragma unroll
     for (int q = 0; q < 4; ++q)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const int i = I * TB + rw + 4 * r + li;
+        const int i = I * TB + 16 * wb + 4 * r + li;
         const int j = J * TB + q * 16 + lj;
         if (i < n && j < n) P[(int64_t)j * n + i] = acc[u][q][r];
+      }
+  }
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    const int I = grp ? WD_T[1][h] : WD_T[0][h], b = h ? 3 - wb : wb;
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+      if (q >= b) {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int i = I * TB + 16 * b + 4 * r + li;
+          const int j = I * TB + q * 16 + lj;
+          if (i < n && j < n) P[(int64_t)j * n + i] = accd[h][q][r];
+        }
       }
   }
 }

@@ -241,20 +241,21 @@ def test_mixed_first_pass_matches_emulated_error_level():
     assert metrics.residual_f(z, q, r) <= 1e-12       # FP64 substitution keeps the residual at FP64 level
 
 
-@pytest.mark.parametrize("m,n", [(4096, 256), (3001, 200)])
-def test_mixed_wide_n(m, n):
-    """n > 128 takes the 512-thread split product over K-step-tiled slices of Z: one BF16x3 pass at the
-    emulated error level, and BF16x3 + FP64 CholQR2 at FP64 orthogonality (ragged m and n included)."""
+@pytest.mark.parametrize("m,n,prec", [(4096, 256, "bf16x3"), (3001, 200, "bf16x3"), (2113, 129, "bf16x2")])
+def test_mixed_wide_n(m, n, prec):
+    """n > 128 takes the 512-thread split product over K-step-tiled slices of Z, the diagonal blocks as a
+    layer of their own and the Gram adding the layers as it loads them: one split pass at the emulated
+    error level, and split + FP64 CholQR2 at FP64 orthogonality (ragged m and n included)."""
     from oracle import mixed
     a, z = dense_case(2, m, n, 1e4, 1e3, seed=8, kind="butterfly")
-    banner(f"mixed wide n m={m} n={n}")
-    qe, re, info, s = mixed.cholqr_pass(a, z, "bf16x3", shift_c=1.0)
+    banner(f"mixed wide n m={m} n={n} {prec}")
+    qe, re, info, s = mixed.cholqr_pass(a, z, prec, shift_c=1.0)
     assert info == 0
-    q, r = run_dense("cholqr", a, z, prec="bf16x3", shift_c=1.0)
+    q, r = run_dense("cholqr", a, z, prec=prec, shift_c=1.0)
     le, lg = metrics.orth_loss(a, qe), metrics.orth_loss(a, q)
     assert le / 10 <= lg <= 10 * le, (le, lg)
     assert metrics.residual_f(z, q, r) <= 1e-12
-    q2, r2 = run_dense("cholqr2", a, z, pass1="bf16x3", pass2="fp64")
+    q2, r2 = run_dense("cholqr2", a, z, pass1=prec, pass2="fp64")
     q0, r0 = reference.chol_eqr(a, z)
     assert metrics.residual_f(z, q2, r2) <= 1e-12
     assert metrics.orth_loss(a, q2) <= 1e-12
