@@ -152,13 +152,14 @@ __global__ __launch_bounds__(NT, 2) void trsm_kernel(const double* Z, int64_t ld
       #pragma unroll
         for (int e = 0; e < 8; ++e)
           if (4 * e + 3 > c) x[e] = __builtin_fma(-q, rzc[e], x[e]);
-        x[ec] = (sub == owner) ? q : x[ec];
       #pragma unroll
         for (int e = 0; e < 8; ++e) rzc[e] = rzn[e];
         ric = rin;
       }
+      // a settled column meets only zeros of RZ, so each x[e] still holds its pivot's numerator: the
+      // scale by 1 / r_kk, made where the pivot was broadcast, is made here once more (same product)
 #pragma unroll
-      for (int e = 0; e < 8; ++e) Qs[(j0 + sub + 4 * e) * LDQ + row] = x[e];
+      for (int e = 0; e < 8; ++e) Qs[(j0 + sub + 4 * e) * LDQ + row] = x[e] * rinv[sub + 4 * e];
     }
     __syncthreads();
   }
@@ -275,13 +276,14 @@ __global__ __launch_bounds__(NT, 2) void trsm_wide_kernel(const double* Z, int64
 #pragma unroll
         for (int e = 0; e < 8; ++e)
           if (4 * e + 3 > c) x[e] = __builtin_fma(-q, rzc[e], x[e]);
-        x[ec] = (sub == owner) ? q : x[ec];
 #pragma unroll
         for (int e = 0; e < 8; ++e) rzc[e] = rzn[e];
         ric = rin;
       }
+      // pivots scaled once more here (settled columns met only zeros of RZ): same products as at the
+      // broadcast
 #pragma unroll
-      for (int e = 0; e < 8; ++e) Qs[(j0 + sub + 4 * e) * WLDQ + row] = x[e];
+      for (int e = 0; e < 8; ++e) Qs[(j0 + sub + 4 * e) * WLDQ + row] = x[e] * rinv[sub + 4 * e];
     }
     __syncthreads();
     // right-looking update of the columns right of block J: independent 16 x 16 tiles, K = 32
@@ -429,13 +431,14 @@ __global__ __launch_bounds__(NT, 1) void trsm_persist_kernel(const double* Z, in
         #pragma unroll
           for (int e = 0; e < 8; ++e)
             if (4 * e + 3 > c) x[e] = __builtin_fma(-q, rzc[e], x[e]);
-          x[ec] = (sub == owner) ? q : x[ec];
         #pragma unroll
           for (int e = 0; e < 8; ++e) rzc[e] = rzn[e];
           ric = rin;
         }
+        // pivots scaled once more here (settled columns met only zeros of RZ): same products as at the
+        // broadcast
 #pragma unroll
-        for (int e = 0; e < 8; ++e) Qs[(j0 + sub + 4 * e) * LDQ + row] = x[e];
+        for (int e = 0; e < 8; ++e) Qs[(j0 + sub + 4 * e) * LDQ + row] = x[e] * rinv[J][sub + 4 * e];
       }
       __syncthreads();
     }
