@@ -332,12 +332,19 @@ __global__ __launch_bounds__(NT, 2) void gram_full_f64_kernel(const double* __re
         }
       }
   };
-  constexpr int NTILE = NBT * (NBT + 1) / 2;
-  f64x4 acc[NTILE][4];
+  // Of the diagonal tiles only the 16 x 16 blocks on or above the diagonal are formed (the reduction
+  // reads the upper triangle): with two column blocks, wave w takes row band w of tile (0,0) and band
+  // 3 - w of tile (1,1), blocks q >= band (five per wave); with one, the ten blocks are dealt to the
+  // waves in turn (block w + 4 v).  The off-diagonal tile (0,1): band w, all four column blocks.
+  // Every entry sums the same products in the same order as when whole tiles were formed.
+  const int wb = __builtin_amdgcn_readfirstlane(wave);
+  f64x4 acc[NBT == 2 ? 1 : 1][4], accd[2][4];
 #pragma unroll
-  for (int u = 0; u < NTILE; ++u)
-#pragma unroll
-    for (int q = 0; q < 4; ++q) acc[u][q] = f64x4{0, 0, 0, 0};
+  for (int q = 0; q < 4; ++q) acc[0][q] = accd[0][q] = accd[1][q] = f64x4{0, 0, 0, 0};
+  auto d1 = [](int d, int& rb, int& qb) {       // block d of a lone diagonal tile, row order
+    rb = d < 4 ? 0 : (d < 7 ? 1 : (d < 9 ? 2 : 3));
+    qb = d < 4 ? d : (d < 7 ? d - 3 : (d < 9 ? d - 5 : 3));
+  };
   load(r0);
   for (int k0 = r0; k0 < r1; k0 += BK) {
 #pragma unroll
@@ -353,36 +360,74 @@ __global__ __launch_bounds__(NT, 2) void gram_full_f64_kernel(const double* __re
 #pragma unroll
     for (int kk = 0; kk < BK; kk += 4) {
       const int kr = kk + li;
-      int u = 0;
-#pragma unroll
-      for (int I = 0; I < NBT; ++I) {
-        const double a = Xs[I][kr][wave * 16 + lj];
-        const double a2 = SYM ? X2s[I][kr][wave * 16 + lj] : 0.0;
-#pragma unroll
-        for (int J = I; J < NBT; ++J, ++u)
+      if constexpr (NBT == 2) {
+        {
+          const double a = Xs[0][kr][wb * 16 + lj];
+          const double a2 = SYM ? X2s[0][kr][wb * 16 + lj] : 0.0;
 #pragma unroll
           for (int q = 0; q < 4; ++q) {
-            acc[u][q] = mfma_f64(a, Ys[J][kr][q * 16 + lj], acc[u][q]);
-            if (SYM) acc[u][q] = mfma_f64(a2, Xs[J][kr][q * 16 + lj], acc[u][q]);
+            acc[0][q] = mfma_f64(a, Ys[1][kr][q * 16 + lj], acc[0][q]);
+            if (SYM) acc[0][q] = mfma_f64(a2, Xs[1][kr][q * 16 + lj], acc[0][q]);
           }
+        }
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+          const int b = h ? 3 - wb : wb;       // wave-uniform: the tests below branch
+          const double a = Xs[h][kr][b * 16 + lj];
+          const double a2 = SYM ? X2s[h][kr][b * 16 + lj] : 0.0;
+#pragma unroll
+          for (int q = 0; q < 4; ++q)
+            if (q >= b) {
+              accd[h][q] = mfma_f64(a, Ys[h][kr][q * 16 + lj], accd[h][q]);
+              if (SYM) accd[h][q] = mfma_f64(a2, Xs[h][kr][q * 16 + lj], accd[h][q]);
+            }
+        }
+      } else {
+#pragma unroll
+        for (int v = 0; v < 3; ++v) {
+          const int d = wb + 4 * v;
+          if (d < 10) {
+            int rb, qb;
+            d1(d, rb, qb);
+            const double a = Xs[0][kr][rb * 16 + lj];
+            const double a2 = SYM ? X2s[0][kr][rb * 16 + lj] : 0.0;
+            accd[0][v] = mfma_f64(a, Ys[0][kr][qb * 16 + lj], accd[0][v]);
+            if (SYM) accd[0][v] = mfma_f64(a2, Xs[0][kr][qb * 16 + lj], accd[0][v]);
+          }
+        }
       }
     }
     __syncthreads();
   }
   double* P = partial + (int64_t)c * n * n;
-  int u = 0;
+  auto put = [&](int i0, int j0, const f64x4& v) {
 #pragma unroll
-  for (int I = 0; I < NBT; ++I)
+    for (int r = 0; r < 4; ++r) {
+      const int i = i0 + 4 * r + li, j = j0 + lj;
+      if (i < n && j < n) P[(int64_t)j * n + i] = v[r];
+    }
+  };
+  if constexpr (NBT == 2) {
 #pragma unroll
-    for (int J = I; J < NBT; ++J, ++u)
+    for (int q = 0; q < 4; ++q) put(wb * 16, TB + q * 16, acc[0][q]);
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int b = h ? 3 - wb : wb;
 #pragma unroll
       for (int q = 0; q < 4; ++q)
+        if (q >= b) put(h * TB + b * 16, h * TB + q * 16, accd[h][q]);
+    }
+  } else {
 #pragma unroll
-        for (int r = 0; r < 4; ++r) {
-          const int i = I * TB + wave * 16 + 4 * r + li;
-          const int j = J * TB + q * 16 + lj;
-          if (i < n && j < n) P[(int64_t)j * n + i] = acc[u][q][r];
-        }
+    for (int v = 0; v < 3; ++v) {
+      const int d = wb + 4 * v;
+      if (d < 10) {
+        int rb, qb;
+        d1(d, rb, qb);
+        put(rb * 16, qb * 16, accd[0][v]);
+      }
+    }
+  }
 }
 
 // ---- all upper tiles per workgroup, 128 < n <= 256, symmetric assembly from layers --------------
