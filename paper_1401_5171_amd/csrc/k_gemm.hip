@@ -192,8 +192,12 @@ __global__ __launch_bounds__(NT, 2) void gemm_f64_kernel(const double* __restric
         } else {
 #pragma unroll
           for (int a = 0; a < 4; ++a)
+            // GEMM_DIAGH: rows 16 a .. of D' are zero left of column 16 a, so a K step wholly left of
+            // them adds nothing (uniform test)
+            if (MODE != GEMM_DIAGH || k0 - i0 >= 16 * a) {
 #pragma unroll
-            for (int b = 0; b < CB; ++b) acc[a][b] = mfma_f64(af[a], bf[b], acc[a][b]);
+              for (int b = 0; b < CB; ++b) acc[a][b] = mfma_f64(af[a], bf[b], acc[a][b]);
+            }
         }
       }
       if (F32 && ++step == F32_FOLD / BK64) {
