@@ -310,18 +310,43 @@ __global__ __launch_bounds__(NTC) void chol_kernel(const double* __restrict__ G,
   }
 }
 
-// R = R2 * R1 for upper triangular n x n factors.
-__global__ void trmm_upper_kernel(const double* __restrict__ R2, int64_t ld2, const double* __restrict__ R1,
-                                  int64_t ld1, double* __restrict__ R, int64_t ldr, int n,
-                                  const int32_t* __restrict__ info) {
-  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (idx >= (int64_t)n * n) return;
-  const int j = (int)(idx / n), i = (int)(idx % n);
+// R = R2 * R1 for upper triangular n x n factors, one workgroup per 16 x 16 tile of R.  Entry (i, j)
+// sums R2(i, k) R1(k, j) over the K blocks of the tile row to the tile column in increasing k; the
+// factors' entries with k < i or k > j are read as zero (whatever the lower parts hold), so those terms
+// add exact zeros and each entry is the plain sum over k = i .. j.  The next K block is loaded into
+// registers while the current one is multiplied from LDS.
+__global__ __launch_bounds__(256) void trmm_upper_kernel(const double* __restrict__ R2, int64_t ld2,
+                                                         const double* __restrict__ R1, int64_t ld1,
+                                                         double* __restrict__ R, int64_t ldr, int n,
+                                                         const int32_t* __restrict__ info) {
+  __shared__ double As[16][17];               // R2(16 I + ti, 16 K + kk)
+  __shared__ double Bs[16][17];               // R1(16 K + kk, 16 J + tj)
+  const int I = blockIdx.y, J = blockIdx.x;
+  const int ti = threadIdx.x & 15, tj = threadIdx.x >> 4;
+  const int i = 16 * I + ti, j = 16 * J + tj;
   if (info && info[0] != 0) return;
+  if (I > J) {                                // below the diagonal: zero
+    if (i < n && j < n) R[(int64_t)j * ldr + i] = 0.0;
+    return;
+  }
+  auto fetch = [&](int K, double& a, double& b) {
+    const int ka = 16 * K + tj, kb = 16 * K + ti;
+    a = (i < n && ka < n && ka >= i) ? R2[(int64_t)ka * ld2 + i] : 0.0;
+    b = (kb < n && j < n && kb <= j) ? R1[(int64_t)j * ld1 + kb] : 0.0;
+  };
+  double a, b;
+  fetch(I, a, b);
   double s = 0.0;
-  if (i <= j)
-    for (int k = i; k <= j; ++k) s += R2[(int64_t)k * ld2 + i] * R1[(int64_t)j * ld1 + k];
-  R[(int64_t)j * ldr + i] = s;
+  for (int K = I; K <= J; ++K) {
+    As[ti][tj] = a;
+    Bs[ti][tj] = b;
+    __syncthreads();
+    if (K < J) fetch(K + 1, a, b);
+#pragma unroll
+    for (int kk = 0; kk < 16; ++kk) s += As[ti][kk] * Bs[kk][tj];
+    __syncthreads();
+  }
+  if (i < n && j < n) R[(int64_t)j * ldr + i] = s;
 }
 
 __global__ void copy_matrix_kernel(const double* __restrict__ X, int64_t ldx, double* __restrict__ Y, int64_t ldy,
@@ -358,8 +383,8 @@ hipError_t launch_chol_small(const double* G, int64_t n, double* R, int64_t ldr,
 
 hipError_t launch_trmm_upper(const double* R2, int64_t ld2, const double* R1, int64_t ld1, double* R, int64_t ldr,
                              int64_t n, const int32_t* info, hipStream_t s) {
-  const int64_t total = n * n;
-  trmm_upper_kernel<<<(unsigned)((total + 255) / 256), 256, 0, s>>>(R2, ld2, R1, ld1, R, ldr, (int)n, info);
+  const unsigned tiles = (unsigned)((n + 15) / 16);
+  trmm_upper_kernel<<<dim3(tiles, tiles), 256, 0, s>>>(R2, ld2, R1, ld1, R, ldr, (int)n, info);
   return hipGetLastError();
 }
 
