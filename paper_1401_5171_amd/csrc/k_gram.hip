@@ -683,22 +683,36 @@ __global__ __launch_bounds__(NT, 2) void gram_full_split_kernel(const double* __
 // G(i, j) = G(j, i) = sum_c partial[c](i, j) for i <= j.  Eight interleaved partial sums (chunk c goes
 // to sum c mod 8) keep eight loads in flight; they are combined in a fixed order, so the result does
 // not depend on timing.
-__global__ void gram_reduce_kernel(const double* __restrict__ partial, int n, int chunks, double* __restrict__ G) {
-  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (idx >= (int64_t)n * n) return;
+// A workgroup reduces 64 consecutive entries with eight waves: wave u sums the partials of chunks u,
+// u + 8, u + 16, ... in that order (64 consecutive entries per load: coalesced), and the eight sums of
+// an entry (i <= j) are combined as ((s0 + s1) + (s2 + s3)) + ((s4 + s5) + (s6 + s7)) through LDS; both
+// triangles of G are written.
+__global__ __launch_bounds__(512) void gram_reduce_kernel(const double* __restrict__ partial, int n, int chunks,
+                                                          double* __restrict__ G) {
+  __shared__ double sh[8][64];
+  const int u = threadIdx.x >> 6, l = threadIdx.x & 63;
+  const int64_t idx = (int64_t)blockIdx.x * 64 + l, nn = (int64_t)n * n;
   const int j = (int)(idx / n), i = (int)(idx % n);
-  if (i > j) return;
-  const int64_t nn = (int64_t)n * n;
-  double s[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-  int c = 0;
-  for (; c + 8 <= chunks; c += 8) {
+  const bool active = idx < nn && i <= j;
+  double s = 0.0;
+  if (active) {
+    int c = u;
+    for (; c + 56 < chunks; c += 64) {        // eight loads in flight, added in chunk order
+      double v[8];
 #pragma unroll
-    for (int u = 0; u < 8; ++u) s[u] += partial[(int64_t)(c + u) * nn + idx];
+      for (int q = 0; q < 8; ++q) v[q] = partial[(int64_t)(c + 8 * q) * nn + idx];
+#pragma unroll
+      for (int q = 0; q < 8; ++q) s += v[q];
+    }
+    for (; c < chunks; c += 8) s += partial[(int64_t)c * nn + idx];
   }
-  for (int u = 0; c < chunks; ++c, ++u) s[u] += partial[(int64_t)c * nn + idx];
-  double t = ((s[0] + s[1]) + (s[2] + s[3])) + ((s[4] + s[5]) + (s[6] + s[7]));
-  G[(int64_t)j * n + i] = t;
-  G[(int64_t)i * n + j] = t;
+  sh[u][l] = s;
+  __syncthreads();
+  if (u == 0 && active) {
+    const double t = ((sh[0][l] + sh[1][l]) + (sh[2][l] + sh[3][l])) + ((sh[4][l] + sh[5][l]) + (sh[6][l] + sh[7][l]));
+    G[(int64_t)j * n + i] = t;
+    G[(int64_t)i * n + j] = t;
+  }
 }
 
 
@@ -1127,8 +1141,7 @@ size_t gram_partial_bytes(int64_t m, int64_t n) {
 }
 
 static hipError_t reduce(const double* partial, int64_t n, int chunks, double* G, hipStream_t s) {
-  const int64_t total = n * n;
-  gram_reduce_kernel<<<(unsigned)((total + 255) / 256), 256, 0, s>>>(partial, (int)n, chunks, G);
+  gram_reduce_kernel<<<(unsigned)((n * n + 63) / 64), 512, 0, s>>>(partial, (int)n, chunks, G);
   return hipGetLastError();
 }
 
