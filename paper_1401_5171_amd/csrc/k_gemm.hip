@@ -47,9 +47,9 @@ struct Seg {
 // [T h / H, T (h + 1) / H)): tile p's steps, then tile R - 1 - p's, each from its start up; or, with
 // sync, tile p's from the top of K down and then tile R - 1 - p's from its start up.  With sync the
 // list has the same length for every pair (for m a multiple of BM) and its s-th entry lies at the same
-// K for every pair (the top step less ks s while in tile p, then BM + ks (s - na)), so the workgroups
-// of one part walk K together and each K tile of Z is fetched into L2 once rather than once per
-// workgroup.
+// K for every pair (the top step less ks s while in tile p, then ks s plus a fixed offset, BM or -BM
+// with diag), so the workgroups of one part walk K together and each K tile of Z is fetched into L2
+// once rather than once per workgroup.
 __device__ __forceinline__ bool upper_segments(int m, int p, int h, int H, int ks, Seg& a, Seg& b,
                                                bool diag = false, bool sync = false) {
   const int R = (m + BM - 1) / BM;
