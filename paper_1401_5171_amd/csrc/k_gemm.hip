@@ -627,16 +627,24 @@ __global__ __launch_bounds__(NT2, 1) void gemm_split2_kernel(const double* __res
 // tile, so that the slices of one 32-row K step form one contiguous block.
 __global__ void split_z_kernel(const double* __restrict__ Z, int64_t ldz, unsigned short* __restrict__ zs,
                                int64_t m, int64_t n, int slices, int tiled) {
+  // four consecutive rows per thread (one 32-row segment in either layout): one 8-byte store per slice
   const int64_t mp = split_ld(m);
-  int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t idx = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) * 4;
   if (idx >= mp * n) return;
-  int64_t j = idx / mp, i = idx % mp;
-  double r = (i < m) ? Z[j * ldz + i] : 0.0;
+  const int64_t j = idx / mp, i = idx % mp;
+  double r[4];
+#pragma unroll
+  for (int e = 0; e < 4; ++e) r[e] = (i + e < m) ? Z[j * ldz + i + e] : 0.0;
   for (int s = 0; s < slices; ++s) {
-    unsigned short b = bf16_bits((float)r);
+    unsigned short b[4];
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      b[e] = bf16_bits((float)r[e]);
+      r[e] -= (double)bf16_to_f32(b[e]);
+    }
     const int64_t o = tiled ? (((i / BKS) * slices + s) * BN2 + j) * BKS + i % BKS : (int64_t)s * mp * n + idx;
-    zs[o] = b;
-    r -= (double)bf16_to_f32(b);
+    *reinterpret_cast<uint2*>(zs + o) = make_uint2((unsigned)b[0] | ((unsigned)b[1] << 16),
+                                                   (unsigned)b[2] | ((unsigned)b[3] << 16));
   }
 }
 
@@ -826,7 +834,7 @@ size_t split_z_elems(int64_t m, int64_t n, int slices) {
 
 hipError_t launch_split_z(const double* Z, int64_t ldz, unsigned short* zs, int64_t m, int64_t n, int slices,
                           hipStream_t s) {
-  int64_t total = split_ld(m) * n;
+  const int64_t total = split_ld(m) * n / 4;     // threads: four rows each (split_ld is a multiple of 32)
   split_z_kernel<<<(unsigned)((total + 255) / 256), 256, 0, s>>>(Z, ldz, zs, m, n, slices, col_blocks(n) == 4);
   return hipGetLastError();
 }
